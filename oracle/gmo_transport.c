@@ -1,0 +1,884 @@
+/*
+ * gmo_transport.c -- oracle: the superphoton Monte Carlo method itself,
+ * one photon at a time.  TEST INFRASTRUCTURE (see gmo.h).
+ *
+ *  make:  weight table (eq:weight_calc), per-zone expected counts and
+ *         stochastic rounding (Sampling procedure section);
+ *  birth: position, frequency and direction by rejection (Sampling
+ *         procedure section), fluid-frame tetrad, wavevector;
+ *  step:  velocity Verlet with iterated corrector (geodesic section,
+ *         eq:predicted_wavevector, eq:calculated_wavevector), absorption
+ *         weighting with the trapezoid optical depth (eq:weight_absorption,
+ *         eq:abs_optdepth), biased scattering with weight split and a
+ *         child superphoton (Scattering section);
+ *  tally: (frequency, inclination) bins at escape.
+ *
+ * Descendants of each root are processed depth-first from an explicit
+ * stack.  Random streams are keyed by photon identity, so the processing
+ * order does not change any photon's history.
+ */
+#include "gmo_internal.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MEC2 (GMO_ME * GMO_CL * GMO_CL)
+
+static __thread char g_err[256];
+void gmo_set_error(const char *msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
+const char *gmo_last_error(void) { return g_err; }
+
+struct gmo_ctx {
+    gmo_grid grid;
+    int nz;
+    double *n_e, *theta, *B, *ucon, *bcon;   /* copies of the inputs          */
+    double *A, *nu_c, *vol;                   /* per-zone emission constants   */
+    int *emits;                               /* zone takes part in emission   */
+    /* last make */
+    int made;
+    gmo_emit_params ep;
+    double lnnu_min, lnnu_span;               /* ln nu_min, ln(nu_max/nu_min)  */
+    double *w_node, *ln_w;                    /* [n_wnodes]                    */
+    uint32_t *count;
+    double *nbar, *fmax;
+    uint64_t *offset;                         /* [nz+1] exclusive prefix       */
+    /* hot cross-section table, built on first use */
+    double *sh;
+    /* accumulators */
+    int n_nu, n_theta;
+    double *spec;
+    double ledger[GMO_L_N];
+    int64_t stats[GMO_S_N];
+};
+
+gmo_ctx *gmo_create(void)
+{
+    gmo_ctx *c = (gmo_ctx *)calloc(1, sizeof(gmo_ctx));
+    return c;
+}
+
+static void free_zones(gmo_ctx *c)
+{
+    free(c->n_e); free(c->theta); free(c->B); free(c->ucon); free(c->bcon);
+    free(c->A); free(c->nu_c); free(c->vol); free(c->emits);
+    free(c->w_node); free(c->ln_w); free(c->count); free(c->nbar); free(c->fmax); free(c->offset);
+    c->n_e = c->theta = c->B = c->ucon = c->bcon = c->A = c->nu_c = c->vol = NULL;
+    c->emits = NULL; c->w_node = c->ln_w = c->nbar = c->fmax = NULL; c->count = NULL; c->offset = NULL;
+    c->made = 0;
+}
+
+void gmo_destroy(gmo_ctx *c)
+{
+    if (!c) return;
+    free_zones(c);
+    free(c->sh); free(c->spec);
+    free(c);
+}
+
+/* ---------------------------------------------------------------------
+ * Geometry helpers
+ * ------------------------------------------------------------------- */
+static double horizon_r(const gmo_grid *g) { return 1.0 + sqrt(1.0 - g->a_spin * g->a_spin); }
+
+static double dot4(const double g[4][4], const double a[4], const double b[4])
+{
+    double s = 0.0;
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) s += g[m][n] * a[m] * b[n];
+    return s;
+}
+
+/* Zone containing code point x, or -1 outside the grid (vacuum).
+ * Cartesian: half-open boxes.  KS: x1 outside the grid is vacuum, x2 is
+ * clamped into [0, n2-1], x3 is periodic. */
+static int zone_of(const gmo_grid *g, const double x[4])
+{
+    int idx[3];
+    for (int j = 0; j < 3; ++j) {
+        double f = floor((x[j + 1] - g->x_start[j]) / g->dx[j]);
+        if (g->metric == GMO_METRIC_MINKOWSKI_CART || j == 0) {
+            if (f < 0.0 || f >= g->n[j]) return -1;
+            idx[j] = (int)f;
+        } else if (j == 1) {
+            if (f < 0.0) f = 0.0;
+            if (f > g->n[j] - 1) f = g->n[j] - 1;
+            idx[j] = (int)f;
+        } else {
+            double m = fmod(f, (double)g->n[j]);
+            if (m < 0.0) m += g->n[j];
+            idx[j] = (int)m;
+        }
+    }
+    return (idx[0] * g->n[1] + idx[1]) * g->n[2] + idx[2];
+}
+
+/* Normalised fluid velocity and unit field direction at a point (the zone
+ * values are renormalised with the local metric, reading). */
+static void fluid_frame(const gmo_ctx *c, int z, const double g[4][4], double u[4], double bh[4],
+                        int *has_b)
+{
+    for (int m = 0; m < 4; ++m) { u[m] = c->ucon[m * c->nz + z]; bh[m] = c->bcon[m * c->nz + z]; }
+    double uu = -dot4(g, u, u);
+    double nu_ = sqrt(uu);
+    for (int m = 0; m < 4; ++m) u[m] /= nu_;
+    double bu = dot4(g, bh, u);
+    for (int m = 0; m < 4; ++m) bh[m] += bu * u[m];
+    double bb = dot4(g, bh, bh);
+    *has_b = (bb > 0.0 && c->B[z] > 0.0);
+    if (*has_b) {
+        double nb = sqrt(bb);
+        for (int m = 0; m < 4; ++m) bh[m] /= nb;
+    } else {
+        for (int m = 0; m < 4; ++m) bh[m] = 0.0;
+    }
+}
+
+/* Gram-Schmidt of v against the orthonormal vectors e[0..ne-1] (e[0]
+ * timelike).  Returns 0 when the residual norm^2 is below 1e-10 of the
+ * original norm^2 (degenerate). */
+static int gs_add(const double g[4][4], double e[4][4], int ne, const double vin[4])
+{
+    double v[4] = {vin[0], vin[1], vin[2], vin[3]};
+    double n0 = fabs(dot4(g, v, v));
+    for (int i = 0; i < ne; ++i) {
+        double p = dot4(g, v, e[i]);
+        double s = (i == 0) ? p : -p;      /* e0.e0 = -1, ei.ei = +1 */
+        for (int m = 0; m < 4; ++m) v[m] += s * e[i][m];
+    }
+    double nn = dot4(g, v, v);
+    if (!(nn > 1e-10 * n0) || !(nn > 0.0)) return 0;
+    nn = sqrt(nn);
+    for (int m = 0; m < 4; ++m) e[ne][m] = v[m] / nn;
+    return 1;
+}
+
+static void basis_vec(int j, double v[4]) { v[0] = v[1] = v[2] = v[3] = 0.0; v[j] = 1.0; }
+
+/* Emission tetrad: e0 = u, e3 = field direction, e1 and e2 from the
+ * coordinate directions 1, 2, 3 in that order (reading). */
+static void emission_tetrad(const double g[4][4], const double u[4], const double bh[4],
+                            double e[4][4])
+{
+    double t[4][4];
+    memcpy(t[0], u, sizeof(double) * 4);
+    memcpy(t[1], bh, sizeof(double) * 4);
+    int n = 2;
+    for (int j = 1; j <= 3 && n < 4; ++j) {
+        double v[4];
+        basis_vec(j, v);
+        n += gs_add(g, t, n, v);
+    }
+    /* order the frame as (u, e1, e2, b) */
+    memcpy(e[0], t[0], sizeof(double) * 4);
+    memcpy(e[1], t[2], sizeof(double) * 4);
+    memcpy(e[2], t[3], sizeof(double) * 4);
+    memcpy(e[3], t[1], sizeof(double) * 4);
+}
+
+/* Scattering tetrad: e0 = u, e1 along the photon's fluid-frame direction,
+ * e2 from the field direction (else coordinate 1, 2, 3), e3 from the first
+ * coordinate direction that is not degenerate (reading). */
+static void scatter_tetrad(const double g[4][4], const double u[4], const double bh[4], int has_b,
+                           const double k[4], double e[4][4], double *eps)
+{
+    memcpy(e[0], u, sizeof(double) * 4);
+    double ep = -dot4(g, k, u);
+    for (int m = 0; m < 4; ++m) e[1][m] = (k[m] - ep * u[m]) / ep;
+    int n = 2;
+    if (has_b) n += gs_add(g, e, n, bh);
+    for (int j = 1; j <= 3 && n < 4; ++j) {
+        double v[4];
+        basis_vec(j, v);
+        n += gs_add(g, e, n, v);
+    }
+    *eps = ep;
+}
+
+static double e_inf(const double g[4][4], const double k[4])
+{
+    double kt = 0.0;
+    for (int n = 0; n < 4; ++n) kt += g[0][n] * k[n];
+    return -kt;
+}
+
+/* ---------------------------------------------------------------------
+ * Zone preparation and weight table (Creation of superphotons section,
+ * eq:weight_calc; Sampling procedure section).
+ * ------------------------------------------------------------------- */
+int gmo_load_zones(gmo_ctx *c, const gmo_grid *grid, const gmo_zones *z)
+{
+    if (!c || !grid || !z) { gmo_set_error("null argument"); return GMO_EINVAL; }
+    for (int j = 0; j < 3; ++j)
+        if (grid->n[j] < 1 || !(grid->dx[j] > 0.0)) { gmo_set_error("bad grid"); return GMO_EINVAL; }
+    if (grid->metric != GMO_METRIC_MINKOWSKI_CART && grid->metric != GMO_METRIC_KS_MKS) {
+        gmo_set_error("unknown metric"); return GMO_EINVAL;
+    }
+    free_zones(c);
+    c->grid = *grid;
+    int nz = grid->n[0] * grid->n[1] * grid->n[2];
+    c->nz = nz;
+    c->n_e = malloc(sizeof(double) * nz); c->theta = malloc(sizeof(double) * nz);
+    c->B = malloc(sizeof(double) * nz);
+    c->ucon = malloc(sizeof(double) * 4 * nz); c->bcon = malloc(sizeof(double) * 4 * nz);
+    c->A = malloc(sizeof(double) * nz); c->nu_c = malloc(sizeof(double) * nz);
+    c->vol = malloc(sizeof(double) * nz); c->emits = malloc(sizeof(int) * nz);
+    memcpy(c->n_e, z->n_e, sizeof(double) * nz);
+    memcpy(c->theta, z->theta_e, sizeof(double) * nz);
+    memcpy(c->B, z->B, sizeof(double) * nz);
+    memcpy(c->ucon, z->ucon, sizeof(double) * 4 * nz);
+    memcpy(c->bcon, z->bcon, sizeof(double) * 4 * nz);
+    const double L3 = grid->L_unit_cm * grid->L_unit_cm * grid->L_unit_cm;
+    const double rh = horizon_r(grid);
+    for (int i = 0; i < nz; ++i) {
+        if (c->n_e[i] > 0.0 && !(c->theta[i] > 0.0)) { gmo_set_error("n_e > 0 needs Theta_e > 0"); return GMO_EINVAL; }
+        c->A[i] = gmo_A_coef(c->n_e[i], c->theta[i], c->B[i]);
+        c->nu_c[i] = gmo_nu_c(c->theta[i], c->B[i]);
+        int i3 = i % grid->n[2], i2 = (i / grid->n[2]) % grid->n[1], i1 = i / (grid->n[2] * grid->n[1]);
+        double xc[4] = {0.0, grid->x_start[0] + (i1 + 0.5) * grid->dx[0],
+                        grid->x_start[1] + (i2 + 0.5) * grid->dx[1],
+                        grid->x_start[2] + (i3 + 0.5) * grid->dx[2]};
+        c->vol[i] = gmo_sqrt_neg_g(grid, xc) * grid->dx[0] * grid->dx[1] * grid->dx[2] * L3;
+        c->emits[i] = (c->A[i] > 0.0);
+        /* Kerr: no emission from zones centred inside the horizon (reading) */
+        if (grid->metric == GMO_METRIC_KS_MKS && exp(xc[1]) < rh) c->emits[i] = 0;
+    }
+    return GMO_OK;
+}
+
+/* j at (nu, angle) in zone z; cos_th = cosine to the field. */
+static double zone_j(const gmo_ctx *c, int z, double nu, double cos_th)
+{
+    if (c->A[z] == 0.0) return 0.0;
+    double s2 = 1.0 - cos_th * cos_th;
+    if (!(s2 > 0.0)) return 0.0;
+    double s = sqrt(s2);
+    return c->A[z] * s * gmo_g_of_X(nu / (c->nu_c[z] * s));
+}
+
+static double zone_J(const gmo_ctx *c, int z, double nu)
+{
+    if (c->A[z] == 0.0) return 0.0;
+    return 4.0 * M_PI * c->A[z] * gmo_G_of_Xc(nu / c->nu_c[z]);
+}
+
+/* ln w at ln nu: linear between nodes (reading), clamped at the ends. */
+static double ln_weight(const gmo_ctx *c, double lnnu)
+{
+    int n = c->ep.n_wnodes;
+    double d = c->lnnu_span / (n - 1);
+    double a = (lnnu - c->lnnu_min) / d;
+    int i = (int)floor(a);
+    if (i < 0) i = 0;
+    if (i > n - 2) i = n - 2;
+    double f = a - i;
+    return (1.0 - f) * c->ln_w[i] + f * c->ln_w[i + 1];
+}
+
+int gmo_make_superphotons(gmo_ctx *c, const gmo_emit_params *p, uint64_t *n_made)
+{
+    if (!c || !c->n_e) { gmo_set_error("load zones first"); return GMO_ESTATE; }
+    if (!(p->nu_max > p->nu_min) || !(p->nu_min > 0.0) || p->n_wnodes < 3 || !(p->n_wnodes & 1) ||
+        !(p->n_target > 0.0) || p->w_floor_rel < 0.0) {
+        gmo_set_error("bad emission parameters"); return GMO_EINVAL;
+    }
+    int nz = c->nz, nw = p->n_wnodes;
+    c->ep = *p;
+    c->lnnu_min = log(p->nu_min);
+    c->lnnu_span = log(p->nu_max / p->nu_min);
+    free(c->w_node); free(c->ln_w); free(c->count); free(c->nbar); free(c->fmax); free(c->offset);
+    c->w_node = malloc(sizeof(double) * nw); c->ln_w = malloc(sizeof(double) * nw);
+    c->count = malloc(sizeof(uint32_t) * nz); c->nbar = malloc(sizeof(double) * nz);
+    c->fmax = malloc(sizeof(double) * nz); c->offset = malloc(sizeof(uint64_t) * (nz + 1));
+    double *nu = malloc(sizeof(double) * nw);
+    for (int k = 0; k < nw; ++k) nu[k] = exp(c->lnnu_min + c->lnnu_span * k / (nw - 1));
+
+    /* J_i(nu_k) for every zone; G depends on nu_c only, so consecutive zones
+     * with the same nu_c reuse it. */
+    double *Jz = malloc(sizeof(double) * (size_t)nz * nw);
+    #pragma omp parallel
+    {
+        double *Gk = malloc(sizeof(double) * nw);
+        double last_nuc = -1.0;
+        #pragma omp for schedule(static)
+        for (int i = 0; i < nz; ++i) {
+            if (!c->emits[i]) {
+                for (int k = 0; k < nw; ++k) Jz[(size_t)i * nw + k] = 0.0;
+                continue;
+            }
+            if (c->nu_c[i] != last_nuc) {
+                for (int k = 0; k < nw; ++k) Gk[k] = gmo_G_of_Xc(nu[k] / c->nu_c[i]);
+                last_nuc = c->nu_c[i];
+            }
+            for (int k = 0; k < nw; ++k) Jz[(size_t)i * nw + k] = 4.0 * M_PI * c->A[i] * Gk[k];
+        }
+        free(Gk);
+    }
+    /* weight table: w(nu) = Delta t Delta(ln nu) / (h N_s) sum_i V_i J_i(nu),
+     * Delta t = 1 s and Delta(ln nu) = ln(nu_max/nu_min) (reading), plus a
+     * floor relative to the maximum. */
+    double wmax = 0.0;
+    for (int k = 0; k < nw; ++k) {
+        double phi = 0.0;
+        for (int i = 0; i < nz; ++i) phi += c->vol[i] * Jz[(size_t)i * nw + k];
+        c->w_node[k] = phi * c->lnnu_span / (GMO_HPL * p->n_target);
+        if (c->w_node[k] > wmax) wmax = c->w_node[k];
+    }
+    if (!(wmax > 0.0)) {
+        free(Jz); free(nu);
+        gmo_set_error("no zone emits in the band"); return GMO_EINVAL;
+    }
+    for (int k = 0; k < nw; ++k) {
+        c->w_node[k] += p->w_floor_rel * wmax;
+        c->ln_w[k] = log(c->w_node[k]);
+    }
+    /* per zone: dN/dln nu = V J / (h w); Simpson over the nodes; bound F_max */
+    const double d = c->lnnu_span / (nw - 1);
+    uint64_t total = 0;
+    for (int i = 0; i < nz; ++i) {
+        double s = 0.0, fm = 0.0;
+        for (int k = 0; k < nw; ++k) {
+            double F = Jz[(size_t)i * nw + k] / c->w_node[k];
+            double wk = (k == 0 || k == nw - 1) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+            s += wk * F;
+            if (F > fm) fm = F;
+        }
+        c->nbar[i] = c->vol[i] / GMO_HPL * s * d / 3.0;
+        /* the bound is the node maximum with a 2% margin for the curvature
+         * of ln J between nodes (reading) */
+        c->fmax[i] = GMO_FMAX_MARGIN * fm;
+        double fl = floor(c->nbar[i]);
+        uint32_t zs[3] = {(uint32_t)i, 0u, ((uint32_t)p->instance << 8) | 2u};
+        double u = gmo_uniform_at(p->seed, zs, 0);
+        uint32_t n = (uint32_t)fl + ((u < c->nbar[i] - fl) ? 1u : 0u);
+        c->count[i] = n;
+        c->offset[i] = total;
+        total += n;
+    }
+    c->offset[nz] = total;
+    free(Jz); free(nu);
+    c->made = 1;
+    if (n_made) *n_made = total;
+    return GMO_OK;
+}
+
+int gmo_read_emission(const gmo_ctx *c, uint32_t *counts, double *nbar, double *fmax, double *ln_w)
+{
+    if (!c || !c->made) { gmo_set_error("nothing made"); return GMO_ESTATE; }
+    if (counts) memcpy(counts, c->count, sizeof(uint32_t) * c->nz);
+    if (nbar) memcpy(nbar, c->nbar, sizeof(double) * c->nz);
+    if (fmax) memcpy(fmax, c->fmax, sizeof(double) * c->nz);
+    if (ln_w) memcpy(ln_w, c->ln_w, sizeof(double) * c->ep.n_wnodes);
+    return GMO_OK;
+}
+
+/* ---------------------------------------------------------------------
+ * Transport
+ * ------------------------------------------------------------------- */
+typedef struct {
+    double x[4], k[4], a[4];
+    double w, w_birth, x1;         /* x1: remaining biased optical depth    */
+    double nua, nus, b;            /* at the current point                  */
+    int n_sc;
+    uint32_t steps;
+    gmo_rng rng;
+} photon;
+
+typedef struct {
+    double *spec;
+    double ledger[GMO_L_N];
+    int64_t stats[GMO_S_N];
+    gmo_trace_rec *trace;
+    uint64_t trace_n, trace_cap;
+    photon *stack;
+    size_t stack_n, stack_cap;
+} worker;
+
+typedef struct {
+    double nua, nus, b;
+    int vacuum;
+} coef;
+
+/* Invariant absorption and scattering coefficients (nu alpha) at a point,
+ * Absorption and Scattering sections: alpha = j/B_nu (Kirchhoff),
+ * alpha_sc = n_e sigma_h.  Also the bias at the point. */
+static void coefficients(const gmo_ctx *c, const gmo_track_params *tp, const double x[4],
+                         const double k[4], int n_sc, coef *out)
+{
+    out->nua = out->nus = 0.0; out->b = 1.0; out->vacuum = 1;
+    int z = zone_of(&c->grid, x);
+    if (z < 0 || !(c->n_e[z] > 0.0)) return;
+    out->vacuum = 0;
+    double g[4][4], u[4], bh[4];
+    int has_b;
+    gmo_gcov(&c->grid, x, g);
+    fluid_frame(c, z, g, u, bh, &has_b);
+    double ef = -dot4(g, k, u);
+    double nuf = ef * MEC2 / GMO_HPL;
+    if (has_b && c->A[z] > 0.0) {
+        double cth = dot4(g, k, bh) / ef;
+        if (cth > 1.0) cth = 1.0;
+        if (cth < -1.0) cth = -1.0;
+        double j = zone_j(c, z, nuf, cth);
+        if (j > 0.0) {
+            double x_ = ef / c->theta[z];
+            double alpha = j * expm1(x_) / (2.0 * GMO_HPL * nuf * nuf * nuf / (GMO_CL * GMO_CL));
+            out->nua = nuf * alpha;
+        }
+    }
+    if (tp->scattering)
+        out->nus = nuf * c->n_e[z] * GMO_SIGT * gmo_sigma_hot_lookup(c->sh, c->theta[z], ef);
+    double b = 1.0;
+    switch (tp->bias_mode) {
+    case GMO_BIAS_CONST: b = tp->bias_value; break;
+    case GMO_BIAS_THETA2: b = tp->bias_value * c->theta[z] * c->theta[z]; break;
+    case GMO_BIAS_GEN2:
+        b = (double)(n_sc + 1) * (n_sc + 1) / (c->n_e[z] * GMO_SIGT * tp->bias_value * c->grid.L_unit_cm);
+        break;
+    }
+    if (b < 1.0) b = 1.0;
+    if (b > tp->bias_max) b = tp->bias_max;
+    out->b = b;
+}
+
+static void accel(const gmo_ctx *c, const double x[4], const double k[4], double a[4])
+{
+    double G[4][4][4];
+    gmo_christoffel(&c->grid, x, G);
+    for (int m = 0; m < 4; ++m) {
+        double s = 0.0;
+        for (int p = 0; p < 4; ++p)
+            for (int q = 0; q < 4; ++q) s += G[m][p][q] * k[p] * k[q];
+        a[m] = -s;
+    }
+}
+
+static void record_end(const gmo_ctx *c, worker *wk, const photon *ph, int kind, int inu, int ith)
+{
+    (void)c;
+    if (wk->trace && wk->trace_n < wk->trace_cap) {
+        gmo_trace_rec *r = &wk->trace[wk->trace_n++];
+        r->s0 = ph->rng.s[0]; r->s1 = ph->rng.s[1]; r->s2 = ph->rng.s[2];
+        r->n_sc = ph->n_sc; r->kind = kind; r->i_nu = inu; r->i_theta = ith;
+        r->n_steps = ph->steps; r->w_birth = ph->w_birth; r->w_end = ph->w;
+        for (int m = 0; m < 4; ++m) { r->x[m] = ph->x[m]; r->k[m] = ph->k[m]; }
+    }
+}
+
+static void push_child(worker *wk, const photon *ch)
+{
+    if (wk->stack_n == wk->stack_cap) {
+        wk->stack_cap = wk->stack_cap ? 2 * wk->stack_cap : 64;
+        wk->stack = realloc(wk->stack, sizeof(photon) * wk->stack_cap);
+    }
+    wk->stack[wk->stack_n++] = *ch;
+}
+
+/* Frame components -> coordinate components. */
+static void from_frame(const double e[4][4], const double kf[4], double k[4])
+{
+    for (int m = 0; m < 4; ++m)
+        k[m] = kf[0] * e[0][m] + kf[1] * e[1][m] + kf[2] * e[2][m] + kf[3] * e[3][m];
+}
+
+/* Scattering event at (x*, k*): a child with weight w_child (Scattering
+ * section).  Draws from the parent's stream. */
+static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *wk, photon *par,
+                          const double xs[4], const double ks[4], double w_child,
+                          const double xa[4], const double xb[4])
+{
+    /* plasma of the zone holding the scatter point; when the interpolated
+     * point lies in vacuum, that of the step's start, else its end (reading) */
+    int z = zone_of(&c->grid, xs);
+    if (z < 0 || !(c->n_e[z] > 0.0)) z = zone_of(&c->grid, xa);
+    if (z < 0 || !(c->n_e[z] > 0.0)) z = zone_of(&c->grid, xb);
+    photon ch;
+    memset(&ch, 0, sizeof(ch));
+    uint32_t block_at_scatter = par->rng.block;
+    double g[4][4];
+    gmo_gcov(&c->grid, xs, g);
+    double kchild[4];
+    if (z >= 0 && c->n_e[z] > 0.0) {
+        double u[4], bh[4], e[4][4], eps;
+        int has_b;
+        fluid_frame(c, z, g, u, bh, &has_b);
+        scatter_tetrad(g, u, bh, has_b, ks, e, &eps);
+        double kf[4];
+        gmo_scatter_in_frame(&par->rng, c->theta[z], eps, NULL, NULL, kf,
+                             &wk->stats[GMO_S_E_TRIALS], &wk->stats[GMO_S_ANG_TRIALS]);
+        from_frame(e, kf, kchild);
+    } else {
+        for (int m = 0; m < 4; ++m) kchild[m] = ks[m];   /* unreachable: tau_s > 0 */
+    }
+    for (int m = 0; m < 4; ++m) { ch.x[m] = xs[m]; ch.k[m] = kchild[m]; }
+    ch.w = ch.w_birth = w_child;
+    ch.n_sc = par->n_sc + 1;
+    ch.rng.seed = par->rng.seed;
+    gmo_child_stream(par->rng.seed, par->rng.s, block_at_scatter, ch.rng.s);
+    ch.rng.block = 0;
+    wk->ledger[GMO_L_E_COMPTON] += w_child * (e_inf(g, kchild) - e_inf(g, ks)) * MEC2;
+    wk->stats[GMO_S_SCATTER] += 1;
+    (void)tp;
+    push_child(wk, &ch);
+}
+
+/* Run one photon (root already born or child) to termination. */
+static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk, photon *ph)
+{
+    const gmo_grid *G = &c->grid;
+    const int ks_metric = (G->metric == GMO_METRIC_KS_MKS);
+    const double rh = horizon_r(G);
+    const double Cc = GMO_HPL * G->L_unit_cm / MEC2;   /* C = h ell / m_e c^2 */
+    coef c0;
+    double g[4][4];
+    if (ph->n_sc > 0) {
+        /* child: its own stream starts with its optical-depth draw */
+        ph->x1 = -log(1.0 - gmo_rng_next(&ph->rng));
+    }
+    accel(c, ph->x, ph->k, ph->a);
+    coefficients(c, tp, ph->x, ph->k, ph->n_sc, &c0);
+    ph->nua = c0.nua; ph->nus = c0.nus; ph->b = c0.b;
+    int gen = ph->n_sc < GMO_MAX_GEN ? ph->n_sc : GMO_MAX_GEN - 1;
+    wk->stats[GMO_S_GEN0 + gen] += 1;
+
+    for (;;) {
+        if ((int64_t)ph->steps >= tp->max_steps) {
+            gmo_gcov(G, ph->x, g);
+            double e = e_inf(g, ph->k);
+            wk->ledger[GMO_L_W_STUCK] += ph->w; wk->ledger[GMO_L_E_STUCK] += ph->w * e * MEC2;
+            wk->stats[GMO_S_STUCK] += 1;
+            record_end(c, wk, ph, GMO_END_STUCK, -1, -1);
+            return;
+        }
+        /* ---- step size (reading) ---- */
+        double dl;
+        if (!ks_metric) {
+            dl = INFINITY;
+            for (int j = 1; j <= 3; ++j)
+                if (ph->k[j] != 0.0) {
+                    double t = G->dx[j - 1] / fabs(ph->k[j]);
+                    if (t < dl) dl = t;
+                }
+            dl *= tp->step_h;
+        } else {
+            double m = 0.0;
+            for (int j = 1; j <= 3; ++j) {
+                double t = fabs(ph->k[j]) / G->dx[j - 1];
+                if (t > m) m = t;
+            }
+            dl = tp->step_h / m;
+            if (ph->k[1] < 0.0) {
+                double r = exp(ph->x[1]);
+                double lim = 0.5 * (r - rh) / (r * fabs(ph->k[1]));
+                if (lim < dl) dl = lim;
+            }
+        }
+        /* ---- velocity Verlet with iterated corrector ---- */
+        double xn[4], kp[4], kn[4], an[4];
+        for (int m = 0; m < 4; ++m) {
+            xn[m] = ph->x[m] + ph->k[m] * dl + 0.5 * ph->a[m] * dl * dl;
+            kp[m] = ph->k[m] + ph->a[m] * dl;
+        }
+        double Gm[4][4][4];
+        gmo_christoffel(G, xn, Gm);
+        for (int it = 1;; ++it) {
+            for (int m = 0; m < 4; ++m) {
+                double s = 0.0;
+                for (int p = 0; p < 4; ++p)
+                    for (int q = 0; q < 4; ++q) s += Gm[m][p][q] * kp[p] * kp[q];
+                an[m] = -s;
+            }
+            double num = 0.0, den = 0.0;
+            for (int m = 0; m < 4; ++m) {
+                kn[m] = ph->k[m] + 0.5 * (ph->a[m] + an[m]) * dl;
+                num += fabs(kn[m] - kp[m]);
+                den += fabs(kn[m]);
+            }
+            for (int m = 0; m < 4; ++m) kp[m] = kn[m];
+            wk->stats[GMO_S_VERLET_IT] += 1;
+            if (num / (den + 1e-300) < tp->verlet_tol || it >= tp->verlet_max_it) break;
+        }
+        if (ks_metric) {   /* pole reflection (reading) */
+            if (xn[2] < 0.0 || xn[2] > 1.0) {
+                xn[2] = (xn[2] < 0.0) ? -xn[2] : 2.0 - xn[2];
+                xn[3] += M_PI;
+                kn[2] = -kn[2];
+                an[2] = -an[2];
+            }
+        }
+        coef c1;
+        coefficients(c, tp, xn, kn, ph->n_sc, &c1);
+        ph->steps += 1;
+        wk->stats[GMO_S_STEPS] += 1;
+
+        double tau_a = 0.5 * (ph->nua + c1.nua) * Cc * dl;
+        double tau_s = tp->scattering ? 0.5 * (ph->nus + c1.nus) * Cc * dl : 0.0;
+        double b = c1.vacuum ? ph->b : c1.b;
+        gmo_gcov(G, ph->x, g);
+        double e_old = e_inf(g, ph->k);
+
+        if (tp->scattering && ph->n_sc < tp->n_sc_max && b * tau_s > ph->x1) {
+            double f = ph->x1 / (b * tau_s);
+            double xs[4], ks[4];
+            for (int m = 0; m < 4; ++m) {
+                xs[m] = ph->x[m] + f * (xn[m] - ph->x[m]);
+                ks[m] = ph->k[m] + f * (kn[m] - ph->k[m]);
+            }
+            double wb = ph->w;
+            ph->w *= exp(-f * tau_a);
+            wk->ledger[GMO_L_W_ABS] += wb - ph->w;
+            wk->ledger[GMO_L_E_ABS] += (wb - ph->w) * e_old * MEC2;
+            gmo_gcov(G, xs, g);
+            double e_s = e_inf(g, ks);
+            wk->ledger[GMO_L_E_DRIFT] += ph->w * (e_s - e_old) * MEC2;
+            scatter_event(c, tp, wk, ph, xs, ks, ph->w / b, ph->x, xn);
+            ph->w *= (1.0 - 1.0 / b);
+            ph->x1 = -log(1.0 - gmo_rng_next(&ph->rng));
+            for (int m = 0; m < 4; ++m) { ph->x[m] = xs[m]; ph->k[m] = ks[m]; }
+            accel(c, ph->x, ph->k, ph->a);
+            coefficients(c, tp, ph->x, ph->k, ph->n_sc, &c0);
+            ph->nua = c0.nua; ph->nus = c0.nus;
+            if (!c0.vacuum) ph->b = c0.b;
+            if (b == 1.0) {   /* all weight went to the child */
+                record_end(c, wk, ph, GMO_END_SPLIT, -1, -1);
+                return;
+            }
+        } else {
+            if (tp->scattering) {
+                if (ph->n_sc < tp->n_sc_max) {
+                    ph->x1 -= b * tau_s;
+                } else {   /* generation cap: extinction without a child (reading) */
+                    double wb = ph->w;
+                    ph->w *= exp(-tau_s);
+                    wk->ledger[GMO_L_W_CAPLOSS] += wb - ph->w;
+                    wk->ledger[GMO_L_E_CAPLOSS] += (wb - ph->w) * e_old * MEC2;
+                }
+            }
+            double wb = ph->w;
+            ph->w *= exp(-tau_a);
+            wk->ledger[GMO_L_W_ABS] += wb - ph->w;
+            wk->ledger[GMO_L_E_ABS] += (wb - ph->w) * e_old * MEC2;
+            for (int m = 0; m < 4; ++m) { ph->x[m] = xn[m]; ph->k[m] = kn[m]; ph->a[m] = an[m]; }
+            ph->nua = c1.nua; ph->nus = c1.nus; ph->b = b;
+            gmo_gcov(G, ph->x, g);
+            double e_new = e_inf(g, ph->k);
+            wk->ledger[GMO_L_E_DRIFT] += ph->w * (e_new - e_old) * MEC2;
+
+            /* ---- termination ---- */
+            int escaped = 0, captured = 0;
+            if (!ks_metric) {
+                for (int j = 0; j < 3; ++j) {
+                    double lo = G->x_start[j], hi = G->x_start[j] + G->n[j] * G->dx[j];
+                    if (ph->x[j + 1] < lo || ph->x[j + 1] >= hi) escaped = 1;
+                }
+            } else {
+                double r = exp(ph->x[1]);
+                if (r >= G->r_record) escaped = 1;
+                else if (r < rh * (1.0 + tp->horizon_eps)) captured = 1;
+            }
+            if (escaped) {
+                double nuinf = e_new * MEC2 / GMO_HPL;
+                double dln = log(tp->nu_hi / tp->nu_lo) / tp->n_nu;
+                double fi = floor((log(nuinf) - log(tp->nu_lo)) / dln);
+                double E = ph->w * e_new * MEC2;
+                if (!(fi >= 0.0 && fi < tp->n_nu)) {
+                    wk->ledger[GMO_L_W_OOB] += ph->w; wk->ledger[GMO_L_E_OOB] += E;
+                    wk->stats[GMO_S_OOB] += 1;
+                    record_end(c, wk, ph, GMO_END_OOB, -1, -1);
+                    return;
+                }
+                double th;
+                if (!ks_metric) {
+                    double kk = sqrt(ph->k[1] * ph->k[1] + ph->k[2] * ph->k[2] + ph->k[3] * ph->k[3]);
+                    th = acos(ph->k[3] / kk);
+                } else {
+                    th = gmo_th_of_x2(G, ph->x[2]);
+                }
+                int ith = (int)floor(th * tp->n_theta / M_PI);
+                if (ith < 0) ith = 0;
+                if (ith > tp->n_theta - 1) ith = tp->n_theta - 1;
+                int inu = (int)fi;
+                double *bin = &wk->spec[((size_t)ith * tp->n_nu + inu) * 3];
+                bin[0] += E; bin[1] += E * E; bin[2] += 1.0;
+                wk->ledger[GMO_L_W_ESC] += ph->w; wk->ledger[GMO_L_E_ESC] += E;
+                wk->stats[GMO_S_ESCAPED] += 1;
+                record_end(c, wk, ph, GMO_END_ESCAPE, inu, ith);
+                return;
+            }
+            if (captured) {
+                wk->ledger[GMO_L_W_CAPT] += ph->w; wk->ledger[GMO_L_E_CAPT] += ph->w * e_new * MEC2;
+                wk->stats[GMO_S_CAPTURED] += 1;
+                record_end(c, wk, ph, GMO_END_CAPTURE, -1, -1);
+                return;
+            }
+        }
+        /* ---- Russian roulette (reading) ---- */
+        if (ph->w < tp->roulette_frac * ph->w_birth) {
+            gmo_gcov(G, ph->x, g);
+            double e = e_inf(g, ph->k);
+            if (gmo_rng_next(&ph->rng) < tp->roulette_p) {
+                double gain = ph->w * (1.0 / tp->roulette_p - 1.0);
+                wk->ledger[GMO_L_W_ROUL] += gain; wk->ledger[GMO_L_E_ROUL] += gain * e * MEC2;
+                ph->w /= tp->roulette_p;
+                wk->stats[GMO_S_ROUL_SURVIVE] += 1;
+            } else {
+                wk->ledger[GMO_L_W_ROUL] -= ph->w; wk->ledger[GMO_L_E_ROUL] -= ph->w * e * MEC2;
+                wk->stats[GMO_S_ROUL_KILL] += 1;
+                double wk_w = ph->w;
+                ph->w = 0.0;
+                record_end(c, wk, ph, GMO_END_ROULETTE, -1, -1);
+                (void)wk_w;
+                return;
+            }
+        }
+    }
+}
+
+/* Birth of root p in zone i (Sampling procedure section). */
+static void birth(const gmo_ctx *c, worker *wk, uint64_t p, int z, photon *ph)
+{
+    const gmo_grid *G = &c->grid;
+    memset(ph, 0, sizeof(*ph));
+    ph->rng.seed = c->ep.seed;
+    ph->rng.s[0] = (uint32_t)p; ph->rng.s[1] = (uint32_t)(p >> 32);
+    ph->rng.s[2] = ((uint32_t)c->ep.instance << 8) | 1u;
+    ph->rng.block = 0;
+    int i3 = z % G->n[2], i2 = (z / G->n[2]) % G->n[1], i1 = z / (G->n[2] * G->n[1]);
+    int id[3] = {i1, i2, i3};
+    ph->x[0] = 0.0;
+    for (int j = 0; j < 3; ++j) ph->x[j + 1] = G->x_start[j] + (id[j] + gmo_rng_next(&ph->rng)) * G->dx[j];
+    /* frequency by rejection against max_k dN/dln nu at the nodes */
+    double lnnu, nu;
+    for (int64_t it = 0;; ++it) {
+        lnnu = c->lnnu_min + gmo_rng_next(&ph->rng) * c->lnnu_span;
+        nu = exp(lnnu);
+        double u2 = gmo_rng_next(&ph->rng);
+        double F = zone_J(c, z, nu) / exp(ln_weight(c, lnnu));
+        wk->stats[GMO_S_NU_TRIALS] += 1;
+        if (F > c->fmax[z]) wk->stats[GMO_S_OVERSHOOT] += 1;
+        if (u2 < F / c->fmax[z] || it >= GMO_MAX_TRIALS) break;
+    }
+    /* direction by rejection against j(pi/2) */
+    double cth;
+    double jmax = zone_j(c, z, nu, 0.0);
+    for (int64_t it = 0;; ++it) {
+        cth = 2.0 * gmo_rng_next(&ph->rng) - 1.0;
+        double u4 = gmo_rng_next(&ph->rng);
+        wk->stats[GMO_S_DIR_TRIALS] += 1;
+        if (u4 < zone_j(c, z, nu, cth) / jmax || it >= GMO_MAX_TRIALS) break;
+    }
+    double phi = 2.0 * M_PI * gmo_rng_next(&ph->rng);
+    double g[4][4], u[4], bh[4], e[4][4];
+    int has_b;
+    gmo_gcov(G, ph->x, g);
+    fluid_frame(c, z, g, u, bh, &has_b);
+    emission_tetrad(g, u, bh, e);
+    double eps = GMO_HPL * nu / MEC2;
+    double sth = sqrt(1.0 - cth * cth);
+    double kf[4] = {eps, eps * sth * cos(phi), eps * sth * sin(phi), eps * cth};
+    from_frame(e, kf, ph->k);
+    ph->w = ph->w_birth = exp(ln_weight(c, lnnu));
+    ph->x1 = -log(1.0 - gmo_rng_next(&ph->rng));
+    ph->n_sc = 0;
+    wk->ledger[GMO_L_W_EMIT] += ph->w;
+    wk->ledger[GMO_L_E_EMIT] += ph->w * e_inf(g, ph->k) * MEC2;
+    wk->stats[GMO_S_ROOTS] += 1;
+}
+
+static int zone_of_root(const gmo_ctx *c, uint64_t p)
+{
+    int lo = 0, hi = c->nz;             /* offset[lo] <= p < offset[hi] */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (c->offset[mid] <= p) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+int gmo_track_scatter(gmo_ctx *c, const gmo_track_params *tp, uint64_t root_begin,
+                      uint64_t root_end, int n_threads, gmo_trace_rec *trace, uint64_t trace_cap,
+                      uint64_t *trace_n)
+{
+    if (!c || !c->made) { gmo_set_error("make superphotons first"); return GMO_ESTATE; }
+    if (tp->n_nu < 1 || tp->n_theta < 1 || !(tp->nu_hi > tp->nu_lo) || !(tp->nu_lo > 0.0) ||
+        !(tp->bias_max >= 1.0) || !(tp->step_h > 0.0) || tp->verlet_max_it < 1 ||
+        tp->n_sc_max < 0 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0)) {
+        gmo_set_error("bad track parameters"); return GMO_EINVAL;
+    }
+    if (root_end > c->offset[c->nz]) root_end = c->offset[c->nz];
+    if (c->spec && (c->n_nu != tp->n_nu || c->n_theta != tp->n_theta)) {
+        gmo_set_error("tally shape changed without reset"); return GMO_EINVAL;
+    }
+    if (!c->spec) {
+        c->n_nu = tp->n_nu; c->n_theta = tp->n_theta;
+        c->spec = calloc((size_t)tp->n_nu * tp->n_theta * 3, sizeof(double));
+    }
+    if (tp->scattering && !c->sh) {
+        c->sh = malloc(sizeof(double) * GMO_SH_NT * GMO_SH_NE);
+        gmo_sigma_hot_table(c->sh);
+    }
+#ifdef _OPENMP
+    int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#else
+    int nt = 1; (void)n_threads;
+#endif
+    worker *W = calloc(nt, sizeof(worker));
+    size_t nbins = (size_t)tp->n_nu * tp->n_theta * 3;
+    for (int t = 0; t < nt; ++t) {
+        W[t].spec = calloc(nbins, sizeof(double));
+        if (trace) { W[t].trace = malloc(sizeof(gmo_trace_rec) * (trace_cap ? trace_cap : 1)); W[t].trace_cap = trace_cap; }
+    }
+    int64_t nroots = (int64_t)(root_end > root_begin ? root_end - root_begin : 0);
+    #pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        worker *wk = &W[omp_get_thread_num()];
+#else
+        worker *wk = &W[0];
+#endif
+        #pragma omp for schedule(static, 1024)
+        for (int64_t q = 0; q < nroots; ++q) {
+            uint64_t p = root_begin + (uint64_t)q;
+            photon ph;
+            birth(c, wk, p, zone_of_root(c, p), &ph);
+            /* roots have block counter > 0 after birth; children start at 0 */
+            run_photon(c, tp, wk, &ph);
+            while (wk->stack_n > 0) {
+                photon ch = wk->stack[--wk->stack_n];
+                wk->stats[GMO_S_CHILDREN] += 1;
+                run_photon(c, tp, wk, &ch);
+            }
+        }
+    }
+    uint64_t tn = 0;
+    for (int t = 0; t < nt; ++t) {
+        for (size_t i = 0; i < nbins; ++i) c->spec[i] += W[t].spec[i];
+        for (int i = 0; i < GMO_L_N; ++i) c->ledger[i] += W[t].ledger[i];
+        for (int i = 0; i < GMO_S_N; ++i) c->stats[i] += W[t].stats[i];
+        if (trace)
+            for (uint64_t r = 0; r < W[t].trace_n && tn < trace_cap; ++r) trace[tn++] = W[t].trace[r];
+        free(W[t].spec); free(W[t].trace); free(W[t].stack);
+    }
+    free(W);
+    if (trace_n) *trace_n = tn;
+    return GMO_OK;
+}
+
+int gmo_read_spectrum(gmo_ctx *c, double *spec, double *ledger, int64_t *stats, int reset)
+{
+    if (!c) { gmo_set_error("null context"); return GMO_EINVAL; }
+    size_t nb = (size_t)c->n_nu * c->n_theta * 3;
+    if (spec && c->spec) memcpy(spec, c->spec, sizeof(double) * nb);
+    if (ledger) memcpy(ledger, c->ledger, sizeof(c->ledger));
+    if (stats) memcpy(stats, c->stats, sizeof(c->stats));
+    if (reset) {
+        if (c->spec) memset(c->spec, 0, sizeof(double) * nb);
+        memset(c->ledger, 0, sizeof(c->ledger));
+        memset(c->stats, 0, sizeof(c->stats));
+    }
+    return GMO_OK;
+}
