@@ -1,0 +1,215 @@
+/*
+ * gm.h -- C ABI of the MI355X (gfx950) superphoton Monte Carlo library.
+ *
+ * The library computes the spectrum emerging from hot, magnetised plasma by
+ * grmonty-style Monte Carlo radiative transfer (Naethe Motta, Nemmen & Joshi,
+ * "GPUmonty", arXiv 2602.13198): superphotons are emitted from each zone in
+ * proportion to the thermal synchrotron emissivity, pushed along null
+ * geodesics, attenuated by absorption, split by biased thermal Compton
+ * scattering into child superphotons, and tallied by (frequency,
+ * inclination) when they escape.
+ *
+ * Conventions
+ *  - Every function returns gm_status; on error the message is available
+ *    from gm_last_error() (per host thread) and, for GM_EINVAL, the context
+ *    is unchanged.  No C++ exception crosses this boundary.
+ *  - All work is queued on the HIP stream given to gm_create (NULL = the
+ *    null stream).  Functions return once the work is queued, except where
+ *    a host output is requested (documented per function), which
+ *    synchronises that stream.
+ *  - Caller buffers are borrowed for the duration of the call only.  The
+ *    context owns every device buffer it allocates; gm_destroy frees them.
+ *  - One context per host thread; a context is not thread safe.
+ *  - Results depend only on (seed, instance, inputs, parameters): launch
+ *    geometry and scheduling change them only through the summation order
+ *    of the floating-point tallies.
+ */
+#ifndef GM_H
+#define GM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gm_ctx gm_ctx;
+
+typedef enum {
+    GM_OK = 0,
+    GM_EINVAL = -1,        /* bad argument; nothing changed                   */
+    GM_ENOMEM = -2,        /* device allocation failed or a queue overflowed  */
+    GM_EDEVICE = -3,       /* a HIP call failed                               */
+    GM_ESTATE = -4,        /* call out of order (e.g. track before make)      */
+    GM_EUNSUPPORTED = -5   /* option not built into this library              */
+} gm_status;
+
+#define GM_MAX_INSTANCES 64
+
+/* Metric of the zone grid. */
+#define GM_METRIC_MINKOWSKI_CART 0   /* flat, x^i Cartesian in units of ell         */
+#define GM_METRIC_KS_MKS         1   /* Kerr, Kerr-Schild in modified coordinates:
+                                        r = exp(x1), theta = pi x2 + (1-h)/2 sin(2 pi x2),
+                                        phi = x3, lengths in r_g = ell              */
+
+typedef struct {
+    int    metric;          /* GM_METRIC_*                                        */
+    int    n[3];            /* zones per coordinate, each >= 1                    */
+    double x_start[3];      /* lower coordinate edge                              */
+    double dx[3];           /* coordinate zone width, > 0                         */
+    double a_spin;          /* Kerr spin |a| < 1 (KS only)                        */
+    double h_slope;         /* modified-coordinate polar slope h (KS only)        */
+    double L_unit_cm;       /* length unit ell in cm, > 0                         */
+    double r_record;        /* record radius in ell (KS only)                     */
+} gm_grid;
+
+/* Zone plasma in double precision, zone index z = (i1*n2 + i2)*n3 + i3.
+ * ucon and bcon are [4][nzones] (component-major).  on_device = 1 means the
+ * pointers are device pointers, else host pointers.  Zones with n_e > 0 need
+ * theta_e > 0.  bcon gives only the field direction; its normalisation is
+ * ignored. */
+typedef struct {
+    int           on_device;
+    const double *n_e;      /* electron density, cm^-3                            */
+    const double *theta_e;  /* electron temperature kT/(m_e c^2)                  */
+    const double *B;        /* field strength, Gauss                              */
+    const double *ucon;     /* fluid 4-velocity, contravariant code components    */
+    const double *bcon;     /* field direction 4-vector                            */
+} gm_zones;
+
+typedef struct {
+    double   n_target;      /* N_s, expected number of root superphotons (> 0)    */
+    double   nu_min, nu_max;/* emission band in Hz, 0 < nu_min < nu_max          */
+    int      n_wnodes;      /* weight-table nodes, odd, 3..4097                    */
+    double   w_floor_rel;   /* weight floor relative to the table maximum, >= 0   */
+    uint64_t seed;          /* key of every random stream                         */
+} gm_emit_params;
+
+/* Scattering bias b >= 1 (Scattering section of the paper). */
+#define GM_BIAS_CONST  0    /* b = bias_value                                    */
+#define GM_BIAS_THETA2 1    /* b = bias_value * Theta_e^2                        */
+#define GM_BIAS_GEN2   2    /* b = (n_sc+1)^2 / (n_e sigma_T bias_value ell)     */
+
+#define GM_PRECISION_F64 0  /* all transport arithmetic in double                 */
+
+typedef struct {
+    int     scattering;     /* 0: no Compton opacity; 1: biased thermal Compton   */
+    int     bias_mode;      /* GM_BIAS_*                                          */
+    double  bias_value;
+    double  bias_max;       /* b is clamped to [1, bias_max]; bias_max >= 1       */
+    int     n_sc_max;       /* highest generation that may still scatter, 0..15   */
+    double  step_h;         /* step-size factor (Cartesian: fraction of a zone)   */
+    double  verlet_tol;     /* corrector tolerance (the paper uses 1e-3)          */
+    int     verlet_max_it;  /* corrector iteration cap, >= 1                      */
+    double  roulette_frac;  /* Russian roulette when w < roulette_frac * w_birth  */
+    double  roulette_p;     /* survival probability, (0, 1]                       */
+    double  horizon_eps;    /* capture when r < r_h (1 + horizon_eps)             */
+    int64_t max_steps;      /* a photon still alive after this many steps stops   */
+    int     n_nu;           /* tally frequency bins, log-uniform on [nu_lo, nu_hi) */
+    double  nu_lo, nu_hi;   /* Hz                                                 */
+    int     n_theta;        /* tally inclination bins, uniform on [0, pi]         */
+    int     precision;      /* GM_PRECISION_*                                     */
+} gm_track_params;
+
+/* Ledger slots read by gm_read_spectrum (photons/s and erg/s at infinity). */
+enum {
+    GM_L_W_EMIT = 0, GM_L_E_EMIT, GM_L_W_ESC, GM_L_E_ESC, GM_L_W_OOB, GM_L_E_OOB,
+    GM_L_W_ABS, GM_L_E_ABS, GM_L_W_CAPT, GM_L_E_CAPT, GM_L_W_CAPLOSS, GM_L_E_CAPLOSS,
+    GM_L_W_ROUL, GM_L_E_ROUL, GM_L_W_STUCK, GM_L_E_STUCK, GM_L_E_COMPTON, GM_L_E_DRIFT,
+    GM_L_N
+};
+
+/* Event counters returned by gm_track_scatter. */
+enum {
+    GM_S_ROOTS = 0, GM_S_CHILDREN, GM_S_STEPS, GM_S_VERLET_IT, GM_S_SCATTER,
+    GM_S_ROUL_KILL, GM_S_ROUL_SURVIVE, GM_S_CAPTURED, GM_S_ESCAPED, GM_S_OOB, GM_S_STUCK,
+    GM_S_OVERSHOOT, GM_S_NU_TRIALS, GM_S_DIR_TRIALS, GM_S_E_TRIALS, GM_S_ANG_TRIALS,
+    GM_S_GEN0  /* GM_S_GEN0 + g: photons of generation g, g < 16 */
+};
+#define GM_S_N (GM_S_GEN0 + 16)
+
+/* Termination kinds in trace records. */
+#define GM_END_ESCAPE   1
+#define GM_END_OOB      2
+#define GM_END_CAPTURE  3
+#define GM_END_ROULETTE 4
+#define GM_END_STUCK    5
+#define GM_END_SPLIT    6
+
+/* One trace record per finished superphoton, 112 bytes. */
+typedef struct {
+    uint32_t s0, s1, s2;    /* random stream id (identifies the photon)           */
+    int32_t  n_sc;          /* scattering generation                              */
+    int32_t  kind;          /* GM_END_*                                           */
+    int32_t  i_nu, i_theta; /* tally bin or -1                                    */
+    uint32_t n_steps;
+    double   w_birth, w_end;
+    double   x[4], k[4];    /* position and wavevector at the end                 */
+} gm_trace_rec;
+
+/* Create a context on HIP device `device` queuing work on `hip_stream`
+ * (a hipStream_t, or NULL).  Builds the device tables used by every run. */
+gm_status gm_create(gm_ctx **out, int device, void *hip_stream);
+
+/* Free every buffer the context owns (synchronises its stream). */
+gm_status gm_destroy(gm_ctx *ctx);
+
+/* Message of the last error on this host thread (never NULL). */
+const char *gm_last_error(void);
+
+/* Load the plasma of one instance (0 <= instance < GM_MAX_INSTANCES):
+ * validates and copies the zones into packed device records and prepares
+ * the per-zone emission constants (Emissivity section).  Replaces what the
+ * instance held; its tallies are kept. */
+gm_status gm_load_zones(gm_ctx *ctx, int instance, const gm_grid *grid, const gm_zones *zones);
+
+/* Superphoton generation (Creation of superphotons and Sampling procedure
+ * sections): builds the weight table w(nu) (eq:weight_calc), draws each
+ * zone's superphoton count by stochastic rounding of its expectation, and
+ * assigns photon ids.  instance = -1 makes every loaded instance with the
+ * same parameters.  n_made (may be NULL) receives the number of roots of the
+ * last instance made and synchronises the stream. */
+gm_status gm_make_superphotons(gm_ctx *ctx, int instance, const gm_emit_params *params,
+                               uint64_t *n_made);
+
+/* Track every root made and not yet tracked, and all its descendants, to
+ * escape, capture or loss (geodesic, Absorption and Scattering sections),
+ * adding to the tallies.  stats (may be NULL) receives GM_S_N counters of
+ * this call and synchronises the stream.  GM_ENOMEM if a child queue would
+ * overflow (the tallies of that call are then incomplete). */
+gm_status gm_track_scatter(gm_ctx *ctx, const gm_track_params *params, int64_t *stats);
+
+/* Copy the tally of one instance into `out` = [n_theta][n_nu][3] doubles
+ * {sum of w E, sum of (w E)^2, number of superphotons}, E the energy at
+ * infinity in erg (so sums are erg/s), out_on_device selecting a device or
+ * host buffer; ledger_out (host, may be NULL) receives GM_L_N doubles.
+ * reset = 1 clears the tally and ledger afterwards.  Synchronises. */
+gm_status gm_read_spectrum(gm_ctx *ctx, int instance, double *out, int out_on_device,
+                           double *ledger_out, int reset);
+
+/* ---- inspection (tests, diagnostics) --------------------------------- */
+
+/* Per-zone results of the last make of an instance, host buffers, any may
+ * be NULL: counts [nz] u32, expected counts [nz], frequency rejection bound
+ * [nz], ln w at the weight nodes [n_wnodes].  Synchronises. */
+gm_status gm_read_emission(gm_ctx *ctx, int instance, uint32_t *counts, double *nbar,
+                           double *fmax, double *ln_w);
+
+/* Record one gm_trace_rec per finished photon into a device buffer of
+ * `capacity` records (NULL disables).  Records past the capacity are
+ * counted but not written.  gm_trace_count returns the count (synchronises). */
+gm_status gm_set_trace(gm_ctx *ctx, void *device_buffer, uint64_t capacity);
+gm_status gm_trace_count(gm_ctx *ctx, uint64_t *n);
+
+/* The hot cross-section table ln(sigma_h/sigma_T) [64 ln Theta][256 ln eps]
+ * over Theta in [1e-2, 1e3], eps in [1e-12, 1e6], into a host buffer. */
+gm_status gm_sigma_hot_table(gm_ctx *ctx, double *host_out);
+
+/* Angle-integrated emissivity shape G(Xc) = int_0^1 s g(Xc/s) dmu,
+ * s = sqrt(1-mu^2), evaluated on the device for n host values. */
+gm_status gm_eval_G(gm_ctx *ctx, const double *host_x, double *host_out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,617 @@
+// gm_api.hip -- the C ABI of include/gm.h: context, device buffers, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gm.h"
+#include "gm_emit.h"
+#include "gm_host_tables.h"
+#include "gm_track.h"
+
+using namespace gm;
+
+static_assert(sizeof(TraceRec) == sizeof(gm_trace_rec), "trace record layout");
+static_assert(sizeof(TraceRec) == 112, "trace record layout");
+
+namespace {
+
+thread_local std::string g_err = "";
+
+gm_status fail(gm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(GM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t count)
+    {
+        if (count <= n && p) return hipSuccess;
+        if (p) { (void)hipFree(p); p = nullptr; n = 0; }
+        hipError_t e = hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T));
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct Instance {
+    bool loaded = false, made = false;
+    gm_grid grid{};
+    int nz = 0;
+    DevBuf<double> zrec, vol;
+    DevBuf<int> emits;
+    // last make
+    gm_emit_params ep{};
+    int nw = 0;
+    double lnnu_min = 0, lnnu_span = 0;
+    DevBuf<double> nu_nodes, w_node, ln_w, nbar, fmax, partial;
+    DevBuf<uint32_t> count, zone_of_root;
+    DevBuf<unsigned long long> offset, tile;
+    DevBuf<unsigned long long> roots;          // [0] n_roots, [1] root cursor
+    unsigned long long n_roots = 0;
+    bool pending = false;                      // roots made, not yet tracked
+    bool dirty = false;                        // tally holds data since the last reset
+    // tallies
+    int n_nu = 0, n_theta = 0;
+    DevBuf<double> spec, ledger;
+    DevBuf<unsigned long long> stats;
+};
+
+}  // namespace
+
+struct gm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    Instance inst[GM_MAX_INSTANCES];
+    // tables
+    DevBuf<double> gcheb, sh_table, gl_x, gl_w;
+    GCheb G{};
+    ShTable sh{};
+    bool sh_built = false;
+    // child queues (ping-pong) and per-generation counters
+    unsigned long long child_cap = 0;
+    DevBuf<double> cbuf[2][9];
+    DevBuf<uint32_t> cs[2][3];
+    DevBuf<int32_t> cnsc[2];
+    DevBuf<unsigned long long> ctr;             // [gen][2]: count, cursor
+    DevBuf<int> flags;                          // [0] overflow, [1] status
+    // trace
+    TraceRec *trace = nullptr;
+    unsigned long long trace_cap = 0;
+    DevBuf<unsigned long long> trace_n;
+};
+
+static gm_status set_device(gm_ctx *c)
+{
+    HIPCHK(hipSetDevice(c->device));
+    return GM_OK;
+}
+
+static gm_status build_tables(gm_ctx *c)
+{
+    host::GChebHost T = host::build_G_cheb();
+    HIPCHK(c->gcheb.ensure(T.coef.size()));
+    HIPCHK(hipMemcpy(c->gcheb.p, T.coef.data(), T.coef.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->G.coef = c->gcheb.p;
+    c->G.t_lo = T.t_lo;
+    c->G.t_hi = T.t_hi;
+    c->G.inv_h = 1.0 / T.h;
+    c->G.ln_c0 = T.ln_c0;
+    c->G.n_pieces = T.n_pieces;
+    c->G.deg = T.deg;
+    std::vector<double> x, w;
+    host::gauss_legendre(16, x, w);
+    HIPCHK(c->gl_x.ensure(16));
+    HIPCHK(c->gl_w.ensure(16));
+    HIPCHK(hipMemcpy(c->gl_x.p, x.data(), 16 * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->gl_w.p, w.data(), 16 * sizeof(double), hipMemcpyHostToDevice));
+    return GM_OK;
+}
+
+static gm_status ensure_sigma_hot(gm_ctx *c)
+{
+    if (c->sh_built) return GM_OK;
+    HIPCHK(c->sh_table.ensure(kShNT * kShNE));
+    ShBuildArgs S;
+    S.gl_x = c->gl_x.p;
+    S.gl_w = c->gl_w.p;
+    S.table = c->sh_table.p;
+    S.lt0 = std::log(kShThMin);
+    S.dt = (std::log(kShThMax) - std::log(kShThMin)) / (kShNT - 1);
+    S.le0 = std::log(kShEMin);
+    S.de = (std::log(kShEMax) - std::log(kShEMin)) / (kShNE - 1);
+    sigma_hot_build_kernel<<<kShNT * kShNE, 256, 0, c->stream>>>(S);
+    HIPCHK(hipGetLastError());
+    c->sh.t = c->sh_table.p;
+    c->sh.lt0 = S.lt0;
+    c->sh.inv_dt = 1.0 / S.dt;
+    c->sh.le0 = S.le0;
+    c->sh.inv_de = 1.0 / S.de;
+    c->sh_built = true;
+    return GM_OK;
+}
+
+extern "C" {
+
+const char *gm_last_error(void) { return g_err.c_str(); }
+
+gm_status gm_create(gm_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return fail(GM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(GM_EINVAL, "device %d of %d", device, ndev);
+    gm_ctx *c = new gm_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    gm_status s = set_device(c);
+    if (s != GM_OK) { delete c; return s; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return fail(GM_EDEVICE, "device properties"); }
+    c->n_cu = prop.multiProcessorCount;
+    s = build_tables(c);
+    if (s == GM_OK && (c->ctr.ensure(2 * 32) != hipSuccess || c->flags.ensure(4) != hipSuccess ||
+                       c->trace_n.ensure(1) != hipSuccess))
+        s = fail(GM_ENOMEM, "counters");
+    if (s != GM_OK) { gm_destroy(c); return s; }
+    *out = c;
+    return GM_OK;
+}
+
+gm_status gm_destroy(gm_ctx *c)
+{
+    if (!c) return GM_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+    for (auto &I : c->inst) {
+        I.zrec.release(); I.vol.release(); I.emits.release(); I.nu_nodes.release();
+        I.w_node.release(); I.ln_w.release(); I.nbar.release(); I.fmax.release();
+        I.partial.release(); I.count.release(); I.zone_of_root.release(); I.offset.release();
+        I.tile.release(); I.roots.release(); I.spec.release(); I.ledger.release(); I.stats.release();
+    }
+    c->gcheb.release(); c->sh_table.release(); c->gl_x.release(); c->gl_w.release();
+    for (int b = 0; b < 2; ++b) {
+        for (auto &d : c->cbuf[b]) d.release();
+        for (auto &d : c->cs[b]) d.release();
+        c->cnsc[b].release();
+    }
+    c->ctr.release(); c->flags.release(); c->trace_n.release();
+    delete c;
+    return GM_OK;
+}
+
+gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zones *z)
+{
+    if (!c || !g || !z) return fail(GM_EINVAL, "NULL argument");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    if (g->metric != GM_METRIC_MINKOWSKI_CART)
+        return fail(GM_EUNSUPPORTED, "metric %d not built into this library", g->metric);
+    for (int j = 0; j < 3; ++j)
+        if (g->n[j] < 1 || !(g->dx[j] > 0.0) || !std::isfinite(g->x_start[j]))
+            return fail(GM_EINVAL, "grid axis %d", j);
+    if (!(g->L_unit_cm > 0.0)) return fail(GM_EINVAL, "L_unit_cm must be > 0");
+    long long nzl = (long long)g->n[0] * g->n[1] * g->n[2];
+    if (nzl > (1ll << 31) - 1) return fail(GM_EINVAL, "too many zones");
+    int nz = (int)nzl;
+    if (!z->n_e || !z->theta_e || !z->B || !z->ucon || !z->bcon) return fail(GM_EINVAL, "zone array NULL");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    // stage inputs on the device
+    const double *src[5] = {z->n_e, z->theta_e, z->B, z->ucon, z->bcon};
+    size_t cnt[5] = {(size_t)nz, (size_t)nz, (size_t)nz, 4 * (size_t)nz, 4 * (size_t)nz};
+    if (!z->on_device) {
+        // validate on the host before anything changes
+        for (int i = 0; i < nz; ++i) {
+            double ne = z->n_e[i], th = z->theta_e[i], B = z->B[i];
+            if (!(ne >= 0.0) || !std::isfinite(ne) || !(B >= 0.0) || !std::isfinite(B) || !std::isfinite(th))
+                return fail(GM_EINVAL, "zone %d: bad n_e/B/theta", i);
+            if (ne > 0.0 && !(th > 0.0)) return fail(GM_EINVAL, "zone %d: n_e > 0 needs theta_e > 0", i);
+            if (ne > 0.0 && !(z->ucon[i] > 0.0)) return fail(GM_EINVAL, "zone %d: u^t must be > 0", i);
+        }
+    }
+    Instance &I = c->inst[instance];
+    DevBuf<double> stage[5];
+    const double *dsrc[5];
+    for (int k = 0; k < 5; ++k) {
+        if (z->on_device) { dsrc[k] = src[k]; continue; }
+        if (stage[k].ensure(cnt[k]) != hipSuccess) {
+            for (auto &b : stage) b.release();
+            return fail(GM_ENOMEM, "zone staging");
+        }
+        if (hipMemcpyAsync(stage[k].p, src[k], cnt[k] * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+            for (auto &b : stage) b.release();
+            return fail(GM_EDEVICE, "zone upload");
+        }
+        dsrc[k] = stage[k].p;
+    }
+    if (I.zrec.ensure((size_t)nz * Z_STRIDE) != hipSuccess || I.vol.ensure(nz) != hipSuccess ||
+        I.emits.ensure(nz) != hipSuccess) {
+        for (auto &b : stage) b.release();
+        return fail(GM_ENOMEM, "zone records");
+    }
+    PrepArgs P;
+    P.n_e = dsrc[0]; P.theta = dsrc[1]; P.B = dsrc[2]; P.ucon = dsrc[3]; P.bcon = dsrc[4];
+    P.zrec = I.zrec.p; P.vol = I.vol.p; P.emits = I.emits.p;
+    for (int j = 0; j < 3; ++j) { P.n[j] = g->n[j]; P.xs[j] = g->x_start[j]; P.dx[j] = g->dx[j]; }
+    P.L3 = g->L_unit_cm * g->L_unit_cm * g->L_unit_cm;
+    P.nz = nz;
+    zone_prep_kernel<<<(nz + 255) / 256, 256, 0, c->stream>>>(P);
+    hipError_t e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(c->stream);     // staging buffers are freed next
+    for (auto &b : stage) b.release();
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(GM_EDEVICE, "zone prep: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    I.grid = *g;
+    I.nz = nz;
+    I.loaded = true;
+    I.made = false;
+    I.pending = false;
+    return GM_OK;
+}
+
+static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint64_t *n_made)
+{
+    Instance &I = c->inst[instance];
+    if (!I.loaded) return fail(GM_ESTATE, "instance %d has no zones", instance);
+    const int nz = I.nz, nw = p->n_wnodes;
+    const int nblk = (nz + 255) / 256;
+    if (I.nu_nodes.ensure(nw) != hipSuccess || I.w_node.ensure(nw) != hipSuccess ||
+        I.ln_w.ensure(nw) != hipSuccess || I.nbar.ensure(nz) != hipSuccess ||
+        I.fmax.ensure(nz) != hipSuccess || I.count.ensure(nz) != hipSuccess ||
+        I.offset.ensure((size_t)nz + 1) != hipSuccess || I.partial.ensure((size_t)nblk * nw) != hipSuccess ||
+        I.tile.ensure((size_t)nz / kScanTile + 2) != hipSuccess || I.roots.ensure(2) != hipSuccess)
+        return fail(GM_ENOMEM, "emission buffers");
+    const double lnmin = std::log(p->nu_min), span = std::log(p->nu_max / p->nu_min);
+    std::vector<double> nus(nw);
+    for (int k = 0; k < nw; ++k) nus[k] = std::exp(lnmin + span * k / (nw - 1));
+    HIPCHK(hipMemcpyAsync(I.nu_nodes.p, nus.data(), nw * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    EmitArgs E;
+    E.zrec = I.zrec.p; E.vol = I.vol.p; E.emits = I.emits.p; E.nu_nodes = I.nu_nodes.p;
+    E.nz = nz; E.nw = nw; E.G = c->G; E.partial = I.partial.p; E.n_blocks = nblk;
+    E.w_node = I.w_node.p; E.ln_w = I.ln_w.p; E.span = span; E.n_target = p->n_target;
+    E.w_floor_rel = p->w_floor_rel; E.nbar = I.nbar.p; E.fmax = I.fmax.p; E.count = I.count.p;
+    E.key0 = (uint32_t)p->seed; E.key1 = (uint32_t)(p->seed >> 32); E.inst = instance;
+    E.status = c->flags.p + 1;
+    phi_partial_kernel<<<nblk, 256, 0, c->stream>>>(E);
+    weight_table_kernel<<<1, 256, 0, c->stream>>>(E);
+    count_kernel<<<nblk, 256, 0, c->stream>>>(E);
+    const int ntile = (nz + kScanTile - 1) / kScanTile;
+    scan_tiles_kernel<<<ntile, 256, 0, c->stream>>>(I.count.p, nz, I.tile.p);
+    scan_sums_kernel<<<1, 256, 0, c->stream>>>(I.tile.p, ntile, I.offset.p + nz);
+    scan_write_kernel<<<ntile, 256, 0, c->stream>>>(I.count.p, nz, I.tile.p, I.offset.p);
+    HIPCHK(hipGetLastError());
+    int status = 0;
+    unsigned long long total = 0;
+    HIPCHK(hipMemcpyAsync(&status, c->flags.p + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&total, I.offset.p + nz, sizeof(total), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (status != 0) return fail(GM_EINVAL, "no zone emits in the band [%g, %g] Hz", p->nu_min, p->nu_max);
+    if (total > 0) {
+        if (I.zone_of_root.ensure(total) != hipSuccess) return fail(GM_ENOMEM, "root table (%llu)", total);
+        unsigned long long nb = (total + 255) / 256;
+        fill_zone_of_root_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(I.offset.p, nz, total, I.zone_of_root.p);
+        HIPCHK(hipGetLastError());
+    }
+    unsigned long long rc[2] = {total, 0ull};
+    HIPCHK(hipMemcpyAsync(I.roots.p, rc, sizeof(rc), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    I.ep = *p;
+    I.nw = nw;
+    I.lnnu_min = lnmin;
+    I.lnnu_span = span;
+    I.n_roots = total;
+    I.made = true;
+    I.pending = true;
+    if (n_made) *n_made = total;
+    return GM_OK;
+}
+
+gm_status gm_make_superphotons(gm_ctx *c, int instance, const gm_emit_params *p, uint64_t *n_made)
+{
+    if (!c || !p) return fail(GM_EINVAL, "NULL argument");
+    if (!(p->nu_min > 0.0) || !(p->nu_max > p->nu_min) || p->n_wnodes < 3 || p->n_wnodes > 4097 ||
+        !(p->n_wnodes & 1) || !(p->n_target > 0.0) || !(p->w_floor_rel >= 0.0))
+        return fail(GM_EINVAL, "bad emission parameters");
+    if (instance < -1 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    if (instance >= 0) return make_one(c, instance, p, n_made);
+    bool any = false;
+    for (int i = 0; i < GM_MAX_INSTANCES; ++i)
+        if (c->inst[i].loaded) {
+            any = true;
+            s = make_one(c, i, p, n_made);
+            if (s != GM_OK) return s;
+        }
+    return any ? GM_OK : fail(GM_ESTATE, "no instance loaded");
+}
+
+static gm_status ensure_children(gm_ctx *c, unsigned long long cap)
+{
+    if (c->child_cap >= cap) return GM_OK;
+    for (int b = 0; b < 2; ++b) {
+        for (auto &d : c->cbuf[b])
+            if (d.ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "child queue of %llu", cap);
+        for (auto &d : c->cs[b])
+            if (d.ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "child queue of %llu", cap);
+        if (c->cnsc[b].ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "child queue of %llu", cap);
+    }
+    c->child_cap = cap;
+    return GM_OK;
+}
+
+static ChildSoA child_soa(gm_ctx *c, int b)
+{
+    ChildSoA s;
+    for (int m = 0; m < 4; ++m) { s.x[m] = c->cbuf[b][m].p; s.k[m] = c->cbuf[b][4 + m].p; }
+    s.w = c->cbuf[b][8].p;
+    s.s0 = c->cs[b][0].p; s.s1 = c->cs[b][1].p; s.s2 = c->cs[b][2].p;
+    s.n_sc = c->cnsc[b].p;
+    return s;
+}
+
+__global__ void reset_counters_kernel(unsigned long long *ctr, int n, int *overflow)
+{
+    int i = threadIdx.x;
+    if (i < n) ctr[i] = 0ull;
+    if (i == 0) *overflow = 0;
+}
+
+static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, std::vector<long long> &acc)
+{
+    Instance &I = c->inst[ii];
+    const size_t nspec = (size_t)tp->n_theta * tp->n_nu * 3;
+    const bool reshape = I.spec.p && (I.n_nu != tp->n_nu || I.n_theta != tp->n_theta);
+    if (reshape && I.dirty) return fail(GM_EINVAL, "tally shape changed without a reset read");
+    if (!I.spec.p || reshape) {
+        if (I.spec.ensure(nspec) != hipSuccess || I.ledger.ensure(L_N) != hipSuccess ||
+            I.stats.ensure(S_N) != hipSuccess)
+            return fail(GM_ENOMEM, "tallies");
+        HIPCHK(hipMemsetAsync(I.spec.p, 0, nspec * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(I.ledger.p, 0, L_N * sizeof(double), c->stream));
+    }
+    I.n_nu = tp->n_nu;
+    I.n_theta = tp->n_theta;
+    I.dirty = true;
+    HIPCHK(hipMemsetAsync(I.stats.p, 0, S_N * sizeof(unsigned long long), c->stream));
+
+    const size_t lds = (size_t)(L_N + S_N) * 8 + nspec * 8;
+    if (lds > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %zu bins exceeds the LDS tally", nspec / 3);
+    int occ = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_kernel<Minkowski>, 256, lds));
+    occ = std::max(occ, 1);
+    const int grid = c->n_cu * occ;
+
+    TrackArgs A{};
+    A.zrec = I.zrec.p;
+    for (int j = 0; j < 3; ++j) { A.n[j] = I.grid.n[j]; A.xs[j] = I.grid.x_start[j]; A.dx[j] = I.grid.dx[j]; }
+    A.C = kH * I.grid.L_unit_cm / kMeC2;
+    A.inst = ii;
+    A.key0 = (uint32_t)I.ep.seed;
+    A.key1 = (uint32_t)(I.ep.seed >> 32);
+    A.zone_of_root = I.zone_of_root.p;
+    A.n_roots = I.roots.p;
+    A.lnnu_min = I.lnnu_min;
+    A.lnnu_span = I.lnnu_span;
+    A.n_wnodes = I.nw;
+    A.ln_w = I.ln_w.p;
+    A.fmax = I.fmax.p;
+    A.G = c->G;
+    A.spec = I.spec.p;
+    A.ledger = I.ledger.p;
+    A.stats = I.stats.p;
+    A.n_nu = tp->n_nu;
+    A.n_theta = tp->n_theta;
+    A.ln_nu_lo = std::log(tp->nu_lo);
+    A.inv_dln_nu = 1.0 / (std::log(tp->nu_hi / tp->nu_lo) / tp->n_nu);
+    A.scattering = tp->scattering;
+    A.bias_mode = tp->bias_mode;
+    A.n_sc_max = tp->n_sc_max;
+    A.verlet_max_it = tp->verlet_max_it;
+    A.bias_value = tp->bias_value;
+    A.bias_max = tp->bias_max;
+    A.step_h = tp->step_h;
+    A.verlet_tol = tp->verlet_tol;
+    A.roulette_frac = tp->roulette_frac;
+    A.roulette_p = tp->roulette_p;
+    A.max_steps = tp->max_steps;
+    A.L_unit_cm = I.grid.L_unit_cm;
+    A.sh = c->sh;
+    A.trace = c->trace;
+    A.trace_n = c->trace_n.p;
+    A.trace_cap = c->trace_cap;
+    A.overflow = c->flags.p;
+    A.dst_cap = c->child_cap;
+    A.backpressure = c->child_cap / 4;
+
+    const int ngen = tp->scattering ? tp->n_sc_max + 1 : 1;
+    for (int pass = 0;; ++pass) {
+        reset_counters_kernel<<<1, 64, 0, c->stream>>>(c->ctr.p, 64, c->flags.p);
+        for (int g = 0; g < ngen; ++g) {
+            A.gen = g;
+            A.src = child_soa(c, g & 1);
+            A.dst = child_soa(c, (g + 1) & 1);
+            A.src_count = c->ctr.p + 2 * g;
+            A.src_cursor = (g == 0) ? I.roots.p + 1 : c->ctr.p + 2 * g + 1;
+            A.dst_count = c->ctr.p + 2 * (g + 1);
+            track_kernel<Minkowski><<<grid, 256, lds, c->stream>>>(A);
+            HIPCHK(hipGetLastError());
+        }
+        unsigned long long rc[2];
+        int ovf = 0;
+        HIPCHK(hipMemcpyAsync(rc, I.roots.p, sizeof(rc), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(&ovf, c->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (ovf) return fail(GM_ENOMEM, "child queue of %llu overflowed", c->child_cap);
+        if (rc[1] >= rc[0]) break;
+        if (pass > 100000) return fail(GM_EDEVICE, "root cursor does not advance");
+    }
+    std::vector<unsigned long long> st(S_N);
+    HIPCHK(hipMemcpy(st.data(), I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int i = 0; i < S_N; ++i) acc[i] += (long long)st[i];
+    I.pending = false;
+    return GM_OK;
+}
+
+gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
+{
+    if (!c || !tp) return fail(GM_EINVAL, "NULL argument");
+    if (tp->n_nu < 1 || tp->n_theta < 1 || !(tp->nu_lo > 0.0) || !(tp->nu_hi > tp->nu_lo) ||
+        !(tp->bias_max >= 1.0) || !(tp->step_h > 0.0) || tp->verlet_max_it < 1 || tp->n_sc_max < 0 ||
+        tp->n_sc_max > 15 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0) || tp->max_steps < 1 ||
+        tp->bias_mode < 0 || tp->bias_mode > 2 || !(tp->bias_value > 0.0))
+        return fail(GM_EINVAL, "bad track parameters");
+    if (tp->precision != GM_PRECISION_F64) return fail(GM_EUNSUPPORTED, "precision %d", tp->precision);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    bool any = false;
+    for (auto &I : c->inst) any |= I.pending;
+    if (!any) return fail(GM_ESTATE, "no superphotons made since the last track");
+    if (tp->scattering) {
+        s = ensure_sigma_hot(c);
+        if (s != GM_OK) return s;
+    }
+    unsigned long long need = 1ull << 22;
+    for (auto &I : c->inst)
+        if (I.pending) need = std::max(need, 2 * I.n_roots);
+    need = std::min(need, 1ull << 26);
+    s = ensure_children(c, need);
+    if (s != GM_OK) return s;
+    std::vector<long long> acc(S_N, 0);
+    for (int i = 0; i < GM_MAX_INSTANCES; ++i)
+        if (c->inst[i].pending) {
+            s = track_instance(c, i, tp, acc);
+            if (s != GM_OK) return s;
+        }
+    if (stats)
+        for (int i = 0; i < S_N; ++i) stats[i] = acc[i];
+    return GM_OK;
+}
+
+gm_status gm_read_spectrum(gm_ctx *c, int instance, double *out, int out_on_device, double *ledger_out,
+                           int reset)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    Instance &I = c->inst[instance];
+    if (!I.spec.p) return fail(GM_ESTATE, "instance %d has no tally", instance);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    const size_t nspec = (size_t)I.n_theta * I.n_nu * 3;
+    if (out)
+        HIPCHK(hipMemcpyAsync(out, I.spec.p, nspec * sizeof(double),
+                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    if (ledger_out)
+        HIPCHK(hipMemcpyAsync(ledger_out, I.ledger.p, L_N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (reset) {
+        HIPCHK(hipMemsetAsync(I.spec.p, 0, nspec * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(I.ledger.p, 0, L_N * sizeof(double), c->stream));
+        I.dirty = false;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_read_emission(gm_ctx *c, int instance, uint32_t *counts, double *nbar, double *fmax, double *ln_w)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    Instance &I = c->inst[instance];
+    if (!I.made) return fail(GM_ESTATE, "instance %d: nothing made", instance);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (counts) HIPCHK(hipMemcpy(counts, I.count.p, (size_t)I.nz * 4, hipMemcpyDeviceToHost));
+    if (nbar) HIPCHK(hipMemcpy(nbar, I.nbar.p, (size_t)I.nz * 8, hipMemcpyDeviceToHost));
+    if (fmax) HIPCHK(hipMemcpy(fmax, I.fmax.p, (size_t)I.nz * 8, hipMemcpyDeviceToHost));
+    if (ln_w) HIPCHK(hipMemcpy(ln_w, I.ln_w.p, (size_t)I.nw * 8, hipMemcpyDeviceToHost));
+    return GM_OK;
+}
+
+gm_status gm_set_trace(gm_ctx *c, void *buf, uint64_t capacity)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (buf && capacity == 0) return fail(GM_EINVAL, "zero capacity");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    c->trace = (TraceRec *)buf;
+    c->trace_cap = buf ? capacity : 0;
+    HIPCHK(hipMemsetAsync(c->trace_n.p, 0, sizeof(unsigned long long), c->stream));
+    return GM_OK;
+}
+
+gm_status gm_trace_count(gm_ctx *c, uint64_t *n)
+{
+    if (!c || !n) return fail(GM_EINVAL, "NULL argument");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    unsigned long long v = 0;
+    HIPCHK(hipMemcpyAsync(&v, c->trace_n.p, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *n = v;
+    return GM_OK;
+}
+
+gm_status gm_sigma_hot_table(gm_ctx *c, double *host_out)
+{
+    if (!c || !host_out) return fail(GM_EINVAL, "NULL argument");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    s = ensure_sigma_hot(c);
+    if (s != GM_OK) return s;
+    HIPCHK(hipMemcpyAsync(host_out, c->sh_table.p, kShNT * kShNE * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_eval_G(gm_ctx *c, const double *hx, double *hy, int n)
+{
+    if (!c || !hx || !hy || n < 0) return fail(GM_EINVAL, "bad argument");
+    if (n == 0) return GM_OK;
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    DevBuf<double> dx, dy;
+    if (dx.ensure(n) != hipSuccess || dy.ensure(n) != hipSuccess) { dx.release(); dy.release(); return fail(GM_ENOMEM, "eval buffers"); }
+    hipError_t e = hipMemcpyAsync(dx.p, hx, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        eval_G_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(c->G, dx.p, dy.p, n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(hy, dy.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dx.release();
+    dy.release();
+    if (e != hipSuccess) return fail(GM_EDEVICE, "eval_G: %s", hipGetErrorString(e));
+    return GM_OK;
+}
+
+}  // extern "C"

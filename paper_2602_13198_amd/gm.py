@@ -1,0 +1,260 @@
+"""ctypes binding of ``include/gm.h`` (argument marshalling only).
+
+Every step of the transport runs in the HIP kernels of ``libgm.so``; this
+module converts Python/numpy/torch arguments to the C structs and pointers of
+the ABI and back.  Importing it imports torch first so that the library binds
+to the same HIP runtime as torch.  It raises if the library is missing: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime that libgm.so must share)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libgm.so")
+
+GM_MAX_INSTANCES = 64
+L_N = 18
+S_GEN0 = 16
+S_N = S_GEN0 + 16
+LEDGER_NAMES = ["W_EMIT", "E_EMIT", "W_ESC", "E_ESC", "W_OOB", "E_OOB", "W_ABS", "E_ABS",
+                "W_CAPT", "E_CAPT", "W_CAPLOSS", "E_CAPLOSS", "W_ROUL", "E_ROUL", "W_STUCK",
+                "E_STUCK", "E_COMPTON", "E_DRIFT"]
+STAT_NAMES = ["ROOTS", "CHILDREN", "STEPS", "VERLET_IT", "SCATTER", "ROUL_KILL",
+              "ROUL_SURVIVE", "CAPTURED", "ESCAPED", "OOB", "STUCK", "OVERSHOOT",
+              "NU_TRIALS", "DIR_TRIALS", "E_TRIALS", "ANG_TRIALS"]
+
+TRACE_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("n_sc", "<i4"),
+                        ("kind", "<i4"), ("i_nu", "<i4"), ("i_theta", "<i4"),
+                        ("n_steps", "<u4"), ("w_birth", "<f8"), ("w_end", "<f8"),
+                        ("x", "<f8", 4), ("k", "<f8", 4)])
+TRACE_BYTES = 112
+
+# Every function the header declares (checked by the CPU symbol test).
+EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make_superphotons",
+           "gm_track_scatter", "gm_read_spectrum", "gm_read_emission", "gm_set_trace",
+           "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G"]
+
+
+class GmGrid(C.Structure):
+    _fields_ = [("metric", C.c_int), ("n", C.c_int * 3), ("x_start", C.c_double * 3),
+                ("dx", C.c_double * 3), ("a_spin", C.c_double), ("h_slope", C.c_double),
+                ("L_unit_cm", C.c_double), ("r_record", C.c_double)]
+
+
+class GmZones(C.Structure):
+    _fields_ = [("on_device", C.c_int), ("n_e", C.c_void_p), ("theta_e", C.c_void_p),
+                ("B", C.c_void_p), ("ucon", C.c_void_p), ("bcon", C.c_void_p)]
+
+
+class GmEmitParams(C.Structure):
+    _fields_ = [("n_target", C.c_double), ("nu_min", C.c_double), ("nu_max", C.c_double),
+                ("n_wnodes", C.c_int), ("w_floor_rel", C.c_double), ("seed", C.c_uint64)]
+
+
+class GmTrackParams(C.Structure):
+    _fields_ = [("scattering", C.c_int), ("bias_mode", C.c_int), ("bias_value", C.c_double),
+                ("bias_max", C.c_double), ("n_sc_max", C.c_int), ("step_h", C.c_double),
+                ("verlet_tol", C.c_double), ("verlet_max_it", C.c_int),
+                ("roulette_frac", C.c_double), ("roulette_p", C.c_double),
+                ("horizon_eps", C.c_double), ("max_steps", C.c_int64), ("n_nu", C.c_int),
+                ("nu_lo", C.c_double), ("nu_hi", C.c_double), ("n_theta", C.c_int),
+                ("precision", C.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libgm.so; raises FileNotFoundError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError("libgm.so is not built (%s); run __graft_entry__.build()" % path)
+    L = C.CDLL(path)
+    vp, i, u64, dp = C.c_void_p, C.c_int, C.c_uint64, C.POINTER(C.c_double)
+    sig = {
+        "gm_create": (i, [C.POINTER(C.c_void_p), i, vp]),
+        "gm_destroy": (i, [vp]),
+        "gm_last_error": (C.c_char_p, []),
+        "gm_load_zones": (i, [vp, i, C.POINTER(GmGrid), C.POINTER(GmZones)]),
+        "gm_make_superphotons": (i, [vp, i, C.POINTER(GmEmitParams), C.POINTER(C.c_uint64)]),
+        "gm_track_scatter": (i, [vp, C.POINTER(GmTrackParams), C.POINTER(C.c_int64)]),
+        "gm_read_spectrum": (i, [vp, i, vp, i, dp, i]),
+        "gm_read_emission": (i, [vp, i, C.POINTER(C.c_uint32), dp, dp, dp]),
+        "gm_set_trace": (i, [vp, vp, u64]),
+        "gm_trace_count": (i, [vp, C.POINTER(C.c_uint64)]),
+        "gm_sigma_hot_table": (i, [vp, dp]),
+        "gm_eval_G": (i, [vp, dp, dp, i]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class GmError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GmError("gm error %d: %s" % (rc, load_library().gm_last_error().decode()))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def grid_struct(g: dict) -> GmGrid:
+    G = GmGrid()
+    G.metric = int(g["metric"])
+    for j in range(3):
+        G.n[j] = int(g["n"][j])
+        G.x_start[j] = float(g["x_start"][j])
+        G.dx[j] = float(g["dx"][j])
+    G.a_spin = float(g.get("a_spin", 0.0))
+    G.h_slope = float(g.get("h_slope", 0.0))
+    G.L_unit_cm = float(g["L_unit_cm"])
+    G.r_record = float(g.get("r_record", 0.0))
+    return G
+
+
+def emit_struct(e: dict) -> GmEmitParams:
+    return GmEmitParams(float(e["n_target"]), float(e["nu_min"]), float(e["nu_max"]),
+                        int(e.get("n_wnodes", 257)), float(e.get("w_floor_rel", 1e-30)),
+                        int(e.get("seed", 0)))
+
+
+def track_struct(t: dict) -> GmTrackParams:
+    T = GmTrackParams()
+    T.scattering = int(t.get("scattering", 0))
+    T.bias_mode = int(t.get("bias_mode", 0))
+    T.bias_value = float(t.get("bias_value", 1.0))
+    T.bias_max = float(t.get("bias_max", 1e6))
+    T.n_sc_max = int(t.get("n_sc_max", 4))
+    T.step_h = float(t.get("step_h", 0.25))
+    T.verlet_tol = float(t.get("verlet_tol", 1e-3))
+    T.verlet_max_it = int(t.get("verlet_max_it", 8))
+    T.roulette_frac = float(t.get("roulette_frac", 1e-4))
+    T.roulette_p = float(t.get("roulette_p", 0.1))
+    T.horizon_eps = float(t.get("horizon_eps", 1e-2))
+    T.max_steps = int(t.get("max_steps", 1000000))
+    T.n_nu = int(t["n_nu"])
+    T.nu_lo = float(t["nu_lo"])
+    T.nu_hi = float(t["nu_hi"])
+    T.n_theta = int(t["n_theta"])
+    T.precision = int(t.get("precision", 0))
+    return T
+
+
+class Context:
+    """A gm_ctx on one device, queuing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(L.gm_create(C.byref(h), int(device), C.c_void_p(stream.cuda_stream)))
+        self._h = h
+        self.device = device
+        self._trace = None
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().gm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the four calls of the hot path ------------------------------------
+    def load_zones(self, wl, instance: int = 0):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64)
+                for a in (wl.n_e, wl.theta_e, wl.B, wl.ucon, wl.bcon)]
+        Z = GmZones(0, *[a.ctypes.data for a in arrs])
+        G = grid_struct(wl.grid)
+        _check(load_library().gm_load_zones(self._h, int(instance), C.byref(G), C.byref(Z)))
+        self.shapes[instance] = int(np.prod(wl.grid["n"]))
+
+    def make_superphotons(self, emit: dict, instance: int = 0, sync: bool = True) -> int | None:
+        P = emit_struct(emit)
+        self.n_wnodes = P.n_wnodes
+        n = C.c_uint64(0)
+        _check(load_library().gm_make_superphotons(self._h, int(instance), C.byref(P),
+                                                   C.byref(n) if sync else None))
+        return int(n.value) if sync else None
+
+    def track_scatter(self, track: dict, stats: bool = True):
+        T = track_struct(track)
+        self.n_nu, self.n_theta = T.n_nu, T.n_theta
+        st = np.zeros(S_N, np.int64)
+        _check(load_library().gm_track_scatter(
+            self._h, C.byref(T), st.ctypes.data_as(C.POINTER(C.c_int64)) if stats else None))
+        return st if stats else None
+
+    def read_spectrum(self, instance: int = 0, reset: bool = False, out=None):
+        """Host numpy [n_theta, n_nu, 3] (or a device torch tensor `out`) and the ledger."""
+        led = np.zeros(L_N)
+        if out is None:
+            spec = np.zeros((self.n_theta, self.n_nu, 3))
+            _check(load_library().gm_read_spectrum(self._h, int(instance), C.c_void_p(spec.ctypes.data),
+                                                   0, _dp(led), int(reset)))
+            return spec, led
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+        assert out.numel() == self.n_theta * self.n_nu * 3
+        _check(load_library().gm_read_spectrum(self._h, int(instance), C.c_void_p(out.data_ptr()),
+                                               1, _dp(led), int(reset)))
+        return out, led
+
+    # -- inspection ---------------------------------------------------------
+    def read_emission(self, instance: int = 0):
+        nz = self.shapes[instance]
+        counts = np.zeros(nz, np.uint32)
+        nbar, fmax = np.zeros(nz), np.zeros(nz)
+        lnw = np.zeros(self.n_wnodes)
+        _check(load_library().gm_read_emission(self._h, int(instance),
+                                               counts.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                               _dp(nbar), _dp(fmax), _dp(lnw)))
+        return dict(counts=counts, nbar=nbar, fmax=fmax, ln_w=lnw)
+
+    def set_trace(self, capacity: int):
+        if capacity <= 0:
+            self._trace = None
+            _check(load_library().gm_set_trace(self._h, None, 0))
+            return
+        self._trace = torch.empty(capacity * TRACE_BYTES, dtype=torch.uint8,
+                                  device="cuda:%d" % self.device)
+        _check(load_library().gm_set_trace(self._h, C.c_void_p(self._trace.data_ptr()), int(capacity)))
+
+    def read_trace(self) -> np.ndarray:
+        n = C.c_uint64(0)
+        _check(load_library().gm_trace_count(self._h, C.byref(n)))
+        cap = self._trace.numel() // TRACE_BYTES
+        m = min(int(n.value), cap)
+        raw = self._trace[: m * TRACE_BYTES].cpu().numpy()
+        return raw.view(TRACE_DTYPE).copy()
+
+    def sigma_hot_table(self) -> np.ndarray:
+        t = np.zeros((64, 256))
+        _check(load_library().gm_sigma_hot_table(self._h, _dp(t)))
+        return t
+
+    def eval_G(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros_like(x)
+        _check(load_library().gm_eval_G(self._h, _dp(x), _dp(y), int(x.size)))
+        return y
