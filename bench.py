@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the superphoton transport on one MI355X.
+
+Workload: the scattering synchrotron sphere -- a uniform sphere of radius
+1e14 cm on a 32^3 Cartesian zone grid, Theta_e = 4, B = 1 G, electron density
+set by the Thomson depth tau_T in {1e-3, 1e-2, 1e-1} (three instances),
+thermal Klein-Nishina Compton scattering with constant bias b = 1/tau_T up to
+four scattering generations, N_s = 1e6 superphotons per instance, 128 log
+bins over 1e8-1e24 Hz x 6 inclination bins, all in double precision.
+
+One step = for each instance: make superphotons (new seed), track and
+scatter all of them to escape/absorption, read the spectrum.  The metric is
+superphotons (roots + scattered children) per second of whole-step wall time
+with the zone data already resident on the GPU.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build runs
+on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+TAUS = (1e-3, 1e-2, 1e-1)
+N_S = 1e6
+FP64_PEAK_TFLOPS = 78.6
+
+# Algorithmic FP64 operations per event of the method (counting convention:
+# + - * / sqrt and each elementary function = 1, fused multiply-add = 2;
+# comparisons, min/max, floor and integer work not counted).  The breakdown
+# of each figure is tabulated in the design doc.
+FLOPS_PER = {
+    "step": 135,          # one flat step incl. opacities at the new point
+    "root": 350,          # birth of a root: position, tetrad, wavevector, opacities
+    "nu_trial": 85,       # one frequency rejection trial (angle integral via Chebyshev)
+    "dir_trial": 18,      # one direction rejection trial
+    "child": 110,         # start of a child: optical-depth draw, opacities
+    "scatter": 510,       # one scattering event: tetrad, boosts, child, parent update
+    "e_trial": 58,        # one electron (gamma, mu) trial of the scattering sampler
+    "ang_trial": 15,      # one Klein-Nishina angle trial
+}
+STAT_INDEX = {"ROOTS": 0, "CHILDREN": 1, "STEPS": 2, "SCATTER": 4, "NU_TRIALS": 12,
+              "DIR_TRIALS": 13, "E_TRIALS": 14, "ANG_TRIALS": 15}
+
+
+def algorithmic_flops(st) -> float:
+    return (FLOPS_PER["step"] * st[STAT_INDEX["STEPS"]]
+            + FLOPS_PER["root"] * st[STAT_INDEX["ROOTS"]]
+            + FLOPS_PER["nu_trial"] * st[STAT_INDEX["NU_TRIALS"]]
+            + FLOPS_PER["dir_trial"] * st[STAT_INDEX["DIR_TRIALS"]]
+            + FLOPS_PER["child"] * st[STAT_INDEX["CHILDREN"]]
+            + FLOPS_PER["scatter"] * st[STAT_INDEX["SCATTER"]]
+            + FLOPS_PER["e_trial"] * st[STAT_INDEX["E_TRIALS"]]
+            + FLOPS_PER["ang_trial"] * st[STAT_INDEX["ANG_TRIALS"]])
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gm_track.h", "gm_frame.h", "gm_physics.h", "gm_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2602_13198_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per tracking launch from the committed counter summary, if
+    it was taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_traffic.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def workloads():
+    from paper_2602_13198_amd import workloads as W
+    return [W.scattering_sphere(t, n_target=N_S, seed=0, instance=i) for i, t in enumerate(TAUS)]
+
+
+def cpu_baseline(wls, roots_per_instance: int):
+    """The oracle, as it stands, on the first `roots_per_instance` roots of
+    each instance (same inputs and seed as the first GPU step)."""
+    import oracle
+    t_total, n_total = 0.0, 0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    o = oracle.Oracle()
+    for k, wl in enumerate(wls):
+        o.load_zones(wl)
+        if k == 0:   # setup outside the timed region: the cross-section table
+            o.make_superphotons(wl.emit)
+            o.track_scatter(wl.track, 0, 0, n_threads=threads)
+            o.read_spectrum(reset=True)
+        t0 = time.perf_counter()
+        o.make_superphotons(wl.emit)
+        o.track_scatter(wl.track, 0, roots_per_instance, n_threads=threads)
+        r = o.read_spectrum(reset=True)
+        t_total += time.perf_counter() - t0
+        n_total += int(r.stats[0] + r.stats[1])
+    o.close()
+    return dict(value=n_total / t_total, unit="superphotons/s", cores=threads, kind="oracle",
+                sample="first %d roots of each of the 3 instances (tau_T=%s) with all their "
+                       "scattered descendants, seed 0; make + track; %.1f s, %d superphotons; "
+                       "host cores visible: %d" % (roots_per_instance, list(TAUS), t_total,
+                                                   n_total, len(os.sched_getaffinity(0))))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-roots", type=int, default=400000,
+                    help="roots per instance in the CPU oracle sample")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (--gpus %d requested); multi-GPU sharding is "
+              "described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_13198_amd import gm
+
+    wls = workloads()
+    ctx = gm.Context(0)
+    for i, wl in enumerate(wls):
+        ctx.load_zones(wl, i)
+    torch.cuda.synchronize()
+
+    def one_step(seed):
+        tot = None
+        for i, wl in enumerate(wls):
+            ctx.make_superphotons(dict(wl.emit, seed=seed), instance=i)
+            st = ctx.track_scatter(wl.track)
+            tot = st if tot is None else tot + st
+        for i in range(len(wls)):
+            ctx.read_spectrum(i, reset=True)
+        return tot
+
+    if args.copy_mib:
+        a = torch.empty(args.copy_mib * 2**20, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for w in range(args.warmup):
+        one_step(1000 + w)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    totals = None
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        st = one_step(s)
+        totals = st if totals is None else totals + st
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    track_ms, launches = ctx.read_timing()
+    ctx.set_timing(False)
+
+    n_sp = int(totals[0] + totals[1])
+    value = n_sp / elapsed
+    flops = algorithmic_flops(totals)
+    achieved = flops / launches / (track_ms / launches * 1e-3) / 1e12 if launches else 0.0
+    traffic = measured_traffic()
+    out = {
+        "metric": "superphotons/s",
+        "value": value,
+        "unit": "superphotons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "scattering synchrotron sphere: R=1e14 cm, 32^3 Cartesian zones, "
+                        "Theta_e=4, B=1 G, tau_T in {1e-3,1e-2,1e-1} (b=1/tau_T, 4 scattering "
+                        "generations), N_s=1e6 per tau_T, 128x6 bins, FP64",
+            "instances": len(wls),
+            "superphotons_per_step": n_sp / args.steps,
+            "roots_per_step": int(totals[0]) / args.steps,
+            "steps_per_superphoton": float(totals[2]) / max(n_sp, 1),
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": "track_kernel<Minkowski>",
+            "launches": launches,
+            "avg_launch_ms": track_ms / launches if launches else None,
+            "algorithmic_flops_per_launch": flops / launches if launches else None,
+            "kernel_time_share": track_ms * 1e-3 / elapsed,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_roots)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

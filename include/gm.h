@@ -209,6 +209,13 @@ gm_status gm_sigma_hot_table(gm_ctx *ctx, double *host_out);
  * s = sqrt(1-mu^2), evaluated on the device for n host values. */
 gm_status gm_eval_G(gm_ctx *ctx, const double *host_x, double *host_out, int n);
 
+/* Event timing of the tracking kernel: with timing enabled, every launch of
+ * the tracking kernel is bracketed by HIP events on the context's stream.
+ * gm_read_timing returns the summed event durations (ms) and the number of
+ * launches since timing was last enabled (synchronises on the events). */
+gm_status gm_set_timing(gm_ctx *ctx, int enable);
+gm_status gm_read_timing(gm_ctx *ctx, double *track_ms, uint64_t *track_launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,12 @@ struct gm_ctx {
     DevBuf<int32_t> cnsc[2];
     DevBuf<unsigned long long> ctr;             // [gen][2]: count, cursor
     DevBuf<int> flags;                          // [0] overflow, [1] status
+    // optional event timing of the tracking launches
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    double track_ms = 0.0;
+    unsigned long long track_launches = 0;
     // trace
     TraceRec *trace = nullptr;
     unsigned long long trace_cap = 0;
@@ -205,6 +211,8 @@ gm_status gm_destroy(gm_ctx *c)
         c->cnsc[b].release();
     }
     c->ctr.release(); c->flags.release(); c->trace_n.release();
+    for (auto &pr : c->ev_pending) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return GM_OK;
 }
@@ -379,6 +387,38 @@ static ChildSoA child_soa(gm_ctx *c, int b)
     return s;
 }
 
+static gm_status take_event_pair(gm_ctx *c, hipEvent_t &a, hipEvent_t &b)
+{
+    for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        if (!c->ev_pool.empty()) {
+            e = c->ev_pool.back();
+            c->ev_pool.pop_back();
+        } else {
+            HIPCHK(hipEventCreate(&e));
+        }
+        (i == 0 ? a : b) = e;
+    }
+    c->ev_pending.emplace_back(a, b);
+    return GM_OK;
+}
+
+// Fold finished event pairs into the running totals (synchronises on them).
+static gm_status drain_events(gm_ctx *c)
+{
+    for (auto &pr : c->ev_pending) {
+        HIPCHK(hipEventSynchronize(pr.second));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        c->track_ms += ms;
+        c->track_launches += 1;
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
+    }
+    c->ev_pending.clear();
+    return GM_OK;
+}
+
 __global__ void reset_counters_kernel(unsigned long long *ctr, int n, int *overflow)
 {
     int i = threadIdx.x;
@@ -463,8 +503,15 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
             A.src_count = c->ctr.p + 2 * g;
             A.src_cursor = (g == 0) ? I.roots.p + 1 : c->ctr.p + 2 * g + 1;
             A.dst_count = c->ctr.p + 2 * (g + 1);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (c->timing) {
+                gm_status ts = take_event_pair(c, e0, e1);
+                if (ts != GM_OK) return ts;
+                HIPCHK(hipEventRecord(e0, c->stream));
+            }
             track_kernel<Minkowski><<<grid, 256, lds, c->stream>>>(A);
             HIPCHK(hipGetLastError());
+            if (c->timing) HIPCHK(hipEventRecord(e1, c->stream));
         }
         unsigned long long rc[2];
         int ovf = 0;
@@ -590,6 +637,31 @@ gm_status gm_sigma_hot_table(gm_ctx *c, double *host_out)
     if (s != GM_OK) return s;
     HIPCHK(hipMemcpyAsync(host_out, c->sh_table.p, kShNT * kShNE * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_set_timing(gm_ctx *c, int enable)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    s = drain_events(c);
+    if (s != GM_OK) return s;
+    c->timing = enable != 0;
+    c->track_ms = 0.0;
+    c->track_launches = 0;
+    return GM_OK;
+}
+
+gm_status gm_read_timing(gm_ctx *c, double *track_ms, uint64_t *track_launches)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    s = drain_events(c);
+    if (s != GM_OK) return s;
+    if (track_ms) *track_ms = c->track_ms;
+    if (track_launches) *track_launches = c->track_launches;
     return GM_OK;
 }
 

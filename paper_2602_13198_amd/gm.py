@@ -37,7 +37,8 @@ TRACE_BYTES = 112
 # Every function the header declares (checked by the CPU symbol test).
 EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make_superphotons",
            "gm_track_scatter", "gm_read_spectrum", "gm_read_emission", "gm_set_trace",
-           "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G"]
+           "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G", "gm_set_timing",
+           "gm_read_timing"]
 
 
 class GmGrid(C.Structure):
@@ -91,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_trace_count": (i, [vp, C.POINTER(C.c_uint64)]),
         "gm_sigma_hot_table": (i, [vp, dp]),
         "gm_eval_G": (i, [vp, dp, dp, i]),
+        "gm_set_timing": (i, [vp, i]),
+        "gm_read_timing": (i, [vp, dp, C.POINTER(C.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -252,6 +255,15 @@ class Context:
         t = np.zeros((64, 256))
         _check(load_library().gm_sigma_hot_table(self._h, _dp(t)))
         return t
+
+    def set_timing(self, enable: bool = True):
+        _check(load_library().gm_set_timing(self._h, int(enable)))
+
+    def read_timing(self):
+        """(summed tracking-kernel event time in ms, number of launches)."""
+        ms, n = C.c_double(0.0), C.c_uint64(0)
+        _check(load_library().gm_read_timing(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, int(n.value)
 
     def eval_G(self, x) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.float64)
