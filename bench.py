@@ -122,6 +122,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-roots", type=int, default=400000,
                     help="roots per instance in the CPU oracle sample")
+    ap.add_argument("--track-waves", type=int, default=0,
+                    help="waves/SIMD variant of the tracker (2-4); 0 = autotune")
+    ap.add_argument("--refill-min", type=int, default=8)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -158,6 +161,15 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    tuning = {"track_waves": args.track_waves, "refill_min": args.refill_min, "autotuned": False}
+    if args.track_waves:
+        ctx.set_tuning(args.track_waves, args.refill_min)
+    else:
+        from paper_2602_13198_amd.autotune import autotune
+        (w_, r_), table = autotune(ctx, one_step,
+                                   log=lambda m: print(m, file=sys.stderr, flush=True))
+        tuning = {"track_waves": w_, "refill_min": r_, "autotuned": True,
+                  "candidates": [[a, b, round(c, 3), round(d, 3)] for a, b, c, d in table]}
     for w in range(args.warmup):
         one_step(1000 + w)
     torch.cuda.synchronize()
@@ -198,6 +210,7 @@ def main():
             "superphotons_per_step": n_sp / args.steps,
             "roots_per_step": int(totals[0]) / args.steps,
             "steps_per_superphoton": float(totals[2]) / max(n_sp, 1),
+            "tuning": tuning,
         },
         "roofline": {
             "bound": "alu",
@@ -206,7 +219,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "track_kernel<Minkowski>",
+            "kernel": "track_kernel_flat",
             "launches": launches,
             "avg_launch_ms": track_ms / launches if launches else None,
             "algorithmic_flops_per_launch": flops / launches if launches else None,

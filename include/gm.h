@@ -209,6 +209,12 @@ gm_status gm_sigma_hot_table(gm_ctx *ctx, double *host_out);
  * s = sqrt(1-mu^2), evaluated on the device for n host values. */
 gm_status gm_eval_G(gm_ctx *ctx, const double *host_x, double *host_out, int n);
 
+/* Scheduling of the tracking kernel (results do not depend on it):
+ * track_waves selects the compiled variant targeting 2, 3 or 4 waves per
+ * SIMD (fewer registers per lane at higher targets); refill_min (1..64) is
+ * the number of idle lanes at which a wave claims new photons. */
+gm_status gm_set_tuning(gm_ctx *ctx, int track_waves, int refill_min);
+
 /* Event timing of the tracking kernel: with timing enabled, every launch of
  * the tracking kernel is bracketed by HIP events on the context's stream.
  * gm_read_timing returns the summed event durations (ms) and the number of

@@ -486,7 +486,10 @@ static void from_frame(const double e[4][4], const double kf[4], double k[4])
 }
 
 /* Scattering event at (x*, k*): a child with weight w_child (Scattering
- * section).  Draws from the parent's stream. */
+ * section).  The child's stream is derived from the parent's stream and the
+ * parent's counter at the event; the scattering draws (electron, angles)
+ * come from the child's stream, which then continues with the child's own
+ * optical-depth draw.  The parent's stream is not advanced here. */
 static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *wk, photon *par,
                           const double xs[4], const double ks[4], double w_child,
                           const double xa[4], const double xb[4])
@@ -498,7 +501,9 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
     if (z < 0 || !(c->n_e[z] > 0.0)) z = zone_of(&c->grid, xb);
     photon ch;
     memset(&ch, 0, sizeof(ch));
-    uint32_t block_at_scatter = par->rng.block;
+    ch.rng.seed = par->rng.seed;
+    gmo_child_stream(par->rng.seed, par->rng.s, par->rng.block, ch.rng.s);
+    ch.rng.block = 0;
     double g[4][4];
     gmo_gcov(&c->grid, xs, g);
     double kchild[4];
@@ -508,7 +513,7 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
         fluid_frame(c, z, g, u, bh, &has_b);
         scatter_tetrad(g, u, bh, has_b, ks, e, &eps);
         double kf[4];
-        gmo_scatter_in_frame(&par->rng, c->theta[z], eps, NULL, NULL, kf,
+        gmo_scatter_in_frame(&ch.rng, c->theta[z], eps, NULL, NULL, kf,
                              &wk->stats[GMO_S_E_TRIALS], &wk->stats[GMO_S_ANG_TRIALS]);
         from_frame(e, kf, kchild);
     } else {
@@ -517,9 +522,6 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
     for (int m = 0; m < 4; ++m) { ch.x[m] = xs[m]; ch.k[m] = kchild[m]; }
     ch.w = ch.w_birth = w_child;
     ch.n_sc = par->n_sc + 1;
-    ch.rng.seed = par->rng.seed;
-    gmo_child_stream(par->rng.seed, par->rng.s, block_at_scatter, ch.rng.s);
-    ch.rng.block = 0;
     wk->ledger[GMO_L_E_COMPTON] += w_child * (e_inf(g, kchild) - e_inf(g, ks)) * MEC2;
     wk->stats[GMO_S_SCATTER] += 1;
     (void)tp;

@@ -96,13 +96,17 @@ struct gm_ctx {
     GCheb G{};
     ShTable sh{};
     bool sh_built = false;
-    // child queues (ping-pong) and per-generation counters
+    // photon queues (ping-pong between generations) and per-generation counters
     unsigned long long child_cap = 0;
-    DevBuf<double> cbuf[2][9];
-    DevBuf<uint32_t> cs[2][3];
-    DevBuf<int32_t> cnsc[2];
+    DevBuf<double> qd[2][13];
+    DevBuf<uint32_t> qu[2][4];
+    DevBuf<int32_t> qi[2][2];
     DevBuf<unsigned long long> ctr;             // [gen][2]: count, cursor
     DevBuf<int> flags;                          // [0] overflow, [1] status
+    // tuning of the tracking launch (waves per SIMD of the compiled variant,
+    // idle lanes before a wave claims new photons)
+    int track_waves = 2;
+    int refill_min = 8;
     // optional event timing of the tracking launches
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -206,9 +210,9 @@ gm_status gm_destroy(gm_ctx *c)
     }
     c->gcheb.release(); c->sh_table.release(); c->gl_x.release(); c->gl_w.release();
     for (int b = 0; b < 2; ++b) {
-        for (auto &d : c->cbuf[b]) d.release();
-        for (auto &d : c->cs[b]) d.release();
-        c->cnsc[b].release();
+        for (auto &d : c->qd[b]) d.release();
+        for (auto &d : c->qu[b]) d.release();
+        for (auto &d : c->qi[b]) d.release();
     }
     c->ctr.release(); c->flags.release(); c->trace_n.release();
     for (auto &pr : c->ev_pending) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
@@ -367,24 +371,27 @@ static gm_status ensure_children(gm_ctx *c, unsigned long long cap)
 {
     if (c->child_cap >= cap) return GM_OK;
     for (int b = 0; b < 2; ++b) {
-        for (auto &d : c->cbuf[b])
-            if (d.ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "child queue of %llu", cap);
-        for (auto &d : c->cs[b])
-            if (d.ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "child queue of %llu", cap);
-        if (c->cnsc[b].ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "child queue of %llu", cap);
+        for (auto &d : c->qd[b])
+            if (d.ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "photon queue of %llu", cap);
+        for (auto &d : c->qu[b])
+            if (d.ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "photon queue of %llu", cap);
+        for (auto &d : c->qi[b])
+            if (d.ensure(cap) != hipSuccess) return fail(GM_ENOMEM, "photon queue of %llu", cap);
     }
     c->child_cap = cap;
     return GM_OK;
 }
 
-static ChildSoA child_soa(gm_ctx *c, int b)
+static PhotonQ queue(gm_ctx *c, int b)
 {
-    ChildSoA s;
-    for (int m = 0; m < 4; ++m) { s.x[m] = c->cbuf[b][m].p; s.k[m] = c->cbuf[b][4 + m].p; }
-    s.w = c->cbuf[b][8].p;
-    s.s0 = c->cs[b][0].p; s.s1 = c->cs[b][1].p; s.s2 = c->cs[b][2].p;
-    s.n_sc = c->cnsc[b].p;
-    return s;
+    PhotonQ q;
+    for (int m = 0; m < 3; ++m) q.x[m] = c->qd[b][m].p;
+    for (int m = 0; m < 4; ++m) q.k[m] = c->qd[b][3 + m].p;
+    q.w = c->qd[b][7].p; q.wb = c->qd[b][8].p; q.x1 = c->qd[b][9].p;
+    q.nua = c->qd[b][10].p; q.nus = c->qd[b][11].p; q.b = c->qd[b][12].p;
+    q.s0 = c->qu[b][0].p; q.s1 = c->qu[b][1].p; q.s2 = c->qu[b][2].p; q.blk = c->qu[b][3].p;
+    q.n_sc = c->qi[b][0].p; q.zone = c->qi[b][1].p;
+    return q;
 }
 
 static gm_status take_event_pair(gm_ctx *c, hipEvent_t &a, hipEvent_t &b)
@@ -444,22 +451,30 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     I.dirty = true;
     HIPCHK(hipMemsetAsync(I.stats.p, 0, S_N * sizeof(unsigned long long), c->stream));
 
-    const size_t lds = (size_t)(L_N + S_N) * 8 + nspec * 8;
-    if (lds > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %zu bins exceeds the LDS tally", nspec / 3);
+    const size_t lds_track = (size_t)(L_N + S_N) * 8 + nspec * 8;
+    const size_t lds_small = (size_t)(L_N + S_N) * 8;
+    if (lds_track > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %zu bins exceeds the LDS tally", nspec / 3);
+    auto track_fn = c->track_waves == 4 ? track_kernel_flat<4>
+                  : c->track_waves == 3 ? track_kernel_flat<3> : track_kernel_flat<2>;
     int occ = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_kernel<Minkowski>, 256, lds));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_fn, 256, lds_track));
     occ = std::max(occ, 1);
     const int grid = c->n_cu * occ;
 
-    TrackArgs A{};
+    TArgs A{};
     A.zrec = I.zrec.p;
-    for (int j = 0; j < 3; ++j) { A.n[j] = I.grid.n[j]; A.xs[j] = I.grid.x_start[j]; A.dx[j] = I.grid.dx[j]; }
+    for (int j = 0; j < 3; ++j) {
+        A.n[j] = I.grid.n[j];
+        A.xs[j] = I.grid.x_start[j];
+        A.dx[j] = I.grid.dx[j];
+        A.inv_dx[j] = 1.0 / I.grid.dx[j];
+        A.xe[j] = I.grid.x_start[j] + I.grid.n[j] * I.grid.dx[j];
+    }
     A.C = kH * I.grid.L_unit_cm / kMeC2;
     A.inst = ii;
     A.key0 = (uint32_t)I.ep.seed;
     A.key1 = (uint32_t)(I.ep.seed >> 32);
     A.zone_of_root = I.zone_of_root.p;
-    A.n_roots = I.roots.p;
     A.lnnu_min = I.lnnu_min;
     A.lnnu_span = I.lnnu_span;
     A.n_wnodes = I.nw;
@@ -476,11 +491,9 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     A.scattering = tp->scattering;
     A.bias_mode = tp->bias_mode;
     A.n_sc_max = tp->n_sc_max;
-    A.verlet_max_it = tp->verlet_max_it;
     A.bias_value = tp->bias_value;
     A.bias_max = tp->bias_max;
     A.step_h = tp->step_h;
-    A.verlet_tol = tp->verlet_tol;
     A.roulette_frac = tp->roulette_frac;
     A.roulette_p = tp->roulette_p;
     A.max_steps = tp->max_steps;
@@ -490,18 +503,27 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     A.trace_n = c->trace_n.p;
     A.trace_cap = c->trace_cap;
     A.overflow = c->flags.p;
-    A.dst_cap = c->child_cap;
-    A.backpressure = c->child_cap / 4;
+    A.cap = c->child_cap;
+    A.refill_min = c->refill_min;
 
+    // generations 0 .. n_sc_max: only photons below the cap can scatter
     const int ngen = tp->scattering ? tp->n_sc_max + 1 : 1;
-    for (int pass = 0;; ++pass) {
+    const unsigned long long chunk = std::max<unsigned long long>(1, c->child_cap / 2);
+    for (unsigned long long start = 0; start < I.n_roots; start += chunk) {
+        const unsigned long long cnt = std::min(chunk, I.n_roots - start);
         reset_counters_kernel<<<1, 64, 0, c->stream>>>(c->ctr.p, 64, c->flags.p);
+        A.root_begin = start;
+        A.root_count = cnt;
+        A.dst = queue(c, 0);
+        A.src_count = c->ctr.p;                       // generation-0 count
+        birth_kernel<Minkowski><<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
+        HIPCHK(hipGetLastError());
         for (int g = 0; g < ngen; ++g) {
             A.gen = g;
-            A.src = child_soa(c, g & 1);
-            A.dst = child_soa(c, (g + 1) & 1);
+            A.src = queue(c, g & 1);
+            A.dst = queue(c, (g + 1) & 1);
             A.src_count = c->ctr.p + 2 * g;
-            A.src_cursor = (g == 0) ? I.roots.p + 1 : c->ctr.p + 2 * g + 1;
+            A.src_cursor = c->ctr.p + 2 * g + 1;
             A.dst_count = c->ctr.p + 2 * (g + 1);
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (c->timing) {
@@ -509,21 +531,22 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
                 if (ts != GM_OK) return ts;
                 HIPCHK(hipEventRecord(e0, c->stream));
             }
-            track_kernel<Minkowski><<<grid, 256, lds, c->stream>>>(A);
+            track_fn<<<grid, 256, lds_track, c->stream>>>(A);
             HIPCHK(hipGetLastError());
             if (c->timing) HIPCHK(hipEventRecord(e1, c->stream));
+            if (g + 1 < ngen) {
+                scatter_kernel_flat<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
+                HIPCHK(hipGetLastError());
+            }
         }
-        unsigned long long rc[2];
         int ovf = 0;
-        HIPCHK(hipMemcpyAsync(rc, I.roots.p, sizeof(rc), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(&ovf, c->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        if (ovf) return fail(GM_ENOMEM, "child queue of %llu overflowed", c->child_cap);
-        if (rc[1] >= rc[0]) break;
-        if (pass > 100000) return fail(GM_EDEVICE, "root cursor does not advance");
+        if (ovf) return fail(GM_ENOMEM, "photon queue of %llu overflowed", c->child_cap);
     }
     std::vector<unsigned long long> st(S_N);
-    HIPCHK(hipMemcpy(st.data(), I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(st.data(), I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     for (int i = 0; i < S_N; ++i) acc[i] += (long long)st[i];
     I.pending = false;
     return GM_OK;
@@ -637,6 +660,16 @@ gm_status gm_sigma_hot_table(gm_ctx *c, double *host_out)
     if (s != GM_OK) return s;
     HIPCHK(hipMemcpyAsync(host_out, c->sh_table.p, kShNT * kShNE * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_set_tuning(gm_ctx *c, int track_waves, int refill_min)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (track_waves < 2 || track_waves > 4) return fail(GM_EINVAL, "track_waves %d not in 2..4", track_waves);
+    if (refill_min < 1 || refill_min > 64) return fail(GM_EINVAL, "refill_min %d not in 1..64", refill_min);
+    c->track_waves = track_waves;
+    c->refill_min = refill_min;
     return GM_OK;
 }
 

@@ -38,9 +38,11 @@ GM_D double e_inf(const double g[4][4], const double *k)
     return -(g[0][0] * k[0] + g[0][1] * k[1] + g[0][2] * k[2] + g[0][3] * k[3]);
 }
 
-// Packed zone record (16 doubles, 128 bytes).
+// Packed zone record (16 doubles, 128 bytes).  In flat spacetime u and the
+// field direction are stored already normalised (Z_HASB = 1 when the field
+// direction exists); in curved spacetime they are stored as given.
 enum { Z_U0 = 0, Z_B0 = 4, Z_A = 8, Z_NUC = 9, Z_TH = 10, Z_NE = 11, Z_LNTH = 12, Z_BG = 13,
-       Z_STRIDE = 16 };
+       Z_HASB = 14, Z_STRIDE = 16 };
 
 // Unit fluid velocity and field direction at a point: the zone's u is
 // normalised with the local metric, the field direction projected normal
@@ -61,6 +63,14 @@ GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], doubl
 #pragma unroll
     for (int m = 0; m < 4; ++m) bh[m] = has_b ? bh[m] * inv : 0.0;
     return has_b;
+}
+
+// Flat spacetime: the normalised vectors were stored by the zone preparation.
+GM_D bool fluid_frame_flat(const double *zr, double u[4], double bh[4])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { u[m] = zr[Z_U0 + m]; bh[m] = zr[Z_B0 + m]; }
+    return zr[Z_HASB] != 0.0;
 }
 
 // Add v, made orthonormal to e[0..ne-1] (e[0] timelike), as e[ne]; false

@@ -1,23 +1,31 @@
-// gm_track.h -- the superphoton transport kernel (device side).
+// gm_track.h -- superphoton transport kernels (device side).
 //
-// One lane carries one superphoton for its whole life.  A persistent grid
-// processes one scattering generation per launch: waves claim photons from
-// the generation's source (roots, or the children written by the previous
-// generation) with one atomic per wave for all their idle lanes, and push
-// the children they create into the next generation's buffer with one
-// atomic per wave.  Tallies, ledgers and counters go to LDS and are merged
-// into HBM when the block finishes.
+// Three kernels per scattering generation, connected by photon queues in
+// structure-of-arrays form:
+//   birth_kernel    one thread per root: position, frequency and direction
+//                   sampling, tetrad, weight, opacities -> generation-0 queue;
+//   track_kernel    persistent grid, one lane per photon for its whole life:
+//                   geodesic steps, absorption, scattering decision, tally at
+//                   escape; a scattering event updates the parent and writes
+//                   the event (point, incoming wavevector, child weight and
+//                   stream) into the next generation's queue;
+//   scatter_kernel  one thread per event: electron and scattering-angle
+//                   sampling, the child's wavevector and opacities, in place.
+// Waves of the tracker claim queue entries for all their idle lanes with one
+// atomic, and reserve event slots with one atomic per wave.  Tallies,
+// ledgers and counters accumulate in LDS and are merged into HBM per block.
 #pragma once
 
 #include "gm_frame.h"
 
 namespace gm {
 
-// Child superphotons in structure-of-arrays form.
-struct ChildSoA {
-    double *x[4], *k[4], *w;
-    uint32_t *s0, *s1, *s2;
-    int32_t *n_sc;
+// Photon queue (one generation), structure of arrays.
+struct PhotonQ {
+    double *x[3], *k[4];
+    double *w, *wb, *x1, *nua, *nus, *b;
+    uint32_t *s0, *s1, *s2, *blk;
+    int32_t *n_sc, *zone;
 };
 
 struct TraceRec {
@@ -28,29 +36,26 @@ struct TraceRec {
     double x[4], k[4];
 };
 
-struct TrackArgs {
+struct TArgs {
     // instance geometry and plasma
     const double *zrec;
     int n[3];
-    double xs[3], dx[3];
+    double xs[3], dx[3], inv_dx[3], xe[3];
     double C;                      // h ell / (m_e c^2): converts d(lambda) to cm s
     int inst;
     uint32_t key0, key1;
-    // roots of the instance
+    // roots of the instance (birth kernel)
     const uint32_t *zone_of_root;
-    const unsigned long long *n_roots;
-    double lnnu_min, lnnu_span, inv_dlnw;
+    unsigned long long root_begin, root_count;
+    double lnnu_min, lnnu_span;
     int n_wnodes;
     const double *ln_w, *fmax;
     GCheb G;
-    // generation being processed
+    // queues of the generation being processed
     int gen;
-    ChildSoA src;
-    const unsigned long long *src_count;
-    unsigned long long *src_cursor;
-    ChildSoA dst;
-    unsigned long long *dst_count;
-    unsigned long long dst_cap, backpressure;
+    PhotonQ src, dst;
+    unsigned long long *src_count, *src_cursor, *dst_count;
+    unsigned long long cap;
     int *overflow;
     // tallies of the instance
     double *spec, *ledger;
@@ -58,25 +63,17 @@ struct TrackArgs {
     int n_nu, n_theta;
     double ln_nu_lo, inv_dln_nu;
     // transport parameters
-    int scattering, bias_mode, n_sc_max, verlet_max_it;
-    double bias_value, bias_max, step_h, verlet_tol, roulette_frac, roulette_p;
+    int scattering, bias_mode, n_sc_max;
+    double bias_value, bias_max, step_h, roulette_frac, roulette_p;
     long long max_steps;
     double L_unit_cm;
     ShTable sh;
+    // scheduling: claim new photons once this many lanes of a wave idle
+    int refill_min;
     // optional trace
     TraceRec *trace;
     unsigned long long *trace_n;
     unsigned long long trace_cap;
-};
-
-struct Photon {
-    double x[4], k[4];
-    double w, w_birth, x1;         // x1: remaining biased optical depth
-    double nua, nus, b;            // invariant opacities and bias at the current point
-    double acc_wabs, acc_wcap;     // weight lost to absorption / the generation cap
-    Rng rng;
-    int n_sc;
-    uint32_t steps;
 };
 
 struct Coef {
@@ -84,6 +81,7 @@ struct Coef {
     bool vacuum;
 };
 
+// Per-block accumulators in LDS.
 struct BlockAcc {
     double *spec, *ledger;
     unsigned long long *stats;
@@ -92,27 +90,52 @@ struct BlockAcc {
 GM_D void lds_add(double *p, double v) { atomicAdd(p, v); }
 GM_D void lds_inc(unsigned long long *p, unsigned long long v) { atomicAdd(p, v); }
 
-// Zone holding a Cartesian point, or -1 outside the grid (vacuum).
-GM_D int zone_cart(const TrackArgs &A, const double *x)
+GM_D BlockAcc lds_setup(double *lds, int nspec)
 {
-    int id[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        double f = floor((x[j + 1] - A.xs[j]) / A.dx[j]);
-        if (!(f >= 0.0) || f >= (double)A.n[j]) return -1;
-        id[j] = (int)f;
+    BlockAcc B;
+    B.ledger = lds;
+    B.stats = reinterpret_cast<unsigned long long *>(lds + L_N);
+    B.spec = lds + L_N + S_N;
+    for (int i = threadIdx.x; i < L_N + S_N + nspec; i += blockDim.x) lds[i] = 0.0;
+    __syncthreads();
+    return B;
+}
+
+GM_D void lds_flush(const TArgs &A, const BlockAcc &B, int nspec)
+{
+    __syncthreads();
+    for (int i = threadIdx.x; i < nspec; i += blockDim.x) {
+        double v = B.spec[i];
+        if (v != 0.0) atomicAdd(&A.spec[i], v);
     }
-    return (id[0] * A.n[1] + id[1]) * A.n[2] + id[2];
+    for (int i = threadIdx.x; i < L_N; i += blockDim.x) {
+        double v = B.ledger[i];
+        if (v != 0.0) atomicAdd(&A.ledger[i], v);
+    }
+    for (int i = threadIdx.x; i < S_N; i += blockDim.x) {
+        unsigned long long v = B.stats[i];
+        if (v) atomicAdd(&A.stats[i], v);
+    }
+}
+
+// Zone holding a Cartesian point, or -1 outside the grid (vacuum).
+GM_D int zone_cart(const TArgs &A, double x1, double x2, double x3)
+{
+    double f1 = floor((x1 - A.xs[0]) * A.inv_dx[0]);
+    double f2 = floor((x2 - A.xs[1]) * A.inv_dx[1]);
+    double f3 = floor((x3 - A.xs[2]) * A.inv_dx[2]);
+    bool in = (f1 >= 0.0) && (f1 < (double)A.n[0]) && (f2 >= 0.0) && (f2 < (double)A.n[1]) &&
+              (f3 >= 0.0) && (f3 < (double)A.n[2]);
+    return in ? ((int)f1 * A.n[1] + (int)f2) * A.n[2] + (int)f3 : -1;
 }
 
 // Invariant absorption and scattering coefficients (nu alpha) at a point
 // (Absorption and Scattering sections): alpha = j / B_nu (Kirchhoff),
 // alpha_sc = n_e sigma_h; and the bias at that point.
 template <class M>
-GM_D Coef coefficients(const TrackArgs &A, const double *x, const double *k, int n_sc)
+GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
-    int z = zone_cart(A, x);
     if (z < 0) return c;
     const double *zr = A.zrec + (size_t)z * Z_STRIDE;
     double ne = zr[Z_NE];
@@ -120,7 +143,7 @@ GM_D Coef coefficients(const TrackArgs &A, const double *x, const double *k, int
     c.vacuum = false;
     double g[4][4], u[4], bh[4];
     M::gcov(x, g);
-    bool has_b = fluid_frame(zr, g, u, bh);
+    bool has_b = fluid_frame_flat(zr, u, bh);
     double ef = -dot4(g, k, u);
     double nuf = ef * (kMeC2 / kH);
     double Az = zr[Z_A];
@@ -147,7 +170,130 @@ GM_D Coef coefficients(const TrackArgs &A, const double *x, const double *k, int
     return c;
 }
 
-GM_D void write_trace(const TrackArgs &A, const Photon &ph, int kind, int inu, int ith)
+// ---------------------------------------------------------------------------
+// Birth of root photons (Sampling procedure section): position uniform in
+// the zone, frequency by rejection against the zone's bound on dN/d ln nu,
+// direction by rejection against j(pi/2), fluid-frame tetrad, weight w(nu),
+// remaining optical depth, opacities at the birth point.
+// ---------------------------------------------------------------------------
+template <class M>
+__global__ __launch_bounds__(256) void birth_kernel(TArgs A)
+{
+    extern __shared__ double lds[];
+    const int nspec = 0;
+    BlockAcc B = lds_setup(lds, nspec);
+    unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < A.root_count) {
+        unsigned long long p = A.root_begin + q;
+        uint32_t z = A.zone_of_root[p];
+        const double *zr = A.zrec + (size_t)z * Z_STRIDE;
+        Rng rng{(uint32_t)p, (uint32_t)(p >> 32), ((uint32_t)A.inst << 8) | 1u, 0u};
+        int i3 = (int)(z % (uint32_t)A.n[2]);
+        int i2 = (int)((z / (uint32_t)A.n[2]) % (uint32_t)A.n[1]);
+        int i1 = (int)(z / ((uint32_t)A.n[2] * (uint32_t)A.n[1]));
+        double x[4];
+        x[0] = 0.0;
+        x[1] = A.xs[0] + (i1 + rng_uniform(rng, A.key0, A.key1)) * A.dx[0];
+        x[2] = A.xs[1] + (i2 + rng_uniform(rng, A.key0, A.key1)) * A.dx[1];
+        x[3] = A.xs[2] + (i3 + rng_uniform(rng, A.key0, A.key1)) * A.dx[2];
+        const double Az = zr[Z_A], nuc = zr[Z_NUC];
+        const double fm = A.fmax[z];
+        const double dlnw = A.lnnu_span / (A.n_wnodes - 1);
+        double lnnu, nu, lnw;
+        uint32_t trials = 0, over = 0;
+        for (int64_t it = 0;; ++it) {
+            lnnu = A.lnnu_min + rng_uniform(rng, A.key0, A.key1) * A.lnnu_span;
+            nu = exp(lnnu);
+            double u2 = rng_uniform(rng, A.key0, A.key1);
+            double a = (lnnu - A.lnnu_min) / dlnw;
+            int i = (int)floor(a);
+            i = max(0, min(i, A.n_wnodes - 2));
+            double f = a - i;
+            lnw = (1.0 - f) * A.ln_w[i] + f * A.ln_w[i + 1];
+            double F = 4.0 * kPi * Az * G_of_Xc(A.G, nu / nuc) / exp(lnw);
+            ++trials;
+            over += (F > fm) ? 1u : 0u;
+            if (u2 < F / fm || it >= kMaxTrials) break;
+        }
+        double jmax = Az * g_shape(nu / nuc);
+        double cth;
+        uint32_t dtr = 0;
+        for (int64_t it = 0;; ++it) {
+            cth = 2.0 * rng_uniform(rng, A.key0, A.key1) - 1.0;
+            double u4 = rng_uniform(rng, A.key0, A.key1);
+            ++dtr;
+            double s2 = 1.0 - cth * cth;
+            double j = 0.0;
+            if (s2 > 0.0) {
+                double s = sqrt(s2);
+                j = Az * s * g_shape(nu / (nuc * s));
+            }
+            if (u4 < j / jmax || it >= kMaxTrials) break;
+        }
+        double phi = 2.0 * kPi * rng_uniform(rng, A.key0, A.key1);
+        double g[4][4], u[4], bh[4], e[4][4];
+        M::gcov(x, g);
+        fluid_frame_flat(zr, u, bh);
+        emission_tetrad(g, u, bh, e);
+        double eps = kH * nu / kMeC2;
+        double sth = sqrt(1.0 - cth * cth);
+        double kf[4] = {eps, eps * sth * cos(phi), eps * sth * sin(phi), eps * cth};
+        double k[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) k[m] = kf[0] * e[0][m] + kf[1] * e[1][m] + kf[2] * e[2][m] + kf[3] * e[3][m];
+        double w = exp(lnw);
+        double x1 = -log(1.0 - rng_uniform(rng, A.key0, A.key1));
+        Coef c = coefficients<M>(A, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
+        // write generation-0 queue entry q
+        const PhotonQ &Q = A.dst;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) Q.x[m][q] = x[m + 1];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) Q.k[m][q] = k[m];
+        Q.w[q] = w; Q.wb[q] = w; Q.x1[q] = x1;
+        Q.nua[q] = c.nua; Q.nus[q] = c.nus; Q.b[q] = c.b;
+        Q.s0[q] = rng.s0; Q.s1[q] = rng.s1; Q.s2[q] = rng.s2; Q.blk[q] = rng.block;
+        Q.n_sc[q] = 0;
+        lds_add(&B.ledger[L_W_EMIT], w);
+        lds_add(&B.ledger[L_E_EMIT], w * e_inf(g, k) * kMeC2);
+        lds_inc(&B.stats[S_ROOTS], 1);
+        lds_inc(&B.stats[S_NU_TRIALS], trials);
+        if (over) lds_inc(&B.stats[S_OVERSHOOT], over);
+        lds_inc(&B.stats[S_DIR_TRIALS], dtr);
+        lds_inc(&B.stats[S_GEN0], 1);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.src_count = A.root_count;
+    lds_flush(A, B, nspec);
+}
+
+// ---------------------------------------------------------------------------
+// The tracker.
+// ---------------------------------------------------------------------------
+struct Photon {
+    double x[3], k[4];
+    double w, wb, x1;              // weight, birth weight, remaining biased depth
+    double nua, nus, b;            // opacities and bias at the current point
+    double acc_wabs, acc_wcap;     // weight lost to absorption / the generation cap
+    Rng rng;
+    int n_sc;
+    uint32_t steps;
+};
+
+GM_D void load_photon(const PhotonQ &Q, unsigned long long i, Photon &ph)
+{
+#pragma unroll
+    for (int m = 0; m < 3; ++m) ph.x[m] = Q.x[m][i];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) ph.k[m] = Q.k[m][i];
+    ph.w = Q.w[i]; ph.wb = Q.wb[i]; ph.x1 = Q.x1[i];
+    ph.nua = Q.nua[i]; ph.nus = Q.nus[i]; ph.b = Q.b[i];
+    ph.rng = Rng{Q.s0[i], Q.s1[i], Q.s2[i], Q.blk[i]};
+    ph.n_sc = Q.n_sc[i];
+    ph.steps = 0;
+    ph.acc_wabs = ph.acc_wcap = 0.0;
+}
+
+GM_D void write_trace(const TArgs &A, const Photon &ph, int kind, int inu, int ith)
 {
     if (!A.trace) return;
     unsigned long long i = atomicAdd(A.trace_n, 1ull);
@@ -155,25 +301,25 @@ GM_D void write_trace(const TrackArgs &A, const Photon &ph, int kind, int inu, i
     TraceRec &r = A.trace[i];
     r.s0 = ph.rng.s0; r.s1 = ph.rng.s1; r.s2 = ph.rng.s2;
     r.n_sc = ph.n_sc; r.kind = kind; r.i_nu = inu; r.i_theta = ith;
-    r.n_steps = ph.steps; r.w_birth = ph.w_birth; r.w_end = ph.w;
+    r.n_steps = ph.steps; r.w_birth = ph.wb; r.w_end = ph.w;
+    r.x[0] = 0.0;               // the coordinate time is not carried
 #pragma unroll
-    for (int m = 0; m < 4; ++m) { r.x[m] = ph.x[m]; r.k[m] = ph.k[m]; }
+    for (int m = 0; m < 3; ++m) r.x[m + 1] = ph.x[m];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) r.k[m] = ph.k[m];
 }
 
-// Book a finished photon: accumulated losses, end kind, trace.
-template <class M>
-GM_D void finish(const TrackArgs &A, BlockAcc &B, const Photon &ph, int kind, int inu, int ith)
+// Book a finished photon: accumulated losses, end kind, trace.  Flat
+// spacetime: the energy at infinity is k^t.
+GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind, int inu, int ith)
 {
-    double g[4][4];
-    M::gcov(ph.x, g);
-    double e = e_inf(g, ph.k) * kMeC2;
+    double e = ph.k[0] * kMeC2;
     if (ph.acc_wabs != 0.0) { lds_add(&B.ledger[L_W_ABS], ph.acc_wabs); lds_add(&B.ledger[L_E_ABS], ph.acc_wabs * e); }
     if (ph.acc_wcap != 0.0) { lds_add(&B.ledger[L_W_CAPLOSS], ph.acc_wcap); lds_add(&B.ledger[L_E_CAPLOSS], ph.acc_wcap * e); }
     double we = ph.w * e;
     switch (kind) {
     case END_ESCAPE: lds_add(&B.ledger[L_W_ESC], ph.w); lds_add(&B.ledger[L_E_ESC], we); lds_inc(&B.stats[S_ESCAPED], 1); break;
     case END_OOB: lds_add(&B.ledger[L_W_OOB], ph.w); lds_add(&B.ledger[L_E_OOB], we); lds_inc(&B.stats[S_OOB], 1); break;
-    case END_CAPTURE: lds_add(&B.ledger[L_W_CAPT], ph.w); lds_add(&B.ledger[L_E_CAPT], we); lds_inc(&B.stats[S_CAPTURED], 1); break;
     case END_STUCK: lds_add(&B.ledger[L_W_STUCK], ph.w); lds_add(&B.ledger[L_E_STUCK], we); lds_inc(&B.stats[S_STUCK], 1); break;
     default: break;
     }
@@ -182,116 +328,13 @@ GM_D void finish(const TrackArgs &A, BlockAcc &B, const Photon &ph, int kind, in
     write_trace(A, ph, kind, inu, ith);
 }
 
-// Birth of root photon p (Sampling procedure section): position uniform in
-// the zone, frequency by rejection against the zone's bound on dN/d ln nu,
-// direction by rejection against j(pi/2), fluid-frame tetrad, weight w(nu).
-template <class M>
-GM_D void birth(const TrackArgs &A, BlockAcc &B, unsigned long long p, Photon &ph)
+GM_D void tally_escape(const TArgs &A, BlockAcc &B, const Photon &ph)
 {
-    uint32_t z = A.zone_of_root[p];
-    const double *zr = A.zrec + (size_t)z * Z_STRIDE;
-    ph.rng = Rng{(uint32_t)p, (uint32_t)(p >> 32), ((uint32_t)A.inst << 8) | 1u, 0u};
-    int i3 = (int)(z % (uint32_t)A.n[2]);
-    int i2 = (int)((z / (uint32_t)A.n[2]) % (uint32_t)A.n[1]);
-    int i1 = (int)(z / ((uint32_t)A.n[2] * (uint32_t)A.n[1]));
-    ph.x[0] = 0.0;
-    ph.x[1] = A.xs[0] + (i1 + rng_uniform(ph.rng, A.key0, A.key1)) * A.dx[0];
-    ph.x[2] = A.xs[1] + (i2 + rng_uniform(ph.rng, A.key0, A.key1)) * A.dx[1];
-    ph.x[3] = A.xs[2] + (i3 + rng_uniform(ph.rng, A.key0, A.key1)) * A.dx[2];
-    const double Az = zr[Z_A], nuc = zr[Z_NUC];
-    const double fm = A.fmax[z];
-    const double dlnw = A.lnnu_span / (A.n_wnodes - 1);
-    double lnnu, nu, lnw;
-    uint32_t trials = 0, over = 0;
-    for (int64_t it = 0;; ++it) {
-        lnnu = A.lnnu_min + rng_uniform(ph.rng, A.key0, A.key1) * A.lnnu_span;
-        nu = exp(lnnu);
-        double u2 = rng_uniform(ph.rng, A.key0, A.key1);
-        double a = (lnnu - A.lnnu_min) / dlnw;
-        int i = (int)floor(a);
-        i = max(0, min(i, A.n_wnodes - 2));
-        double f = a - i;
-        lnw = (1.0 - f) * A.ln_w[i] + f * A.ln_w[i + 1];
-        double F = 4.0 * kPi * Az * G_of_Xc(A.G, nu / nuc) / exp(lnw);
-        ++trials;
-        over += (F > fm) ? 1u : 0u;
-        if (u2 < F / fm || it >= kMaxTrials) break;
-    }
-    double jmax = Az * g_shape(nu / nuc);
-    double cth;
-    uint32_t dtr = 0;
-    for (int64_t it = 0;; ++it) {
-        cth = 2.0 * rng_uniform(ph.rng, A.key0, A.key1) - 1.0;
-        double u4 = rng_uniform(ph.rng, A.key0, A.key1);
-        ++dtr;
-        double s2 = 1.0 - cth * cth;
-        double j = 0.0;
-        if (s2 > 0.0) {
-            double s = sqrt(s2);
-            j = Az * s * g_shape(nu / (nuc * s));
-        }
-        if (u4 < j / jmax || it >= kMaxTrials) break;
-    }
-    double phi = 2.0 * kPi * rng_uniform(ph.rng, A.key0, A.key1);
-    double g[4][4], u[4], bh[4], e[4][4];
-    M::gcov(ph.x, g);
-    fluid_frame(zr, g, u, bh);
-    emission_tetrad(g, u, bh, e);
-    double eps = kH * nu / kMeC2;
-    double sth = sqrt(1.0 - cth * cth);
-    double kf[4] = {eps, eps * sth * cos(phi), eps * sth * sin(phi), eps * cth};
-#pragma unroll
-    for (int m = 0; m < 4; ++m) ph.k[m] = kf[0] * e[0][m] + kf[1] * e[1][m] + kf[2] * e[2][m] + kf[3] * e[3][m];
-    ph.w = ph.w_birth = exp(lnw);
-    ph.x1 = -log(1.0 - rng_uniform(ph.rng, A.key0, A.key1));
-    ph.n_sc = 0;
-    ph.steps = 0;
-    ph.acc_wabs = ph.acc_wcap = 0.0;
-    lds_add(&B.ledger[L_W_EMIT], ph.w);
-    lds_add(&B.ledger[L_E_EMIT], ph.w * e_inf(g, ph.k) * kMeC2);
-    lds_inc(&B.stats[S_ROOTS], 1);
-    lds_inc(&B.stats[S_NU_TRIALS], trials);
-    if (over) lds_inc(&B.stats[S_OVERSHOOT], over);
-    lds_inc(&B.stats[S_DIR_TRIALS], dtr);
-    lds_inc(&B.stats[S_GEN0], 1);
-    Coef c = coefficients<M>(A, ph.x, ph.k, 0);
-    ph.nua = c.nua; ph.nus = c.nus; ph.b = c.b;
-}
-
-template <class M>
-GM_D void load_child(const TrackArgs &A, BlockAcc &B, unsigned long long i, Photon &ph)
-{
-#pragma unroll
-    for (int m = 0; m < 4; ++m) { ph.x[m] = A.src.x[m][i]; ph.k[m] = A.src.k[m][i]; }
-    ph.w = ph.w_birth = A.src.w[i];
-    ph.rng = Rng{A.src.s0[i], A.src.s1[i], A.src.s2[i], 0u};
-    ph.n_sc = A.src.n_sc[i];
-    ph.steps = 0;
-    ph.acc_wabs = ph.acc_wcap = 0.0;
-    ph.x1 = -log(1.0 - rng_uniform(ph.rng, A.key0, A.key1));
-    lds_inc(&B.stats[S_CHILDREN], 1);
-    lds_inc(&B.stats[S_GEN0 + min(ph.n_sc, 15)], 1);
-    Coef c = coefficients<M>(A, ph.x, ph.k, ph.n_sc);
-    ph.nua = c.nua; ph.nus = c.nus; ph.b = c.b;
-}
-
-// State carried from a step into the wave's scattering pass.
-struct Pending {
-    double xn[4], kn[4];
-    double f, b, tau_a;
-};
-
-// Tally an escaping photon into its (theta, nu) bin.
-template <class M>
-GM_D void tally_escape(const TrackArgs &A, BlockAcc &B, const Photon &ph)
-{
-    double g[4][4];
-    M::gcov(ph.x, g);
-    double einf = e_inf(g, ph.k);
+    double einf = ph.k[0];
     double nuinf = einf * (kMeC2 / kH);
     double fi = floor((log(nuinf) - A.ln_nu_lo) * A.inv_dln_nu);
     if (!(fi >= 0.0 && fi < (double)A.n_nu)) {
-        finish<M>(A, B, ph, END_OOB, -1, -1);
+        finish(A, B, ph, END_OOB, -1, -1);
         return;
     }
     double kk = sqrt(ph.k[1] * ph.k[1] + ph.k[2] * ph.k[2] + ph.k[3] * ph.k[3]);
@@ -304,81 +347,14 @@ GM_D void tally_escape(const TrackArgs &A, BlockAcc &B, const Photon &ph)
     lds_add(&bin[0], E);
     lds_add(&bin[1], E * E);
     lds_add(&bin[2], 1.0);
-    finish<M>(A, B, ph, END_ESCAPE, inu, ith);
+    finish(A, B, ph, END_ESCAPE, inu, ith);
 }
 
-// One transport step (geodesic section: velocity Verlet; Absorption
-// section: trapezoid optical depth; Scattering section: biased scattering
-// test).  Returns 1 when the photon scatters in this step (handled by the
-// wave's scattering pass), else 0; `alive` drops when the photon ends.
-template <class M>
-GM_D int step(const TrackArgs &A, BlockAcc &B, Photon &ph, Pending &pd, bool &alive, bool &stepped)
+// Russian roulette below roulette_frac of the birth weight.
+GM_D void roulette(const TArgs &A, BlockAcc &B, Photon &ph, bool &alive)
 {
-    stepped = false;
-    if ((long long)ph.steps >= A.max_steps) {
-        finish<M>(A, B, ph, END_STUCK, -1, -1);
-        alive = false;
-        return 0;
-    }
-    double dl = 1.0 / 0.0;
-#pragma unroll
-    for (int j = 1; j <= 3; ++j)
-        if (ph.k[j] != 0.0) dl = fmin(dl, A.dx[j - 1] / fabs(ph.k[j]));
-    dl *= A.step_h;
-    double xn[4], kn[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) { xn[m] = ph.x[m] + ph.k[m] * dl; kn[m] = ph.k[m]; }
-    Coef c1 = coefficients<M>(A, xn, kn, ph.n_sc);
-    ph.steps += 1;
-    stepped = true;
-    double tau_a = 0.5 * (ph.nua + c1.nua) * A.C * dl;
-    double tau_s = A.scattering ? 0.5 * (ph.nus + c1.nus) * A.C * dl : 0.0;
-    double b = c1.vacuum ? ph.b : c1.b;
-    if (A.scattering && ph.n_sc < A.n_sc_max && b * tau_s > ph.x1) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) { pd.xn[m] = xn[m]; pd.kn[m] = kn[m]; }
-        pd.f = ph.x1 / (b * tau_s);
-        pd.b = b;
-        pd.tau_a = tau_a;
-        return 1;
-    }
-    if (A.scattering) {
-        if (ph.n_sc < A.n_sc_max) {
-            ph.x1 -= b * tau_s;
-        } else {   // generation cap: extinction without a child
-            double wb = ph.w;
-            ph.w *= exp(-tau_s);
-            ph.acc_wcap += wb - ph.w;
-        }
-    }
-    double wb = ph.w;
-    ph.w *= exp(-tau_a);
-    ph.acc_wabs += wb - ph.w;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) { ph.x[m] = xn[m]; ph.k[m] = kn[m]; }
-    ph.nua = c1.nua; ph.nus = c1.nus; ph.b = b;
-    bool escaped = false;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        double lo = A.xs[j], hi = A.xs[j] + A.n[j] * A.dx[j];
-        escaped |= (ph.x[j + 1] < lo) || (ph.x[j + 1] >= hi);
-    }
-    if (escaped) {
-        tally_escape<M>(A, B, ph);
-        alive = false;
-    }
-    return 0;
-}
-
-// Russian roulette for low-weight photons (reading: below roulette_frac of
-// the birth weight, survive with probability roulette_p).
-template <class M>
-GM_D void roulette(const TrackArgs &A, BlockAcc &B, Photon &ph, bool &alive)
-{
-    if (!(ph.w < A.roulette_frac * ph.w_birth)) return;
-    double g[4][4];
-    M::gcov(ph.x, g);
-    double e = e_inf(g, ph.k) * kMeC2;
+    if (!(ph.w < A.roulette_frac * ph.wb)) return;
+    double e = ph.k[0] * kMeC2;
     if (rng_uniform(ph.rng, A.key0, A.key1) < A.roulette_p) {
         double gain = ph.w * (1.0 / A.roulette_p - 1.0);
         lds_add(&B.ledger[L_W_ROUL], gain);
@@ -390,56 +366,202 @@ GM_D void roulette(const TrackArgs &A, BlockAcc &B, Photon &ph, bool &alive)
         lds_add(&B.ledger[L_E_ROUL], -ph.w * e);
         lds_inc(&B.stats[S_ROUL_KILL], 1);
         ph.w = 0.0;
-        finish<M>(A, B, ph, END_ROULETTE, -1, -1);
+        finish(A, B, ph, END_ROULETTE, -1, -1);
         alive = false;
     }
 }
 
-// Scattering pass for the lanes whose step found a scattering point: the
-// child is built from the parent's stream (Scattering section), pushed
-// with one atomic per wave, and the parent continues from the scattering
-// point with weight w (1 - 1/b).
-template <class M>
-GM_D void scatter_pass(const TrackArgs &A, BlockAcc &B, Photon &ph, const Pending &pd, bool want,
-                       bool &alive)
+
+// Flat-spacetime tracker (geodesic section with Gamma = 0; Absorption and
+// Scattering sections).  Each lane evaluates the opacities at one point per
+// iteration: the end of a trial step, or -- on the iteration after a
+// scattering -- the scattering point the parent restarts from.
+template <int WAVES>
+__global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
 {
-    double xs[4], kc[4];
-    double wchild = 0.0;
-    uint32_t blk_at = 0;
-    Rng crng{0, 0, 0, 0};
-    if (want) {
-        double ks[4];
+    extern __shared__ double lds[];
+    const int nspec = A.n_theta * A.n_nu * 3;
+    BlockAcc B = lds_setup(lds, nspec);
+    const unsigned long long n_src = min(*A.src_count, A.cap);
+    Photon ph;
+    bool alive = false, exhausted = false, restart = false;
+    for (;;) {
+        uint64_t idle = __ballot(!alive);
+        int nidle = __popcll(idle);
+        if (!exhausted && (nidle >= A.refill_min || nidle == 64)) {
+            unsigned long long base = 0;
+            if (lane_id() == 0) base = atomicAdd(A.src_cursor, (unsigned long long)nidle);
+            base = bcast_u64(base, 0);
+            if (base + (unsigned long long)nidle >= n_src) exhausted = true;
+            if (!alive) {
+                unsigned long long idx = base + rank_in_mask(idle);
+                if (idx < n_src) {
+                    load_photon(A.src, idx, ph);
+                    alive = true;
+                    restart = false;
+                }
+            }
+        }
+        if (!__any(alive)) break;
+        bool scat = false;
+        double wchild = 0.0;
+        int zs = -1;
+        Rng crng{0u, 0u, 0u, 0u};
+        if (alive && !restart && (long long)ph.steps >= A.max_steps) {
+            finish(A, B, ph, END_STUCK, -1, -1);
+            alive = false;
+        }
+        if (alive) {
+            // ---- the point where the opacities are needed ----
+            double dl = 0.0;
+            double xn[3];
+            if (restart) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            xs[m] = ph.x[m] + pd.f * (pd.xn[m] - ph.x[m]);
-            ks[m] = ph.k[m] + pd.f * (pd.kn[m] - ph.k[m]);
+                for (int m = 0; m < 3; ++m) xn[m] = ph.x[m];
+            } else {
+                dl = 1.0 / 0.0;
+#pragma unroll
+                for (int j = 1; j <= 3; ++j)
+                    if (ph.k[j] != 0.0) dl = fmin(dl, A.dx[j - 1] / fabs(ph.k[j]));
+                dl *= A.step_h;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) xn[m] = ph.x[m] + ph.k[m + 1] * dl;
+            }
+            int zn = zone_cart(A, xn[0], xn[1], xn[2]);
+            double xv[4] = {0.0, xn[0], xn[1], xn[2]};
+            Coef c1 = coefficients<Minkowski>(A, zn, xv, ph.k, ph.n_sc);
+            if (restart) {
+                ph.nua = c1.nua; ph.nus = c1.nus;
+                if (!c1.vacuum) ph.b = c1.b;
+                restart = false;
+            } else {
+                ph.steps += 1;
+                // ---- optical depths by the trapezoid rule ----
+                double tau_a = 0.5 * (ph.nua + c1.nua) * A.C * dl;
+                double tau_s = A.scattering ? 0.5 * (ph.nus + c1.nus) * A.C * dl : 0.0;
+                double b = c1.vacuum ? ph.b : c1.b;
+                if (A.scattering && ph.n_sc < A.n_sc_max && b * tau_s > ph.x1) {
+                    // ---- scattering point at the fraction f of the step ----
+                    double f = ph.x1 / (b * tau_s);
+                    double xs[3];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) xs[m] = ph.x[m] + f * (xn[m] - ph.x[m]);
+                    double wbf = ph.w;
+                    ph.w *= exp(-f * tau_a);
+                    ph.acc_wabs += wbf - ph.w;
+                    wchild = ph.w / b;
+                    // plasma of the scattering point, else of the step's start, else its end
+                    zs = zone_cart(A, xs[0], xs[1], xs[2]);
+                    if (zs >= 0 && !(A.zrec[(size_t)zs * Z_STRIDE + Z_NE] > 0.0)) zs = -1;
+                    if (zs < 0) {
+                        zs = zone_cart(A, ph.x[0], ph.x[1], ph.x[2]);
+                        if (zs >= 0 && !(A.zrec[(size_t)zs * Z_STRIDE + Z_NE] > 0.0)) zs = -1;
+                    }
+                    if (zs < 0) {
+                        zs = zn;
+                        if (zs >= 0 && !(A.zrec[(size_t)zs * Z_STRIDE + Z_NE] > 0.0)) zs = -1;
+                    }
+                    crng = child_rng(ph.rng, ph.rng.block, A.key0, A.key1);
+                    // the parent continues from the scattering point; its
+                    // opacities there are evaluated on the next iteration
+                    ph.w *= (1.0 - 1.0 / b);
+                    ph.x1 = -log(1.0 - rng_uniform(ph.rng, A.key0, A.key1));
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) ph.x[m] = xs[m];
+                    restart = true;
+                    scat = true;
+                    if (b == 1.0) {    // all weight went to the child
+                        finish(A, B, ph, END_SPLIT, -1, -1);
+                        alive = false;
+                    }
+                } else {
+                    if (A.scattering) {
+                        if (ph.n_sc < A.n_sc_max) {
+                            ph.x1 -= b * tau_s;
+                        } else {   // generation cap: extinction without a child
+                            double wbc = ph.w;
+                            ph.w *= exp(-tau_s);
+                            ph.acc_wcap += wbc - ph.w;
+                        }
+                    }
+                    double wba = ph.w;
+                    ph.w *= exp(-tau_a);
+                    ph.acc_wabs += wba - ph.w;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) ph.x[m] = xn[m];
+                    ph.nua = c1.nua; ph.nus = c1.nus; ph.b = b;
+                    bool esc = false;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) esc |= (ph.x[j] < A.xs[j]) || (ph.x[j] >= A.xe[j]);
+                    if (esc) {
+                        tally_escape(A, B, ph);
+                        alive = false;
+                    }
+                }
+                if (alive) roulette(A, B, ph, alive);
+            }
         }
-        double wb = ph.w;
-        ph.w *= exp(-pd.f * pd.tau_a);
-        ph.acc_wabs += wb - ph.w;
-        wchild = ph.w / pd.b;
-        // plasma of the scattering point, else of the step's start, else its end
-        int z = zone_cart(A, xs);
-        if (z >= 0 && !(A.zrec[(size_t)z * Z_STRIDE + Z_NE] > 0.0)) z = -1;
-        if (z < 0) {
-            z = zone_cart(A, ph.x);
-            if (z >= 0 && !(A.zrec[(size_t)z * Z_STRIDE + Z_NE] > 0.0)) z = -1;
+        // ---- scattering events: one slot reservation per wave; the event
+        // holds the scattering point and the incoming wavevector (the
+        // parent's own, unchanged in flat spacetime) ----
+        uint64_t smask = __ballot(scat);
+        if (smask) {
+            unsigned long long base = 0;
+            if (lane_id() == 0) base = atomicAdd(A.dst_count, (unsigned long long)__popcll(smask));
+            base = bcast_u64(base, 0);
+            if (scat) {
+                unsigned long long i = base + rank_in_mask(smask);
+                if (i < A.cap) {
+                    const PhotonQ &Q = A.dst;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) Q.x[m][i] = ph.x[m];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) Q.k[m][i] = ph.k[m];
+                    Q.w[i] = wchild;
+                    Q.s0[i] = crng.s0; Q.s1[i] = crng.s1; Q.s2[i] = crng.s2;
+                    Q.n_sc[i] = ph.n_sc + 1;
+                    Q.zone[i] = zs;
+                } else {
+                    atomicOr(A.overflow, 1);
+                }
+            }
         }
-        if (z < 0) {
-            z = zone_cart(A, pd.xn);
-            if (z >= 0 && !(A.zrec[(size_t)z * Z_STRIDE + Z_NE] > 0.0)) z = -1;
-        }
-        blk_at = ph.rng.block;
+    }
+    lds_flush(A, B, nspec);
+}
+
+// ---------------------------------------------------------------------------
+// Scattering events -> child photons (Scattering section), one thread per
+// event of the generation just tracked.  Draws come from the child's stream
+// (derived from the parent's stream and counter at the event): electron
+// (gamma, mu), electron azimuth, scattering angle and azimuth, then the
+// child's own optical-depth draw.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs A)
+{
+    extern __shared__ double lds[];
+    BlockAcc B = lds_setup(lds, 0);
+    const unsigned long long n = min(*A.dst_count, A.cap);
+    const PhotonQ &Q = A.dst;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        double x[4] = {0.0, Q.x[0][i], Q.x[1][i], Q.x[2][i]};
+        double ks[4] = {Q.k[0][i], Q.k[1][i], Q.k[2][i], Q.k[3][i]};
+        int z = Q.zone[i];
+        int n_sc = Q.n_sc[i];
+        double wchild = Q.w[i];
+        Rng r{Q.s0[i], Q.s1[i], Q.s2[i], 0u};
         double g[4][4];
-        M::gcov(xs, g);
+        Minkowski::gcov(x, g);
+        double kc[4];
         if (z >= 0) {
             const double *zr = A.zrec + (size_t)z * Z_STRIDE;
             double u[4], bh[4], e[4][4];
-            bool has_b = fluid_frame(zr, g, u, bh);
+            bool has_b = fluid_frame_flat(zr, u, bh);
             double eps = scatter_tetrad(g, u, bh, has_b, ks, e);
             double kf[4];
             ScatterCount cnt{0, 0};
-            scatter_in_frame(ph.rng, A.key0, A.key1, zr[Z_TH], eps, kf, cnt);
+            scatter_in_frame(r, A.key0, A.key1, zr[Z_TH], eps, kf, cnt);
 #pragma unroll
             for (int m = 0; m < 4; ++m) kc[m] = kf[0] * e[0][m] + kf[1] * e[1][m] + kf[2] * e[2][m] + kf[3] * e[3][m];
             lds_inc(&B.stats[S_E_TRIALS], cnt.e_trials);
@@ -450,102 +572,18 @@ GM_D void scatter_pass(const TrackArgs &A, BlockAcc &B, Photon &ph, const Pendin
         }
         lds_add(&B.ledger[L_E_COMPTON], wchild * (e_inf(g, kc) - e_inf(g, ks)) * kMeC2);
         lds_inc(&B.stats[S_SCATTER], 1);
-        crng = child_rng(ph.rng, blk_at, A.key0, A.key1);
-        // the parent continues from the scattering point
-        ph.w *= (1.0 - 1.0 / pd.b);
-        ph.x1 = -log(1.0 - rng_uniform(ph.rng, A.key0, A.key1));
+        lds_inc(&B.stats[S_CHILDREN], 1);
+        lds_inc(&B.stats[S_GEN0 + min(n_sc, 15)], 1);
+        double x1 = -log(1.0 - rng_uniform(r, A.key0, A.key1));
+        Coef c = coefficients<Minkowski>(A, zone_cart(A, x[1], x[2], x[3]), x, kc, n_sc);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) { ph.x[m] = xs[m]; ph.k[m] = ks[m]; }
-        Coef c0 = coefficients<M>(A, ph.x, ph.k, ph.n_sc);
-        ph.nua = c0.nua; ph.nus = c0.nus;
-        if (!c0.vacuum) ph.b = c0.b;
-        if (pd.b == 1.0) {
-            finish<M>(A, B, ph, END_SPLIT, -1, -1);
-            alive = false;
-        }
+        for (int m = 0; m < 4; ++m) Q.k[m][i] = kc[m];
+        Q.wb[i] = wchild;
+        Q.x1[i] = x1;
+        Q.nua[i] = c.nua; Q.nus[i] = c.nus; Q.b[i] = c.b;
+        Q.blk[i] = r.block;
     }
-    // one slot reservation per wave
-    uint64_t mask = __ballot(want);
-    unsigned long long base = 0;
-    if (lane_id() == 0) base = atomicAdd(A.dst_count, (unsigned long long)__popcll(mask));
-    base = bcast_u64(base, 0);
-    if (want) {
-        unsigned long long i = base + rank_in_mask(mask);
-        if (i < A.dst_cap) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) { A.dst.x[m][i] = xs[m]; A.dst.k[m][i] = kc[m]; }
-            A.dst.w[i] = wchild;
-            A.dst.s0[i] = crng.s0; A.dst.s1[i] = crng.s1; A.dst.s2[i] = crng.s2;
-            A.dst.n_sc[i] = ph.n_sc + 1;
-        } else {
-            atomicOr(A.overflow, 1);
-        }
-    }
-}
-
-constexpr int kRefillMin = 16;   // claim new photons once this many lanes idle
-
-template <class M>
-__global__ __launch_bounds__(256) void track_kernel(TrackArgs A)
-{
-    extern __shared__ double lds[];
-    BlockAcc B;
-    B.ledger = lds;
-    B.stats = reinterpret_cast<unsigned long long *>(lds + L_N);
-    B.spec = lds + L_N + S_N;
-    const int nspec = A.n_theta * A.n_nu * 3;
-    for (int i = threadIdx.x; i < L_N + S_N + nspec; i += blockDim.x) lds[i] = 0.0;
-    __syncthreads();
-
-    // a generation never reads past its queue's capacity (an overflowed
-    // count is reported to the host through A.overflow)
-    const unsigned long long n_src =
-        (A.gen == 0) ? *A.n_roots : min(*A.src_count, A.dst_cap);
-    Photon ph;
-    Pending pd;
-    bool alive = false, exhausted = false;
-    for (;;) {
-        uint64_t idle = __ballot(!alive);
-        int nidle = __popcll(idle);
-        if (!exhausted && (nidle >= kRefillMin || nidle == 64)) {
-            unsigned long long base = 0;
-            if (lane_id() == 0) {
-                bool hold = (A.gen == 0) &&
-                            (__hip_atomic_load(A.dst_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= A.backpressure);
-                base = hold ? ~0ull : atomicAdd(A.src_cursor, (unsigned long long)nidle);
-            }
-            base = bcast_u64(base, 0);
-            if (base == ~0ull || base + (unsigned long long)nidle >= n_src) exhausted = true;
-            if (base != ~0ull && !alive) {
-                unsigned long long idx = base + rank_in_mask(idle);
-                if (idx < n_src) {
-                    alive = true;
-                    if (A.gen == 0) birth<M>(A, B, idx, ph);
-                    else load_child<M>(A, B, idx, ph);
-                }
-            }
-        }
-        if (!__any(alive)) break;
-        bool stepped = false;
-        int want = 0;
-        if (alive) want = step<M>(A, B, ph, pd, alive, stepped);
-        if (__any(want)) scatter_pass<M>(A, B, ph, pd, want != 0, alive);
-        if (alive && stepped) roulette<M>(A, B, ph, alive);
-    }
-
-    __syncthreads();
-    for (int i = threadIdx.x; i < nspec; i += blockDim.x) {
-        double v = B.spec[i];
-        if (v != 0.0) atomicAdd(&A.spec[i], v);
-    }
-    for (int i = threadIdx.x; i < L_N; i += blockDim.x) {
-        double v = B.ledger[i];
-        if (v != 0.0) atomicAdd(&A.ledger[i], v);
-    }
-    for (int i = threadIdx.x; i < S_N; i += blockDim.x) {
-        unsigned long long v = B.stats[i];
-        if (v) atomicAdd(&A.stats[i], v);
-    }
+    lds_flush(A, B, 0);
 }
 
 }  // namespace gm

@@ -38,7 +38,7 @@ TRACE_BYTES = 112
 EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make_superphotons",
            "gm_track_scatter", "gm_read_spectrum", "gm_read_emission", "gm_set_trace",
            "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G", "gm_set_timing",
-           "gm_read_timing"]
+           "gm_read_timing", "gm_set_tuning"]
 
 
 class GmGrid(C.Structure):
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_eval_G": (i, [vp, dp, dp, i]),
         "gm_set_timing": (i, [vp, i]),
         "gm_read_timing": (i, [vp, dp, C.POINTER(C.c_uint64)]),
+        "gm_set_tuning": (i, [vp, i, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -255,6 +256,9 @@ class Context:
         t = np.zeros((64, 256))
         _check(load_library().gm_sigma_hot_table(self._h, _dp(t)))
         return t
+
+    def set_tuning(self, track_waves: int = 2, refill_min: int = 8):
+        _check(load_library().gm_set_tuning(self._h, int(track_waves), int(refill_min)))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().gm_set_timing(self._h, int(enable)))

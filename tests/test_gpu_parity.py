@@ -171,3 +171,26 @@ def test_errors_are_reported(gm):
     st = c.track_scatter(wl.track)
     assert st[0] == 0
     c.close()
+
+
+def test_histories_do_not_depend_on_tuning(gm):
+    """Every compiled tracker variant and refill threshold gives the same
+    photon histories (bitwise) and the same tallies up to summation order."""
+    wl = W.scattering_sphere(0.1, n_target=5000, seed=21)
+    ref = None
+    for waves, refill in ((2, 8), (3, 1), (4, 64), (2, 32)):
+        c = gm.Context(0)
+        c.set_tuning(waves, refill)
+        c.load_zones(wl)
+        c.make_superphotons(wl.emit)
+        c.set_trace(200000)
+        c.track_scatter(wl.track)
+        spec, led = c.read_spectrum()
+        tr = np.sort(c.read_trace(), order=["s2", "s1", "s0"])
+        c.close()
+        if ref is None:
+            ref = (tr, spec, led)
+            continue
+        assert np.array_equal(tr.view(np.uint8), ref[0].view(np.uint8)), (waves, refill)
+        np.testing.assert_allclose(spec, ref[1], rtol=1e-12, atol=0)
+        np.testing.assert_allclose(led, ref[2], rtol=1e-12, atol=0)
