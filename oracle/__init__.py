@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
             "gmo_gcon": (None, [C.POINTER(Grid), dp, dp]),
             "gmo_christoffel": (None, [C.POINTER(Grid), dp, dp]),
             "gmo_sqrt_neg_g": (d, [C.POINTER(Grid), dp]),
+            "gmo_integrate_geodesic": (i, [C.POINTER(Grid), dp, dp, d, d, i, i, d, d, dp]),
             "gmo_create": (C.c_void_p, []), "gmo_destroy": (None, [C.c_void_p]),
             "gmo_load_zones": (i, [C.c_void_p, C.POINTER(Grid), C.POINTER(Zones)]),
             "gmo_make_superphotons": (i, [C.c_void_p, C.POINTER(EmitParams),
@@ -259,6 +260,18 @@ def sqrt_neg_g(grid: dict, x):
     G = make_grid(grid)
     xx = np.ascontiguousarray(x, dtype=np.float64)
     return lib().gmo_sqrt_neg_g(C.byref(G), _dp(xx))
+
+
+def integrate_geodesic(grid: dict, x0, k0, h=0.5, tol=1e-3, max_it=8, n=10000, r_min=0.0,
+                       r_max=1e300):
+    """States (x, k) after each step: array [steps, 8]."""
+    G = make_grid(grid)
+    x = np.ascontiguousarray(x0, dtype=np.float64)
+    k = np.ascontiguousarray(k0, dtype=np.float64)
+    out = np.zeros((n, 8))
+    m = lib().gmo_integrate_geodesic(C.byref(G), _dp(x), _dp(k), h, tol, max_it, n, r_min, r_max,
+                                     _dp(out))
+    return out[:m]
 
 
 # ---------------------------------------------------------------------------

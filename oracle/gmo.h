@@ -176,6 +176,13 @@ double gmo_sqrt_neg_g(const gmo_grid *grid, const double x[4]);
 double gmo_r_of_x1(const gmo_grid *grid, double x1);
 double gmo_th_of_x2(const gmo_grid *grid, double x2);
 
+/* Integrate a bare null geodesic with the transport's step rule (factor h)
+ * and Verlet integrator; out receives n rows (x[4], k[4]).  Stops early when
+ * r leaves [r_min, r_max] (KS).  Returns the rows written. */
+int    gmo_integrate_geodesic(const gmo_grid *grid, const double x0[4], const double k0[4],
+                              double h, double tol, int max_it, int n, double r_min,
+                              double r_max, double *out);
+
 /* ---- the method, as a context --------------------------------------- */
 typedef struct gmo_ctx gmo_ctx;
 

@@ -445,10 +445,10 @@ static void coefficients(const gmo_ctx *c, const gmo_track_params *tp, const dou
     out->b = b;
 }
 
-static void accel(const gmo_ctx *c, const double x[4], const double k[4], double a[4])
+static void accel_at(const gmo_grid *grid, const double x[4], const double k[4], double a[4])
 {
     double G[4][4][4];
-    gmo_christoffel(&c->grid, x, G);
+    gmo_christoffel(grid, x, G);
     for (int m = 0; m < 4; ++m) {
         double s = 0.0;
         for (int p = 0; p < 4; ++p)
@@ -528,6 +528,113 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
     push_child(wk, &ch);
 }
 
+/* Step size (reading; the paper names only "the step size"):
+ * Cartesian: h * min_j dx^j/|k^j| (h = 0.25 keeps a step within a quarter
+ * zone); KS: h / max_j (|k^j|/s^j) with s = (dx1, dx2, min(dx3, pi dx2)) --
+ * the azimuth is resolved at least as finely as the polar angle, also on
+ * axisymmetric grids with a single 2 pi zone -- and at most half the
+ * coordinate distance to the horizon when moving inward. */
+static double step_size(const gmo_grid *G, double h, const double x[4], const double k[4])
+{
+    double dl;
+    if (G->metric != GMO_METRIC_KS_MKS) {
+        dl = INFINITY;
+        for (int j = 1; j <= 3; ++j)
+            if (k[j] != 0.0) {
+                double t = G->dx[j - 1] / fabs(k[j]);
+                if (t < dl) dl = t;
+            }
+        return dl * h;
+    }
+    double sc[3] = {G->dx[0], G->dx[1], fmin(G->dx[2], M_PI * G->dx[1])};
+    double m = 0.0;
+    for (int j = 1; j <= 3; ++j) {
+        double t = fabs(k[j]) / sc[j - 1];
+        if (t > m) m = t;
+    }
+    dl = h / m;
+    if (k[1] < 0.0) {
+        double r = exp(x[1]);
+        double lim = 0.5 * (r - horizon_r(G)) / (r * fabs(k[1]));
+        if (lim < dl) dl = lim;
+    }
+    return dl;
+}
+
+/* Velocity Verlet with iterated corrector (geodesic section,
+ * eq:predicted_wavevector and eq:calculated_wavevector): predictor
+ * x' = x + k dl + a dl^2/2 (the printed line lacks dl^2; reading), k_p = k + a dl;
+ * Gamma at x' once; repeat a' = -Gamma k_p k_p, k' = k + (a + a') dl/2,
+ * error = sum|k' - k_p| / sum|k'|, k_p = k', until error < tol or max_it.
+ * Returns the number of corrector passes. */
+static int verlet(const gmo_grid *G, double tol, int max_it, const double x[4], const double k[4],
+                  const double a[4], double dl, double xn[4], double kn[4], double an[4])
+{
+    double kp[4];
+    for (int m = 0; m < 4; ++m) {
+        xn[m] = x[m] + k[m] * dl + 0.5 * a[m] * dl * dl;
+        kp[m] = k[m] + a[m] * dl;
+    }
+    double Gm[4][4][4];
+    gmo_christoffel(G, xn, Gm);
+    int it;
+    for (it = 1;; ++it) {
+        for (int m = 0; m < 4; ++m) {
+            double s = 0.0;
+            for (int p = 0; p < 4; ++p)
+                for (int q = 0; q < 4; ++q) s += Gm[m][p][q] * kp[p] * kp[q];
+            an[m] = -s;
+        }
+        double num = 0.0, den = 0.0;
+        for (int m = 0; m < 4; ++m) {
+            kn[m] = k[m] + 0.5 * (a[m] + an[m]) * dl;
+            num += fabs(kn[m] - kp[m]);
+            den += fabs(kn[m]);
+        }
+        for (int m = 0; m < 4; ++m) kp[m] = kn[m];
+        if (num / (den + 1e-300) < tol || it >= max_it) break;
+    }
+    return it;
+}
+
+/* Reflection through the pole of the modified coordinates (reading). */
+static void pole_reflect(double xn[4], double kn[4], double an[4])
+{
+    if (xn[2] < 0.0 || xn[2] > 1.0) {
+        xn[2] = (xn[2] < 0.0) ? -xn[2] : 2.0 - xn[2];
+        xn[3] += M_PI;
+        kn[2] = -kn[2];
+        an[2] = -an[2];
+    }
+}
+
+/* Integrate a bare null geodesic (no plasma) with the transport's step rule
+ * and integrator for n steps or until r leaves [r_min, r_max]; writes the
+ * states (x, k) after every step into out[n][8].  Returns the steps taken.
+ * Used by the geodesic-invariant pins. */
+int gmo_integrate_geodesic(const gmo_grid *G, const double x0[4], const double k0[4], double h,
+                           double tol, int max_it, int n, double r_min, double r_max, double *out)
+{
+    double x[4], k[4], a[4];
+    memcpy(x, x0, sizeof(x));
+    memcpy(k, k0, sizeof(k));
+    accel_at(G, x, k, a);
+    int s;
+    for (s = 0; s < n; ++s) {
+        double dl = step_size(G, h, x, k);
+        double xn[4], kn[4], an[4];
+        verlet(G, tol, max_it, x, k, a, dl, xn, kn, an);
+        if (G->metric == GMO_METRIC_KS_MKS) pole_reflect(xn, kn, an);
+        memcpy(x, xn, sizeof(x)); memcpy(k, kn, sizeof(k)); memcpy(a, an, sizeof(a));
+        for (int m = 0; m < 4; ++m) { out[8 * s + m] = x[m]; out[8 * s + 4 + m] = k[m]; }
+        if (G->metric == GMO_METRIC_KS_MKS) {
+            double r = exp(x[1]);
+            if (r < r_min || r > r_max) { ++s; break; }
+        }
+    }
+    return s;
+}
+
 /* Run one photon (root already born or child) to termination. */
 static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk, photon *ph)
 {
@@ -541,7 +648,7 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
         /* child: its own stream starts with its optical-depth draw */
         ph->x1 = -log(1.0 - gmo_rng_next(&ph->rng));
     }
-    accel(c, ph->x, ph->k, ph->a);
+    accel_at(&c->grid, ph->x, ph->k, ph->a);
     coefficients(c, tp, ph->x, ph->k, ph->n_sc, &c0);
     ph->nua = c0.nua; ph->nus = c0.nus; ph->b = c0.b;
     int gen = ph->n_sc < GMO_MAX_GEN ? ph->n_sc : GMO_MAX_GEN - 1;
@@ -556,62 +663,10 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
             record_end(c, wk, ph, GMO_END_STUCK, -1, -1);
             return;
         }
-        /* ---- step size (reading) ---- */
-        double dl;
-        if (!ks_metric) {
-            dl = INFINITY;
-            for (int j = 1; j <= 3; ++j)
-                if (ph->k[j] != 0.0) {
-                    double t = G->dx[j - 1] / fabs(ph->k[j]);
-                    if (t < dl) dl = t;
-                }
-            dl *= tp->step_h;
-        } else {
-            double m = 0.0;
-            for (int j = 1; j <= 3; ++j) {
-                double t = fabs(ph->k[j]) / G->dx[j - 1];
-                if (t > m) m = t;
-            }
-            dl = tp->step_h / m;
-            if (ph->k[1] < 0.0) {
-                double r = exp(ph->x[1]);
-                double lim = 0.5 * (r - rh) / (r * fabs(ph->k[1]));
-                if (lim < dl) dl = lim;
-            }
-        }
-        /* ---- velocity Verlet with iterated corrector ---- */
-        double xn[4], kp[4], kn[4], an[4];
-        for (int m = 0; m < 4; ++m) {
-            xn[m] = ph->x[m] + ph->k[m] * dl + 0.5 * ph->a[m] * dl * dl;
-            kp[m] = ph->k[m] + ph->a[m] * dl;
-        }
-        double Gm[4][4][4];
-        gmo_christoffel(G, xn, Gm);
-        for (int it = 1;; ++it) {
-            for (int m = 0; m < 4; ++m) {
-                double s = 0.0;
-                for (int p = 0; p < 4; ++p)
-                    for (int q = 0; q < 4; ++q) s += Gm[m][p][q] * kp[p] * kp[q];
-                an[m] = -s;
-            }
-            double num = 0.0, den = 0.0;
-            for (int m = 0; m < 4; ++m) {
-                kn[m] = ph->k[m] + 0.5 * (ph->a[m] + an[m]) * dl;
-                num += fabs(kn[m] - kp[m]);
-                den += fabs(kn[m]);
-            }
-            for (int m = 0; m < 4; ++m) kp[m] = kn[m];
-            wk->stats[GMO_S_VERLET_IT] += 1;
-            if (num / (den + 1e-300) < tp->verlet_tol || it >= tp->verlet_max_it) break;
-        }
-        if (ks_metric) {   /* pole reflection (reading) */
-            if (xn[2] < 0.0 || xn[2] > 1.0) {
-                xn[2] = (xn[2] < 0.0) ? -xn[2] : 2.0 - xn[2];
-                xn[3] += M_PI;
-                kn[2] = -kn[2];
-                an[2] = -an[2];
-            }
-        }
+        double dl = step_size(G, tp->step_h, ph->x, ph->k);
+        double xn[4], kn[4], an[4];
+        wk->stats[GMO_S_VERLET_IT] += verlet(G, tp->verlet_tol, tp->verlet_max_it, ph->x, ph->k, ph->a, dl, xn, kn, an);
+        if (ks_metric) pole_reflect(xn, kn, an);
         coef c1;
         coefficients(c, tp, xn, kn, ph->n_sc, &c1);
         ph->steps += 1;
@@ -641,7 +696,7 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
             ph->w *= (1.0 - 1.0 / b);
             ph->x1 = -log(1.0 - gmo_rng_next(&ph->rng));
             for (int m = 0; m < 4; ++m) { ph->x[m] = xs[m]; ph->k[m] = ks[m]; }
-            accel(c, ph->x, ph->k, ph->a);
+            accel_at(&c->grid, ph->x, ph->k, ph->a);
             coefficients(c, tp, ph->x, ph->k, ph->n_sc, &c0);
             ph->nua = c0.nua; ph->nus = c0.nus;
             if (!c0.vacuum) ph->b = c0.b;

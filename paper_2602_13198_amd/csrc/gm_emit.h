@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
         raw[Z_U0 + m] = P.ucon[(size_t)m * P.nz + z];
         raw[Z_B0 + m] = P.bcon[(size_t)m * P.nz + z];
     }
-    raw[Z_BG] = B;
+    raw[Z_HASB] = (B > 0.0) ? 1.0 : 0.0;
     // flat metric: normalise u and project/normalise the field direction once
     double g[4][4], u[4], bh[4];
     Minkowski::gcov(nullptr, g);
@@ -39,13 +39,14 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
     for (int m = 0; m < 4; ++m) { r[Z_U0 + m] = u[m]; r[Z_B0 + m] = bh[m]; }
     r[Z_HASB] = has_b ? 1.0 : 0.0;
     double A = emis_coef(ne, th, B);
+    double nuc = nu_crit(th, B);
     r[Z_A] = A;
-    r[Z_NUC] = nu_crit(th, B);
+    r[Z_NUC] = nuc;
     r[Z_TH] = th;
     r[Z_NE] = ne;
     r[Z_LNTH] = th > 0.0 ? log(th) : 0.0;
-    r[Z_BG] = B;
-    r[15] = 0.0;
+    r[Z_INVTH] = th > 0.0 ? 1.0 / th : 0.0;
+    r[Z_INVNUC] = nuc > 0.0 ? 1.0 / nuc : 0.0;
     P.vol[z] = 1.0 * P.dx[0] * P.dx[1] * P.dx[2] * P.L3;   // flat: sqrt(-g) = 1
     P.emits[z] = (A > 0.0) ? 1 : 0;
 }

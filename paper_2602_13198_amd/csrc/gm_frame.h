@@ -38,15 +38,18 @@ GM_D double e_inf(const double g[4][4], const double *k)
     return -(g[0][0] * k[0] + g[0][1] * k[1] + g[0][2] * k[2] + g[0][3] * k[3]);
 }
 
-// Packed zone record (16 doubles, 128 bytes).  In flat spacetime u and the
-// field direction are stored already normalised (Z_HASB = 1 when the field
-// direction exists); in curved spacetime they are stored as given.
-enum { Z_U0 = 0, Z_B0 = 4, Z_A = 8, Z_NUC = 9, Z_TH = 10, Z_NE = 11, Z_LNTH = 12, Z_BG = 13,
-       Z_HASB = 14, Z_STRIDE = 16 };
+// Packed zone record (16 doubles, 128 bytes): u (4), field direction (4),
+// emission coefficient A, nu_c, Theta_e, n_e, ln Theta_e, 1/Theta_e, field
+// flag (1 when B > 0 and the direction exists), 1/nu_c.  In flat spacetime u
+// and the field direction are stored already normalised; in curved
+// spacetime they are stored as given and normalised at each point.
+enum { Z_U0 = 0, Z_B0 = 4, Z_A = 8, Z_NUC = 9, Z_TH = 10, Z_NE = 11, Z_LNTH = 12, Z_INVTH = 13,
+       Z_HASB = 14, Z_INVNUC = 15, Z_STRIDE = 16 };
 
 // Unit fluid velocity and field direction at a point: the zone's u is
 // normalised with the local metric, the field direction projected normal
-// to u and normalised (absent when B = 0 or degenerate).
+// to u and normalised (absent when the zone has no field or it is
+// degenerate here).
 GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], double bh[4])
 {
 #pragma unroll
@@ -58,7 +61,7 @@ GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], doubl
 #pragma unroll
     for (int m = 0; m < 4; ++m) bh[m] += bu * u[m];
     double bb = dot4(g, bh, bh);
-    bool has_b = (bb > 0.0) && (zr[Z_BG] > 0.0);
+    bool has_b = (bb > 0.0) && (zr[Z_HASB] != 0.0);
     double inv = has_b ? 1.0 / sqrt(bb) : 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) bh[m] = has_b ? bh[m] * inv : 0.0;

@@ -145,26 +145,28 @@ GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, 
     M::gcov(x, g);
     bool has_b = fluid_frame_flat(zr, u, bh);
     double ef = -dot4(g, k, u);
+    double inv_ef = 1.0 / ef;
     double nuf = ef * (kMeC2 / kH);
     double Az = zr[Z_A];
-    double th = zr[Z_TH];
     if (has_b && Az > 0.0) {
-        double cth = dot4(g, k, bh) / ef;
+        double cth = dot4(g, k, bh) * inv_ef;
         cth = fmin(fmax(cth, -1.0), 1.0);
         double s2 = 1.0 - cth * cth;
         if (s2 > 0.0) {
-            double s = sqrt(s2);
-            double j = Az * s * g_shape(nuf / (zr[Z_NUC] * s));
+            double rs = rsqrt(s2);                      // 1 / sin(theta)
+            double s = s2 * rs;
+            double j = Az * s * g_shape(nuf * zr[Z_INVNUC] * rs);
             if (j > 0.0) {
-                double alpha = j * expm1(ef / th) / (2.0 * kH * nuf * nuf * nuf / (kC * kC));
-                c.nua = nuf * alpha;
+                // nu alpha = j (e^{h nu / kT} - 1) c^2 / (2 h nu^2), Kirchhoff
+                double inv_nu = inv_ef * (kH / kMeC2);
+                c.nua = j * expm1(ef * zr[Z_INVTH]) * (kC * kC / (2.0 * kH)) * inv_nu * inv_nu;
             }
         }
     }
     if (A.scattering) c.nus = nuf * ne * kSigT * sigma_hot(A.sh, zr[Z_LNTH], ef);
     double b;
     if (A.bias_mode == 0) b = A.bias_value;
-    else if (A.bias_mode == 1) b = A.bias_value * th * th;
+    else if (A.bias_mode == 1) b = A.bias_value * zr[Z_TH] * zr[Z_TH];
     else b = (double)((n_sc + 1) * (n_sc + 1)) / (ne * kSigT * A.bias_value * A.L_unit_cm);
     c.b = fmin(fmax(b, 1.0), A.bias_max);
     return c;
@@ -309,11 +311,29 @@ GM_D void write_trace(const TArgs &A, const Photon &ph, int kind, int inu, int i
     for (int m = 0; m < 4; ++m) r.k[m] = ph.k[m];
 }
 
-// Book a finished photon: accumulated losses, end kind, trace.  Flat
-// spacetime: the energy at infinity is k^t.
-GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind, int inu, int ith)
+// Book a finished photon: tally (escape), accumulated losses, end kind,
+// trace.  Flat spacetime: the energy at infinity is k^t.
+GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind)
 {
     double e = ph.k[0] * kMeC2;
+    int inu = -1, ith = -1;
+    if (kind == END_ESCAPE) {
+        double nuinf = ph.k[0] * (kMeC2 / kH);
+        double fi = floor((log(nuinf) - A.ln_nu_lo) * A.inv_dln_nu);
+        if (!(fi >= 0.0 && fi < (double)A.n_nu)) {
+            kind = END_OOB;
+        } else {
+            double kk = sqrt(ph.k[1] * ph.k[1] + ph.k[2] * ph.k[2] + ph.k[3] * ph.k[3]);
+            double th = acos(ph.k[3] / kk);
+            ith = max(0, min((int)floor(th * A.n_theta / kPi), A.n_theta - 1));
+            inu = (int)fi;
+            double E = ph.w * e;
+            double *bin = B.spec + ((size_t)ith * A.n_nu + inu) * 3;
+            lds_add(&bin[0], E);
+            lds_add(&bin[1], E * E);
+            lds_add(&bin[2], 1.0);
+        }
+    }
     if (ph.acc_wabs != 0.0) { lds_add(&B.ledger[L_W_ABS], ph.acc_wabs); lds_add(&B.ledger[L_E_ABS], ph.acc_wabs * e); }
     if (ph.acc_wcap != 0.0) { lds_add(&B.ledger[L_W_CAPLOSS], ph.acc_wcap); lds_add(&B.ledger[L_E_CAPLOSS], ph.acc_wcap * e); }
     double we = ph.w * e;
@@ -328,54 +348,13 @@ GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind, int in
     write_trace(A, ph, kind, inu, ith);
 }
 
-GM_D void tally_escape(const TArgs &A, BlockAcc &B, const Photon &ph)
-{
-    double einf = ph.k[0];
-    double nuinf = einf * (kMeC2 / kH);
-    double fi = floor((log(nuinf) - A.ln_nu_lo) * A.inv_dln_nu);
-    if (!(fi >= 0.0 && fi < (double)A.n_nu)) {
-        finish(A, B, ph, END_OOB, -1, -1);
-        return;
-    }
-    double kk = sqrt(ph.k[1] * ph.k[1] + ph.k[2] * ph.k[2] + ph.k[3] * ph.k[3]);
-    double th = acos(ph.k[3] / kk);
-    int ith = (int)floor(th * A.n_theta / kPi);
-    ith = max(0, min(ith, A.n_theta - 1));
-    int inu = (int)fi;
-    double E = ph.w * einf * kMeC2;
-    double *bin = B.spec + ((size_t)ith * A.n_nu + inu) * 3;
-    lds_add(&bin[0], E);
-    lds_add(&bin[1], E * E);
-    lds_add(&bin[2], 1.0);
-    finish(A, B, ph, END_ESCAPE, inu, ith);
-}
-
-// Russian roulette below roulette_frac of the birth weight.
-GM_D void roulette(const TArgs &A, BlockAcc &B, Photon &ph, bool &alive)
-{
-    if (!(ph.w < A.roulette_frac * ph.wb)) return;
-    double e = ph.k[0] * kMeC2;
-    if (rng_uniform(ph.rng, A.key0, A.key1) < A.roulette_p) {
-        double gain = ph.w * (1.0 / A.roulette_p - 1.0);
-        lds_add(&B.ledger[L_W_ROUL], gain);
-        lds_add(&B.ledger[L_E_ROUL], gain * e);
-        ph.w /= A.roulette_p;
-        lds_inc(&B.stats[S_ROUL_SURVIVE], 1);
-    } else {
-        lds_add(&B.ledger[L_W_ROUL], -ph.w);
-        lds_add(&B.ledger[L_E_ROUL], -ph.w * e);
-        lds_inc(&B.stats[S_ROUL_KILL], 1);
-        ph.w = 0.0;
-        finish(A, B, ph, END_ROULETTE, -1, -1);
-        alive = false;
-    }
-}
-
-
 // Flat-spacetime tracker (geodesic section with Gamma = 0; Absorption and
 // Scattering sections).  Each lane evaluates the opacities at one point per
 // iteration: the end of a trial step, or -- on the iteration after a
-// scattering -- the scattering point the parent restarts from.
+// scattering -- the scattering point the parent restarts from.  A photon
+// that ends keeps its state in the idle lane; its bookkeeping (tally,
+// ledger, trace) runs in the wave's next refill pass together with the
+// other lanes that ended, instead of diverging from the stepping lanes.
 template <int WAVES>
 __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
 {
@@ -385,20 +364,27 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
     const unsigned long long n_src = min(*A.src_count, A.cap);
     Photon ph;
     bool alive = false, exhausted = false, restart = false;
+    int ended = 0;                          // end kind awaiting bookkeeping
     for (;;) {
         uint64_t idle = __ballot(!alive);
         int nidle = __popcll(idle);
-        if (!exhausted && (nidle >= A.refill_min || nidle == 64)) {
-            unsigned long long base = 0;
-            if (lane_id() == 0) base = atomicAdd(A.src_cursor, (unsigned long long)nidle);
-            base = bcast_u64(base, 0);
-            if (base + (unsigned long long)nidle >= n_src) exhausted = true;
-            if (!alive) {
-                unsigned long long idx = base + rank_in_mask(idle);
-                if (idx < n_src) {
-                    load_photon(A.src, idx, ph);
-                    alive = true;
-                    restart = false;
+        if (nidle >= A.refill_min || nidle == 64) {
+            if (ended) {
+                finish(A, B, ph, ended);
+                ended = 0;
+            }
+            if (!exhausted) {
+                unsigned long long base = 0;
+                if (lane_id() == 0) base = atomicAdd(A.src_cursor, (unsigned long long)nidle);
+                base = bcast_u64(base, 0);
+                if (base + (unsigned long long)nidle >= n_src) exhausted = true;
+                if (!alive) {
+                    unsigned long long idx = base + rank_in_mask(idle);
+                    if (idx < n_src) {
+                        load_photon(A.src, idx, ph);
+                        alive = true;
+                        restart = false;
+                    }
                 }
             }
         }
@@ -408,7 +394,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
         int zs = -1;
         Rng crng{0u, 0u, 0u, 0u};
         if (alive && !restart && (long long)ph.steps >= A.max_steps) {
-            finish(A, B, ph, END_STUCK, -1, -1);
+            ended = END_STUCK;
             alive = false;
         }
         if (alive) {
@@ -419,11 +405,10 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
 #pragma unroll
                 for (int m = 0; m < 3; ++m) xn[m] = ph.x[m];
             } else {
-                dl = 1.0 / 0.0;
-#pragma unroll
-                for (int j = 1; j <= 3; ++j)
-                    if (ph.k[j] != 0.0) dl = fmin(dl, A.dx[j - 1] / fabs(ph.k[j]));
-                dl *= A.step_h;
+                // step: step_h times the smallest zone-crossing parameter
+                double rate = fmax(fmax(fabs(ph.k[1]) * A.inv_dx[0], fabs(ph.k[2]) * A.inv_dx[1]),
+                                   fabs(ph.k[3]) * A.inv_dx[2]);
+                dl = A.step_h / rate;
 #pragma unroll
                 for (int m = 0; m < 3; ++m) xn[m] = ph.x[m] + ph.k[m + 1] * dl;
             }
@@ -471,7 +456,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
                     restart = true;
                     scat = true;
                     if (b == 1.0) {    // all weight went to the child
-                        finish(A, B, ph, END_SPLIT, -1, -1);
+                        ended = END_SPLIT;
                         alive = false;
                     }
                 } else {
@@ -494,11 +479,28 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
 #pragma unroll
                     for (int j = 0; j < 3; ++j) esc |= (ph.x[j] < A.xs[j]) || (ph.x[j] >= A.xe[j]);
                     if (esc) {
-                        tally_escape(A, B, ph);
+                        ended = END_ESCAPE;
                         alive = false;
                     }
                 }
-                if (alive) roulette(A, B, ph, alive);
+                // ---- Russian roulette below roulette_frac of the birth weight ----
+                if (alive && ph.w < A.roulette_frac * ph.wb) {
+                    double e = ph.k[0] * kMeC2;
+                    if (rng_uniform(ph.rng, A.key0, A.key1) < A.roulette_p) {
+                        double gain = ph.w * (1.0 / A.roulette_p - 1.0);
+                        lds_add(&B.ledger[L_W_ROUL], gain);
+                        lds_add(&B.ledger[L_E_ROUL], gain * e);
+                        ph.w /= A.roulette_p;
+                        lds_inc(&B.stats[S_ROUL_SURVIVE], 1);
+                    } else {
+                        lds_add(&B.ledger[L_W_ROUL], -ph.w);
+                        lds_add(&B.ledger[L_E_ROUL], -ph.w * e);
+                        lds_inc(&B.stats[S_ROUL_KILL], 1);
+                        ph.w = 0.0;
+                        ended = END_ROULETTE;
+                        alive = false;
+                    }
+                }
             }
         }
         // ---- scattering events: one slot reservation per wave; the event
@@ -527,6 +529,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
             }
         }
     }
+    if (ended) finish(A, B, ph, ended);
     lds_flush(A, B, nspec);
 }
 
