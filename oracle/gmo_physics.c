@@ -233,19 +233,31 @@ double gmo_jnu(double n_e, double theta_e, double B, double nu, double cos_th)
 
 /* Angle integral: int j dOmega = 2 pi A int_{-1}^{1} s g(X_c/s) dmu
  * = 4 pi A G(X_c), G(X_c) = int_0^1 s g(X_c/s) dmu, s = sqrt(1-mu^2).
- * With mu = sin(phi): G = int_0^{pi/2} cos^2(phi) g(X_c / cos(phi)) dphi. */
-static double G_integrand(double phi, void *ctx)
+ * With mu = sin(phi): G = int_0^{pi/2} cos^2(phi) g(X_c / cos(phi)) dphi.
+ * The integrand peaks at phi = 0, where it equals g(X_c); it is integrated
+ * as g(X_c) times the ratio g(X_c/c)/g(X_c) written out,
+ *   [(X/c)^{1/2} + 2^{11/12}(X/c)^{1/6}]^2 / [X^{1/2} + 2^{11/12} X^{1/6}]^2
+ *     * exp(-X^{1/3} (c^{-1/3} - 1)),
+ * which stays of order one where g itself is subnormal (X_c near 4e8). */
+static double G_ratio_integrand(double phi, void *ctx)
 {
     double Xc = *(double *)ctx;
     double c = cos(phi);
     if (!(c > 0.0)) return 0.0;
-    return c * c * gmo_g_of_X(Xc / c);
+    const double k = pow(2.0, 11.0 / 12.0);
+    double X = Xc / c;
+    double num = pow(X, 0.5) + k * pow(X, 1.0 / 6.0);
+    double den = pow(Xc, 0.5) + k * pow(Xc, 1.0 / 6.0);
+    double e = exp(-pow(Xc, 1.0 / 3.0) * (pow(c, -1.0 / 3.0) - 1.0));
+    return c * c * (num / den) * (num / den) * e;
 }
 
 double gmo_G_of_Xc(double Xc)
 {
-    if (!(Xc > 0.0)) return 0.0;
-    return gmo_quad(G_integrand, &Xc, 0.0, 0.5 * M_PI, 1e-13);
+    if (!(Xc > 0.0) || isinf(Xc)) return 0.0;
+    double g0 = gmo_g_of_X(Xc);
+    if (g0 == 0.0) return 0.0;
+    return g0 * gmo_quad(G_ratio_integrand, &Xc, 0.0, 0.5 * M_PI, 1e-13);
 }
 
 double gmo_Jnu(double n_e, double theta_e, double B, double nu)

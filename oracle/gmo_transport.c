@@ -180,15 +180,22 @@ static void emission_tetrad(const double g[4][4], const double u[4], const doubl
     memcpy(e[3], t[1], sizeof(double) * 4);
 }
 
-/* Scattering tetrad: e0 = u, e1 along the photon's fluid-frame direction,
- * e2 from the field direction (else coordinate 1, 2, 3), e3 from the first
- * coordinate direction that is not degenerate (reading). */
+/* Scattering tetrad by Gram-Schmidt (Scattering section): e0 = u, e1 the
+ * photon's direction in the fluid frame -- k with its projection on u
+ * removed, divided by its own norm (equal to the fluid-frame energy only
+ * while k is exactly null; along an integrated path it is null to the
+ * integrator's accuracy) -- e2 from the field direction (else coordinate 1,
+ * 2, 3), e3 from the first coordinate direction that is not degenerate
+ * (reading). */
 static void scatter_tetrad(const double g[4][4], const double u[4], const double bh[4], int has_b,
                            const double k[4], double e[4][4], double *eps)
 {
     memcpy(e[0], u, sizeof(double) * 4);
     double ep = -dot4(g, k, u);
-    for (int m = 0; m < 4; ++m) e[1][m] = (k[m] - ep * u[m]) / ep;
+    double v[4];
+    for (int m = 0; m < 4; ++m) v[m] = k[m] - ep * u[m];
+    double nv = sqrt(dot4(g, v, v));
+    for (int m = 0; m < 4; ++m) e[1][m] = v[m] / nv;
     int n = 2;
     if (has_b) n += gs_add(g, e, n, bh);
     for (int j = 1; j <= 3 && n < 4; ++j) {
@@ -532,8 +539,10 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
  * Cartesian: h * min_j dx^j/|k^j| (h = 0.25 keeps a step within a quarter
  * zone); KS: h / max_j (|k^j|/s^j) with s = (dx1, dx2, min(dx3, pi dx2)) --
  * the azimuth is resolved at least as finely as the polar angle, also on
- * axisymmetric grids with a single 2 pi zone -- and at most half the
- * coordinate distance to the horizon when moving inward. */
+ * axisymmetric grids with a single 2 pi zone -- at most half the coordinate
+ * distance to the horizon when moving inward, and at most a tenth of the x2
+ * distance to the nearer pole (k^phi grows like 1/sin^2 theta there; a
+ * longer step leaves the corrector without a fixed point). */
 static double step_size(const gmo_grid *G, double h, const double x[4], const double k[4])
 {
     double dl;
@@ -558,6 +567,10 @@ static double step_size(const gmo_grid *G, double h, const double x[4], const do
         double lim = 0.5 * (r - horizon_r(G)) / (r * fabs(k[1]));
         if (lim < dl) dl = lim;
     }
+    double dp = fmin(x[2], 1.0 - x[2]);
+    if (dp < 1e-9) dp = 1e-9;
+    double lim_p = 0.1 * dp / fabs(k[2]);      /* +inf when k^2 = 0 */
+    if (lim_p < dl) dl = lim_p;
     return dl;
 }
 
@@ -679,12 +692,13 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
         double e_old = e_inf(g, ph->k);
 
         if (tp->scattering && ph->n_sc < tp->n_sc_max && b * tau_s > ph->x1) {
+            /* the scattering point: the same integrator advanced over the
+             * fraction f of the step from its start (reading) */
             double f = ph->x1 / (b * tau_s);
-            double xs[4], ks[4];
-            for (int m = 0; m < 4; ++m) {
-                xs[m] = ph->x[m] + f * (xn[m] - ph->x[m]);
-                ks[m] = ph->k[m] + f * (kn[m] - ph->k[m]);
-            }
+            double xs[4], ks[4], as[4];
+            wk->stats[GMO_S_VERLET_IT] += verlet(G, tp->verlet_tol, tp->verlet_max_it, ph->x, ph->k,
+                                                 ph->a, f * dl, xs, ks, as);
+            if (ks_metric) pole_reflect(xs, ks, as);
             double wb = ph->w;
             ph->w *= exp(-f * tau_a);
             wk->ledger[GMO_L_W_ABS] += wb - ph->w;

@@ -137,3 +137,118 @@ def scattering_sphere(tau_T: float = 0.1, n_target=1e6, seed=0, n=32, instance=0
     wl.emit["instance"] = int(instance)
     wl.meta["tau_T"] = tau_T
     return wl
+
+
+# ---------------------------------------------------------------------------
+# Kerr accretion torus (stands in for the GRMHD snapshot of the paper's GRMHD
+# test section)
+# ---------------------------------------------------------------------------
+def _fm_lnh(r, th, a, l):
+    """Fishbone-Moncrief enthalpy of a constant-angular-momentum torus
+    (Boyer-Lindquist r, theta; up to an additive constant)."""
+    s2 = np.sin(th) ** 2
+    S = r * r + a * a * np.cos(th) ** 2
+    D = r * r - 2 * r + a * a
+    A = (r * r + a * a) ** 2 - D * a * a * s2
+    q = np.sqrt(1 + 4 * l * l * S * S * D / (A * A * s2))
+    return 0.5 * np.log((1 + q) / (S * D / A)) - 0.5 * q - 2 * a * r * l / A
+
+
+def _fm_angular_momentum(a, r_max):
+    """The l that puts the pressure maximum at r_max on the equator."""
+    def dlnh(l, h=1e-4):
+        return (_fm_lnh(r_max + h, np.pi / 2, a, l) - _fm_lnh(r_max - h, np.pi / 2, a, l)) / (2 * h)
+    lo, hi = 1.0, 20.0
+    flo = dlnh(lo)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        fm = dlnh(mid)
+        if (fm > 0) == (flo > 0):
+            lo, flo = mid, fm
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def torus(n1=256, n2=128, n3=1, a=0.9375, h_slope=0.3, r_in=6.0, r_max=12.0, gamma_ad=13.0 / 9.0,
+          beta=100.0, R_high=40.0, R_low=1.0, M_bh_sun=6.5e9, M_unit=1e27, perturb=0.05,
+          perturb_seed=1, n_target=1e7, seed=3, nu_min=1e8, nu_max=1e16, r_record=1000.0,
+          theta_floor=1e-2, name="kerr_torus", **track_kw) -> Workload:
+    """Fishbone-Moncrief-shaped torus on a modified Kerr-Schild grid
+    (x1 = ln r over [ln(0.9 r_h), ln r_record], theta = pi x2 +
+    (1-h)/2 sin(2 pi x2), n3 azimuthal zones).
+
+    Density and internal energy follow the FM enthalpy (polytrope
+    p = K rho^gamma, both normalised to the density maximum) times seeded
+    log-normal factors exp(s Z - s^2/2).  The fluid rotates on circles with
+    angular velocity 1/(R^1.5 + a), R = r sin(theta); ucon gives only the
+    direction (1, 0, 0, Omega) and each consumer normalises it with its own
+    metric.  The field direction follows a single poloidal loop
+    A_phi ~ max(rho/rho_max - 0.2, 0); its strength is set from a uniform
+    plasma beta: B^2/(8 pi) = p_gas / beta.  Electron temperature from the
+    R-beta prescription Theta_e = (m_p/m_e)(gamma-1)(u/rho)/(1 + R),
+    R = (R_high beta^2 + R_low)/(1 + beta^2), floored at theta_floor.  Units: ell = r_g = G M/c^2,
+    rho_unit = M_unit / ell^3.
+
+    Transport defaults: scattering bias b = 1e3 Theta_e^2 (the paper's
+    Theta_e^2 form; its coefficient 96e4 belongs to a hotter, thinner
+    snapshot and here would give b tau_T ~ 300, an exponential cascade of
+    generations) and a step factor of half a zone, meant for the full
+    256x128 grid: on coarser test grids scale step_h down in proportion."""
+    rh = 1.0 + math.sqrt(1.0 - a * a)
+    x1a, x1b = math.log(0.9 * rh), math.log(r_record)
+    dx = [(x1b - x1a) / n1, 1.0 / n2, 2.0 * math.pi / n3]
+    x1 = x1a + (np.arange(n1) + 0.5) * dx[0]
+    x2 = (np.arange(n2) + 0.5) * dx[1]
+    r = np.exp(x1)[:, None]
+    th = (np.pi * x2 + 0.5 * (1 - h_slope) * np.sin(2 * np.pi * x2))[None, :]
+    l = _fm_angular_momentum(a, r_max)
+    with np.errstate(invalid="ignore", divide="ignore"):      # no torus inside the horizon
+        lnh = _fm_lnh(r, th, a, l) - _fm_lnh(r_in, np.pi / 2, a, l)
+    lnh = np.nan_to_num(lnh, nan=-1.0)
+    inside = (lnh > 0) & (r >= r_in)
+    hh = np.where(inside, np.exp(np.where(inside, lnh, 0.0)), 1.0)
+    kappa = 1e-3
+    rho = np.where(inside, ((hh - 1) * (gamma_ad - 1) / (kappa * gamma_ad)) ** (1 / (gamma_ad - 1)), 0.0)
+    uu = kappa * rho ** gamma_ad / (gamma_ad - 1)
+    rmax = rho.max()
+    rho, uu = rho / rmax, uu / rmax
+    # vector potential and poloidal field direction (finite differences in code coordinates)
+    Aphi = np.maximum(rho - 0.2, 0.0)
+    dA1 = np.gradient(Aphi, dx[0], axis=0)
+    dA2 = np.gradient(Aphi, dx[1], axis=1)
+    rng = np.random.Generator(np.random.Philox(perturb_seed))
+    shape = (n1, n2, n3)
+    rho3 = np.repeat(rho[:, :, None], n3, axis=2) * np.exp(perturb * rng.standard_normal(shape) - perturb ** 2 / 2)
+    uu3 = np.repeat(uu[:, :, None], n3, axis=2) * np.exp(perturb * rng.standard_normal(shape) - perturb ** 2 / 2)
+    L = G_NEWTON * M_bh_sun * M_SUN / C_LIGHT ** 2
+    rho_unit = M_unit / L ** 3
+    n_e = rho3 * rho_unit / M_P
+    p_gas = (gamma_ad - 1) * uu3 * rho_unit * C_LIGHT ** 2
+    B = np.sqrt(8 * math.pi * p_gas / beta)
+    R = (R_high * beta ** 2 + R_low) / (1 + beta ** 2)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        theta_e = np.where(rho3 > 0, (M_P / M_E) * (gamma_ad - 1) * uu3 / rho3 / (1 + R), 0.0)
+    # floor: below ~1e-3 the thermal normalisation K2(1/Theta) underflows
+    theta_e = np.where(rho3 > 0, np.maximum(theta_e, theta_floor), 0.0)
+    has_field = (np.repeat((np.abs(dA1) + np.abs(dA2))[:, :, None], n3, axis=2) > 0)
+    B = np.where(has_field, B, 0.0)
+    Rc = r * np.sin(th)
+    Omega = 1.0 / (Rc ** 1.5 + a)
+    nz = n1 * n2 * n3
+    ucon = np.zeros((4, nz))
+    ucon[0] = 1.0
+    ucon[3] = np.repeat(Omega[:, :, None], n3, axis=2).reshape(-1)
+    bcon = np.zeros((4, nz))
+    bcon[1] = np.repeat(-dA2[:, :, None], n3, axis=2).reshape(-1)
+    bcon[2] = np.repeat(dA1[:, :, None], n3, axis=2).reshape(-1)
+    grid = dict(metric=METRIC_KS_MKS, n=[n1, n2, n3], x_start=[x1a, 0.0, 0.0], dx=dx, a_spin=a,
+                h_slope=h_slope, L_unit_cm=L, r_record=r_record)
+    emit = dict(n_target=float(n_target), nu_min=nu_min, nu_max=nu_max, n_wnodes=257,
+                w_floor_rel=1e-30, seed=int(seed), instance=0)
+    tk = dict(scattering=1, bias_mode=BIAS_THETA2, bias_value=1e3, bias_max=1e6, n_sc_max=4,
+              step_h=0.5, n_nu=200, nu_lo=1e8, nu_hi=1e24, n_theta=6)
+    tk.update(track_kw)
+    return Workload(name, grid, n_e.reshape(-1), theta_e.reshape(-1), B.reshape(-1), ucon, bcon,
+                    emit, default_track(**tk),
+                    meta=dict(l=l, rho_unit=rho_unit, M_unit=M_unit, r_h=rh))
