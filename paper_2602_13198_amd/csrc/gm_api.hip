@@ -13,6 +13,7 @@
 #include "gm_emit.h"
 #include "gm_host_tables.h"
 #include "gm_track.h"
+#include "gm_track_ks.h"
 
 using namespace gm;
 
@@ -225,12 +226,21 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
 {
     if (!c || !g || !z) return fail(GM_EINVAL, "NULL argument");
     if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
-    if (g->metric != GM_METRIC_MINKOWSKI_CART)
-        return fail(GM_EUNSUPPORTED, "metric %d not built into this library", g->metric);
+    if (g->metric != GM_METRIC_MINKOWSKI_CART && g->metric != GM_METRIC_KS_MKS)
+        return fail(GM_EINVAL, "unknown metric %d", g->metric);
     for (int j = 0; j < 3; ++j)
         if (g->n[j] < 1 || !(g->dx[j] > 0.0) || !std::isfinite(g->x_start[j]))
             return fail(GM_EINVAL, "grid axis %d", j);
     if (!(g->L_unit_cm > 0.0)) return fail(GM_EINVAL, "L_unit_cm must be > 0");
+    const bool kerr = g->metric == GM_METRIC_KS_MKS;
+    if (kerr) {
+        if (!(std::fabs(g->a_spin) < 1.0)) return fail(GM_EINVAL, "spin |a| must be < 1");
+        if (!(g->h_slope > 0.0 && g->h_slope <= 1.0)) return fail(GM_EINVAL, "h_slope must be in (0, 1]");
+        if (g->x_start[1] < 0.0 || g->x_start[1] + g->n[1] * g->dx[1] > 1.0 + 1e-12)
+            return fail(GM_EINVAL, "x2 range must lie in [0, 1]");
+        if (!(g->r_record > std::exp(g->x_start[0])))
+            return fail(GM_EINVAL, "r_record must exceed the inner radius");
+    }
     long long nzl = (long long)g->n[0] * g->n[1] * g->n[2];
     if (nzl > (1ll << 31) - 1) return fail(GM_EINVAL, "too many zones");
     int nz = (int)nzl;
@@ -248,6 +258,20 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
                 return fail(GM_EINVAL, "zone %d: bad n_e/B/theta", i);
             if (ne > 0.0 && !(th > 0.0)) return fail(GM_EINVAL, "zone %d: n_e > 0 needs theta_e > 0", i);
             if (ne > 0.0 && !(z->ucon[i] > 0.0)) return fail(GM_EINVAL, "zone %d: u^t must be > 0", i);
+            if (ne > 0.0 && kerr) {
+                // the fluid velocity must be timelike at the zone centre
+                int i2 = (i / g->n[2]) % g->n[1], i1 = i / (g->n[2] * g->n[1]);
+                KMetric K;
+                kerr_metric<false>(g->a_spin, g->h_slope, g->x_start[0] + (i1 + 0.5) * g->dx[0],
+                                   g->x_start[1] + (i2 + 0.5) * g->dx[1], K);
+                double gm4[4][4], u[4];
+                kerr_full(K, gm4);
+                for (int m = 0; m < 4; ++m) u[m] = z->ucon[(size_t)m * nz + i];
+                double uu = 0.0;
+                for (int m = 0; m < 4; ++m)
+                    for (int n = 0; n < 4; ++n) uu += gm4[m][n] * u[m] * u[n];
+                if (!(uu < 0.0)) return fail(GM_EINVAL, "zone %d: u is not timelike", i);
+            }
         }
     }
     Instance &I = c->inst[instance];
@@ -276,6 +300,10 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
     for (int j = 0; j < 3; ++j) { P.n[j] = g->n[j]; P.xs[j] = g->x_start[j]; P.dx[j] = g->dx[j]; }
     P.L3 = g->L_unit_cm * g->L_unit_cm * g->L_unit_cm;
     P.nz = nz;
+    P.metric = g->metric;
+    P.a_spin = g->a_spin;
+    P.h_slope = g->h_slope;
+    P.r_h = kerr_horizon(g->a_spin);
     zone_prep_kernel<<<(nz + 255) / 256, 256, 0, c->stream>>>(P);
     hipError_t e = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(c->stream);     // staging buffers are freed next
@@ -454,8 +482,11 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     const size_t lds_track = (size_t)(L_N + S_N) * 8 + nspec * 8;
     const size_t lds_small = (size_t)(L_N + S_N) * 8;
     if (lds_track > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %zu bins exceeds the LDS tally", nspec / 3);
-    auto track_fn = c->track_waves == 4 ? track_kernel_flat<4>
-                  : c->track_waves == 3 ? track_kernel_flat<3> : track_kernel_flat<2>;
+    const bool kerr = I.grid.metric == GM_METRIC_KS_MKS;
+    auto track_fn = kerr ? (c->track_waves == 4 ? track_kernel_ks<4>
+                            : c->track_waves == 3 ? track_kernel_ks<3> : track_kernel_ks<2>)
+                         : (c->track_waves == 4 ? track_kernel_flat<4>
+                            : c->track_waves == 3 ? track_kernel_flat<3> : track_kernel_flat<2>);
     int occ = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_fn, 256, lds_track));
     occ = std::max(occ, 1);
@@ -505,6 +536,16 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     A.overflow = c->flags.p;
     A.cap = c->child_cap;
     A.refill_min = c->refill_min;
+    A.a_spin = I.grid.a_spin;
+    A.h_slope = I.grid.h_slope;
+    A.r_h = kerr_horizon(I.grid.a_spin);
+    A.r_capture = A.r_h * (1.0 + tp->horizon_eps);
+    A.r_record = I.grid.r_record;
+    A.verlet_tol = tp->verlet_tol;
+    A.verlet_max_it = tp->verlet_max_it;
+    A.inv_sc[0] = 1.0 / I.grid.dx[0];
+    A.inv_sc[1] = 1.0 / I.grid.dx[1];
+    A.inv_sc[2] = 1.0 / std::min(I.grid.dx[2], kPi * I.grid.dx[1]);
 
     // generations 0 .. n_sc_max: only photons below the cap can scatter
     const int ngen = tp->scattering ? tp->n_sc_max + 1 : 1;
@@ -516,7 +557,10 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
         A.root_count = cnt;
         A.dst = queue(c, 0);
         A.src_count = c->ctr.p;                       // generation-0 count
-        birth_kernel<Minkowski><<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
+        if (kerr)
+            birth_kernel<KerrMKS><<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
+        else
+            birth_kernel<Minkowski><<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
         HIPCHK(hipGetLastError());
         for (int g = 0; g < ngen; ++g) {
             A.gen = g;
@@ -535,7 +579,10 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
             HIPCHK(hipGetLastError());
             if (c->timing) HIPCHK(hipEventRecord(e1, c->stream));
             if (g + 1 < ngen) {
-                scatter_kernel_flat<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
+                if (kerr)
+                    scatter_kernel_ks<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
+                else
+                    scatter_kernel_flat<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
                 HIPCHK(hipGetLastError());
             }
         }

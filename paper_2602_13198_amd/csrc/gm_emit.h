@@ -2,6 +2,7 @@
 #pragma once
 
 #include "gm_frame.h"
+#include "gm_kerr.h"
 
 namespace gm {
 
@@ -16,6 +17,8 @@ struct PrepArgs {
     double xs[3], dx[3];
     double L3;
     int nz;
+    int metric;                  // 0 flat Cartesian, 1 Kerr (modified Kerr-Schild)
+    double a_spin, h_slope, r_h;
 };
 
 __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
@@ -31,13 +34,30 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
         raw[Z_B0 + m] = P.bcon[(size_t)m * P.nz + z];
     }
     raw[Z_HASB] = (B > 0.0) ? 1.0 : 0.0;
-    // flat metric: normalise u and project/normalise the field direction once
-    double g[4][4], u[4], bh[4];
-    Minkowski::gcov(nullptr, g);
-    bool has_b = fluid_frame(raw, g, u, bh);
+    double sqrt_g = 1.0;
+    bool inside = false;
+    if (P.metric == 0) {
+        // flat metric: normalise u and project/normalise the field direction once
+        double g[4][4], u[4], bh[4];
+        Minkowski::gcov(nullptr, g);
+        bool has_b = fluid_frame(raw, g, u, bh);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) { r[Z_U0 + m] = u[m]; r[Z_B0 + m] = bh[m]; }
-    r[Z_HASB] = has_b ? 1.0 : 0.0;
+        for (int m = 0; m < 4; ++m) { r[Z_U0 + m] = u[m]; r[Z_B0 + m] = bh[m]; }
+        r[Z_HASB] = has_b ? 1.0 : 0.0;
+    } else {
+        // Kerr: u and the field direction are normalised with the metric at
+        // each point of use; the volume uses sqrt(-g) at the zone centre and
+        // zones centred inside the horizon do not emit
+#pragma unroll
+        for (int m = 0; m < 8; ++m) r[m] = raw[m];
+        r[Z_HASB] = raw[Z_HASB];
+        int i3 = z % P.n[2], i2 = (z / P.n[2]) % P.n[1], i1 = z / (P.n[2] * P.n[1]);
+        double xc1 = P.xs[0] + (i1 + 0.5) * P.dx[0];
+        double xc2 = P.xs[1] + (i2 + 0.5) * P.dx[1];
+        (void)i3;
+        sqrt_g = kerr_sqrt_neg_g(P.a_spin, P.h_slope, xc1, xc2);
+        inside = exp(xc1) < P.r_h;
+    }
     double A = emis_coef(ne, th, B);
     double nuc = nu_crit(th, B);
     r[Z_A] = A;
@@ -47,8 +67,8 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
     r[Z_LNTH] = th > 0.0 ? log(th) : 0.0;
     r[Z_INVTH] = th > 0.0 ? 1.0 / th : 0.0;
     r[Z_INVNUC] = nuc > 0.0 ? 1.0 / nuc : 0.0;
-    P.vol[z] = 1.0 * P.dx[0] * P.dx[1] * P.dx[2] * P.L3;   // flat: sqrt(-g) = 1
-    P.emits[z] = (A > 0.0) ? 1 : 0;
+    P.vol[z] = sqrt_g * P.dx[0] * P.dx[1] * P.dx[2] * P.L3;
+    P.emits[z] = (A > 0.0 && !inside) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -116,15 +116,23 @@ GM_D void emission_tetrad(const double g[4][4], const double u[4], const double 
     }
 }
 
-// Scattering tetrad: e0 = u, e1 along the photon's fluid-frame direction,
-// e2 from the field direction (else coordinate 1, 2, 3), e3 from the next
-// non-degenerate coordinate direction.  Returns the fluid-frame energy.
+// Scattering tetrad (Gram-Schmidt): e0 = u; e1 the photon's fluid-frame
+// direction, i.e. k minus its projection on u, normalised by its own norm
+// (which equals the fluid-frame energy only for an exactly null k; an
+// integrated k is null only to the integrator's accuracy, and a unit e1
+// keeps the frame orthonormal regardless); e2 from the field direction
+// (else coordinate 1, 2, 3), e3 from the next non-degenerate coordinate
+// direction.  Returns the fluid-frame energy -k.u.
 GM_D double scatter_tetrad(const double g[4][4], const double u[4], const double bh[4], bool has_b,
                            const double k[4], double e[4][4])
 {
     double ep = -dot4(g, k, u);
+    double v[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) { e[0][m] = u[m]; e[1][m] = (k[m] - ep * u[m]) / ep; }
+    for (int m = 0; m < 4; ++m) v[m] = k[m] - ep * u[m];
+    double inv = 1.0 / sqrt(dot4(g, v, v));
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { e[0][m] = u[m]; e[1][m] = v[m] * inv; }
     int n = 2;
     if (has_b) n += gram_schmidt(g, e, n, bh) ? 1 : 0;
     for (int j = 1; j <= 3 && n < 4; ++j) {
@@ -147,7 +155,7 @@ GM_D double scatter_tetrad(const double g[4][4], const double u[4], const double
 // Then the photon is boosted to the electron rest frame, scattered by
 // rejection on the Klein-Nishina differential cross section (Thomson below
 // eps_e = 1e-4), and boosted back.  Returns the frame components of the
-// scattered photon.  Draws come from the parent's stream in a fixed order.
+// scattered photon.  Draws come from the child's stream in a fixed order.
 // ---------------------------------------------------------------------------
 struct ScatterCount { uint32_t e_trials, ang_trials; };
 

@@ -17,6 +17,7 @@
 #pragma once
 
 #include "gm_frame.h"
+#include "gm_kerr.h"
 
 namespace gm {
 
@@ -68,6 +69,12 @@ struct TArgs {
     long long max_steps;
     double L_unit_cm;
     ShTable sh;
+    // Kerr (modified Kerr-Schild): spin, polar slope, horizon, capture and
+    // record radii, corrector, reciprocal step scales (dx1, dx2, min(dx3, pi dx2))
+    double a_spin, h_slope, r_h, r_capture, r_record;
+    double verlet_tol;
+    int verlet_max_it;
+    double inv_sc[3];
     // scheduling: claim new photons once this many lanes of a wave idle
     int refill_min;
     // optional trace
@@ -129,11 +136,26 @@ GM_D int zone_cart(const TArgs &A, double x1, double x2, double x3)
     return in ? ((int)f1 * A.n[1] + (int)f2) * A.n[2] + (int)f3 : -1;
 }
 
+// Zone holding a modified Kerr-Schild point: x1 outside the grid is vacuum
+// (-1), x2 is clamped to the first/last polar zone, x3 is periodic.
+GM_D int zone_ks(const TArgs &A, double x1, double x2, double x3)
+{
+    double f1 = floor((x1 - A.xs[0]) * A.inv_dx[0]);
+    if (!(f1 >= 0.0 && f1 < (double)A.n[0])) return -1;
+    double f2 = floor((x2 - A.xs[1]) * A.inv_dx[1]);
+    f2 = fmin(fmax(f2, 0.0), (double)(A.n[1] - 1));
+    double f3 = floor((x3 - A.xs[2]) * A.inv_dx[2]);
+    double n3 = (double)A.n[2];
+    f3 -= n3 * floor(f3 / n3);
+    return ((int)f1 * A.n[1] + (int)f2) * A.n[2] + (int)f3;
+}
+
 // Invariant absorption and scattering coefficients (nu alpha) at a point
 // (Absorption and Scattering sections): alpha = j / B_nu (Kirchhoff),
-// alpha_sc = n_e sigma_h; and the bias at that point.
-template <class M>
-GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, int n_sc)
+// alpha_sc = n_e sigma_h; and the bias at that point.  g is the metric at
+// the point; FLAT zones carry their unit u and field direction already.
+template <bool FLAT>
+GM_D Coef coefficients_at(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
@@ -141,9 +163,8 @@ GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, 
     double ne = zr[Z_NE];
     if (!(ne > 0.0)) return c;
     c.vacuum = false;
-    double g[4][4], u[4], bh[4];
-    M::gcov(x, g);
-    bool has_b = fluid_frame_flat(zr, u, bh);
+    double u[4], bh[4];
+    bool has_b = FLAT ? fluid_frame_flat(zr, u, bh) : fluid_frame(zr, g, u, bh);
     double ef = -dot4(g, k, u);
     double inv_ef = 1.0 / ef;
     double nuf = ef * (kMeC2 / kH);
@@ -170,6 +191,14 @@ GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, 
     else b = (double)((n_sc + 1) * (n_sc + 1)) / (ne * kSigT * A.bias_value * A.L_unit_cm);
     c.b = fmin(fmax(b, 1.0), A.bias_max);
     return c;
+}
+
+template <class M>
+GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, int n_sc)
+{
+    double g[4][4];
+    M::gcov(x, g);
+    return coefficients_at<true>(A, z, g, k, n_sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,8 +263,15 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs A)
         }
         double phi = 2.0 * kPi * rng_uniform(rng, A.key0, A.key1);
         double g[4][4], u[4], bh[4], e[4][4];
-        M::gcov(x, g);
-        fluid_frame_flat(zr, u, bh);
+        if constexpr (M::kCurved) {
+            KMetric K;
+            kerr_metric<false>(A.a_spin, A.h_slope, x[1], x[2], K);
+            kerr_full(K, g);
+            fluid_frame(zr, g, u, bh);
+        } else {
+            M::gcov(x, g);
+            fluid_frame_flat(zr, u, bh);
+        }
         emission_tetrad(g, u, bh, e);
         double eps = kH * nu / kMeC2;
         double sth = sqrt(1.0 - cth * cth);
@@ -245,7 +281,10 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs A)
         for (int m = 0; m < 4; ++m) k[m] = kf[0] * e[0][m] + kf[1] * e[1][m] + kf[2] * e[2][m] + kf[3] * e[3][m];
         double w = exp(lnw);
         double x1 = -log(1.0 - rng_uniform(rng, A.key0, A.key1));
-        Coef c = coefficients<M>(A, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
+        // flat: opacities at the birth point now; Kerr: the tracker's first
+        // evaluation of a loaded photon computes them with the acceleration
+        Coef c{0.0, 0.0, 1.0, true};
+        if constexpr (!M::kCurved) c = coefficients<M>(A, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
         // write generation-0 queue entry q
         const PhotonQ &Q = A.dst;
 #pragma unroll
@@ -278,7 +317,7 @@ struct Photon {
     double acc_wabs, acc_wcap;     // weight lost to absorption / the generation cap
     Rng rng;
     int n_sc;
-    uint32_t steps;
+    uint32_t steps, nsub;          // steps; partial steps to scattering points
 };
 
 GM_D void load_photon(const PhotonQ &Q, unsigned long long i, Photon &ph)
@@ -292,6 +331,7 @@ GM_D void load_photon(const PhotonQ &Q, unsigned long long i, Photon &ph)
     ph.rng = Rng{Q.s0[i], Q.s1[i], Q.s2[i], Q.blk[i]};
     ph.n_sc = Q.n_sc[i];
     ph.steps = 0;
+    ph.nsub = 0;
     ph.acc_wabs = ph.acc_wcap = 0.0;
 }
 
@@ -344,7 +384,7 @@ GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind)
     default: break;
     }
     lds_inc(&B.stats[S_STEPS], ph.steps);
-    lds_inc(&B.stats[S_VERLET_IT], ph.steps);   // flat: one corrector pass per step
+    lds_inc(&B.stats[S_VERLET_IT], ph.steps + ph.nsub);   // flat: one corrector pass per (partial) step
     write_trace(A, ph, kind, inu, ith);
 }
 
@@ -426,11 +466,14 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
                 double tau_s = A.scattering ? 0.5 * (ph.nus + c1.nus) * A.C * dl : 0.0;
                 double b = c1.vacuum ? ph.b : c1.b;
                 if (A.scattering && ph.n_sc < A.n_sc_max && b * tau_s > ph.x1) {
-                    // ---- scattering point at the fraction f of the step ----
+                    // ---- scattering point: the step's start advanced over
+                    // the fraction f of the step (a straight line here) ----
                     double f = ph.x1 / (b * tau_s);
+                    double fdl = f * dl;
                     double xs[3];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) xs[m] = ph.x[m] + f * (xn[m] - ph.x[m]);
+                    for (int m = 0; m < 3; ++m) xs[m] = ph.x[m] + ph.k[m + 1] * fdl;
+                    ph.nsub += 1;
                     double wbf = ph.w;
                     ph.w *= exp(-f * tau_a);
                     ph.acc_wabs += wbf - ph.w;
