@@ -142,11 +142,11 @@ def main():
         ctx.load_zones(wl, i)
     torch.cuda.synchronize()
 
-    def one_step(seed):
+    def one_step(seed, precision=0):
         tot = None
         for i, wl in enumerate(wls):
             ctx.make_superphotons(dict(wl.emit, seed=seed), instance=i)
-            st = ctx.track_scatter(wl.track)
+            st = ctx.track_scatter(dict(wl.track, precision=precision))
             tot = st if tot is None else tot + st
         for i in range(len(wls)):
             ctx.read_spectrum(i, reset=True)
@@ -182,6 +182,20 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     track_ms, launches = ctx.read_timing()
+    ctx.set_timing(False)
+
+    # the FP32 precision form on the same workload and tuning, timed the same way
+    one_step(2000, precision=1)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t1 = time.perf_counter()
+    tot32 = None
+    for s in range(args.steps):
+        st = one_step(s, precision=1)
+        tot32 = st if tot32 is None else tot32 + st
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t1
+    ms32, l32 = ctx.read_timing()
     ctx.set_timing(False)
 
     n_sp = int(totals[0] + totals[1])
@@ -225,6 +239,16 @@ def main():
             "algorithmic_flops_per_launch": flops / launches if launches else None,
             "kernel_time_share": track_ms * 1e-3 / elapsed,
         },
+    }
+    n32 = int(tot32[0] + tot32[1])
+    out["forms"] = {
+        "f32_emissivity": {
+            "what": "emissivity, Kirchhoff absorption and hot cross section in FP32 (log space, "
+                    "64-byte zone records); geodesics, weights, tallies FP64",
+            "value": n32 / el32, "unit": "superphotons/s", "ms_per_step": el32 / args.steps * 1e3,
+            "avg_track_launch_ms": ms32 / l32 if l32 else None,
+            "speedup_vs_f64": (n32 / el32) / value,
+        }
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wls, args.cpu_roots)

@@ -91,6 +91,12 @@ typedef struct {
 #define GM_BIAS_GEN2   2    /* b = (n_sc+1)^2 / (n_e sigma_T bias_value ell)     */
 
 #define GM_PRECISION_F64 0  /* all transport arithmetic in double                 */
+#define GM_PRECISION_F32_EMISSIVITY 1
+                            /* emissivity, Kirchhoff absorption and the hot cross
+                               section in single precision (log space, FP32 zone
+                               records and table); geodesics, step control,
+                               optical-depth sums, weights, sampling and tallies
+                               in double                                          */
 
 typedef struct {
     int     scattering;     /* 0: no Compton opacity; 1: biased thermal Compton   */

@@ -67,6 +67,7 @@ struct Instance {
     gm_grid grid{};
     int nz = 0;
     DevBuf<double> zrec, vol;
+    DevBuf<float> zrec32;
     DevBuf<int> emits;
     // last make
     gm_emit_params ep{};
@@ -94,8 +95,10 @@ struct gm_ctx {
     Instance inst[GM_MAX_INSTANCES];
     // tables
     DevBuf<double> gcheb, sh_table, gl_x, gl_w;
+    DevBuf<float> sh_table32;
     GCheb G{};
     ShTable sh{};
+    ShTable32 sh32{};
     bool sh_built = false;
     // photon queues (ping-pong between generations) and per-generation counters
     unsigned long long child_cap = 0;
@@ -161,6 +164,14 @@ static gm_status ensure_sigma_hot(gm_ctx *c)
     S.de = (std::log(kShEMax) - std::log(kShEMin)) / (kShNE - 1);
     sigma_hot_build_kernel<<<kShNT * kShNE, 256, 0, c->stream>>>(S);
     HIPCHK(hipGetLastError());
+    HIPCHK(c->sh_table32.ensure(kShNT * kShNE));
+    to_float_kernel<<<(kShNT * kShNE + 255) / 256, 256, 0, c->stream>>>(c->sh_table.p, c->sh_table32.p, kShNT * kShNE);
+    HIPCHK(hipGetLastError());
+    c->sh32.t = c->sh_table32.p;
+    c->sh32.lt0 = (float)S.lt0;
+    c->sh32.inv_dt = (float)(1.0 / S.dt);
+    c->sh32.le0 = (float)S.le0;
+    c->sh32.inv_de = (float)(1.0 / S.de);
     c->sh.t = c->sh_table.p;
     c->sh.lt0 = S.lt0;
     c->sh.inv_dt = 1.0 / S.dt;
@@ -204,12 +215,12 @@ gm_status gm_destroy(gm_ctx *c)
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
     for (auto &I : c->inst) {
-        I.zrec.release(); I.vol.release(); I.emits.release(); I.nu_nodes.release();
+        I.zrec.release(); I.zrec32.release(); I.vol.release(); I.emits.release(); I.nu_nodes.release();
         I.w_node.release(); I.ln_w.release(); I.nbar.release(); I.fmax.release();
         I.partial.release(); I.count.release(); I.zone_of_root.release(); I.offset.release();
         I.tile.release(); I.roots.release(); I.spec.release(); I.ledger.release(); I.stats.release();
     }
-    c->gcheb.release(); c->sh_table.release(); c->gl_x.release(); c->gl_w.release();
+    c->gcheb.release(); c->sh_table.release(); c->sh_table32.release(); c->gl_x.release(); c->gl_w.release();
     for (int b = 0; b < 2; ++b) {
         for (auto &d : c->qd[b]) d.release();
         for (auto &d : c->qu[b]) d.release();
@@ -289,14 +300,14 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
         }
         dsrc[k] = stage[k].p;
     }
-    if (I.zrec.ensure((size_t)nz * Z_STRIDE) != hipSuccess || I.vol.ensure(nz) != hipSuccess ||
-        I.emits.ensure(nz) != hipSuccess) {
+    if (I.zrec.ensure((size_t)nz * Z_STRIDE) != hipSuccess || I.zrec32.ensure((size_t)nz * F_STRIDE) != hipSuccess ||
+        I.vol.ensure(nz) != hipSuccess || I.emits.ensure(nz) != hipSuccess) {
         for (auto &b : stage) b.release();
         return fail(GM_ENOMEM, "zone records");
     }
     PrepArgs P;
     P.n_e = dsrc[0]; P.theta = dsrc[1]; P.B = dsrc[2]; P.ucon = dsrc[3]; P.bcon = dsrc[4];
-    P.zrec = I.zrec.p; P.vol = I.vol.p; P.emits = I.emits.p;
+    P.zrec = I.zrec.p; P.zrec32 = I.zrec32.p; P.vol = I.vol.p; P.emits = I.emits.p;
     for (int j = 0; j < 3; ++j) { P.n[j] = g->n[j]; P.xs[j] = g->x_start[j]; P.dx[j] = g->dx[j]; }
     P.L3 = g->L_unit_cm * g->L_unit_cm * g->L_unit_cm;
     P.nz = nz;
@@ -483,10 +494,18 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     const size_t lds_small = (size_t)(L_N + S_N) * 8;
     if (lds_track > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %zu bins exceeds the LDS tally", nspec / 3);
     const bool kerr = I.grid.metric == GM_METRIC_KS_MKS;
-    auto track_fn = kerr ? (c->track_waves == 4 ? track_kernel_ks<4>
-                            : c->track_waves == 3 ? track_kernel_ks<3> : track_kernel_ks<2>)
-                         : (c->track_waves == 4 ? track_kernel_flat<4>
-                            : c->track_waves == 3 ? track_kernel_flat<3> : track_kernel_flat<2>);
+    const bool f32 = tp->precision == GM_PRECISION_F32_EMISSIVITY;
+    using KernelFn = void (*)(TArgs);
+    static const KernelFn track_fns[2][2][3] = {
+        {{track_kernel_flat<2, false>, track_kernel_flat<3, false>, track_kernel_flat<4, false>},
+         {track_kernel_flat<2, true>, track_kernel_flat<3, true>, track_kernel_flat<4, true>}},
+        {{track_kernel_ks<2, false>, track_kernel_ks<3, false>, track_kernel_ks<4, false>},
+         {track_kernel_ks<2, true>, track_kernel_ks<3, true>, track_kernel_ks<4, true>}}};
+    const KernelFn track_fn = track_fns[kerr][f32][c->track_waves - 2];
+    const KernelFn birth_fn = kerr ? (KernelFn)birth_kernel<KerrMKS, false>
+                                   : f32 ? (KernelFn)birth_kernel<Minkowski, true> : (KernelFn)birth_kernel<Minkowski, false>;
+    const KernelFn scatter_fn = kerr ? (KernelFn)scatter_kernel_ks
+                                     : f32 ? (KernelFn)scatter_kernel_flat<true> : (KernelFn)scatter_kernel_flat<false>;
     int occ = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_fn, 256, lds_track));
     occ = std::max(occ, 1);
@@ -494,6 +513,9 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
 
     TArgs A{};
     A.zrec = I.zrec.p;
+    A.zrec32 = I.zrec32.p;
+    A.sh32 = c->sh32;
+    A.ln_c2_2h = (float)std::log(kC * kC / (2.0 * kH));
     for (int j = 0; j < 3; ++j) {
         A.n[j] = I.grid.n[j];
         A.xs[j] = I.grid.x_start[j];
@@ -557,10 +579,7 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
         A.root_count = cnt;
         A.dst = queue(c, 0);
         A.src_count = c->ctr.p;                       // generation-0 count
-        if (kerr)
-            birth_kernel<KerrMKS><<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
-        else
-            birth_kernel<Minkowski><<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
+        birth_fn<<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
         HIPCHK(hipGetLastError());
         for (int g = 0; g < ngen; ++g) {
             A.gen = g;
@@ -579,10 +598,7 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
             HIPCHK(hipGetLastError());
             if (c->timing) HIPCHK(hipEventRecord(e1, c->stream));
             if (g + 1 < ngen) {
-                if (kerr)
-                    scatter_kernel_ks<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
-                else
-                    scatter_kernel_flat<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
+                scatter_fn<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
                 HIPCHK(hipGetLastError());
             }
         }
@@ -607,7 +623,8 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
         tp->n_sc_max > 15 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0) || tp->max_steps < 1 ||
         tp->bias_mode < 0 || tp->bias_mode > 2 || !(tp->bias_value > 0.0))
         return fail(GM_EINVAL, "bad track parameters");
-    if (tp->precision != GM_PRECISION_F64) return fail(GM_EUNSUPPORTED, "precision %d", tp->precision);
+    if (tp->precision != GM_PRECISION_F64 && tp->precision != GM_PRECISION_F32_EMISSIVITY)
+        return fail(GM_EINVAL, "precision %d", tp->precision);
     gm_status s = set_device(c);
     if (s != GM_OK) return s;
     bool any = false;

@@ -1,6 +1,7 @@
 // gm_emit.h -- zone preparation and superphoton generation (device side).
 #pragma once
 
+#include "gm_emis32.h"
 #include "gm_frame.h"
 #include "gm_kerr.h"
 
@@ -12,6 +13,7 @@ namespace gm {
 struct PrepArgs {
     const double *n_e, *theta, *B, *ucon, *bcon;
     double *zrec, *vol;
+    float *zrec32;
     int *emits;
     int n[3];
     double xs[3], dx[3];
@@ -69,6 +71,18 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
     r[Z_INVNUC] = nuc > 0.0 ? 1.0 / nuc : 0.0;
     P.vol[z] = sqrt_g * P.dx[0] * P.dx[1] * P.dx[2] * P.L3;
     P.emits[z] = (A > 0.0 && !inside) ? 1 : 0;
+    // the FP32 record of the precision form
+    float *f = P.zrec32 + (size_t)z * F_STRIDE;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) f[m] = (float)r[m];
+    f[F_LNA] = A > 0.0 ? (float)log(A) : -INFINITY;
+    f[F_LNINVNUC] = nuc > 0.0 ? (float)(-log(nuc)) : 0.0f;
+    f[F_TH] = (float)th;
+    f[F_INVTH] = th > 0.0 ? (float)(1.0 / th) : 0.0f;
+    f[F_LNTH] = th > 0.0 ? (float)log(th) : 0.0f;
+    f[F_LNNESIG] = ne > 0.0 ? (float)log(ne * kSigT) : -INFINITY;
+    f[F_HASB] = (float)r[Z_HASB];
+    f[F_NE] = (float)ne;
 }
 
 // ---------------------------------------------------------------------------
@@ -316,6 +330,13 @@ __global__ void eval_G_kernel(GCheb G, const double *x, double *y, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = G_of_Xc(G, x[i]);
+}
+
+// FP32 copy of the hot cross-section table (ln sigma_h / sigma_T).
+__global__ __launch_bounds__(256) void to_float_kernel(const double *src, float *dst, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
 }
 
 }  // namespace gm

@@ -46,14 +46,12 @@ GM_D double e_inf(const double g[4][4], const double *k)
 enum { Z_U0 = 0, Z_B0 = 4, Z_A = 8, Z_NUC = 9, Z_TH = 10, Z_NE = 11, Z_LNTH = 12, Z_INVTH = 13,
        Z_HASB = 14, Z_INVNUC = 15, Z_STRIDE = 16 };
 
-// Unit fluid velocity and field direction at a point: the zone's u is
-// normalised with the local metric, the field direction projected normal
-// to u and normalised (absent when the zone has no field or it is
-// degenerate here).
-GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], double bh[4])
+// Unit fluid velocity and field direction at a point: the zone's u (given
+// in u) is normalised with the local metric, the field direction (in bh)
+// projected normal to u and normalised (absent when the zone has no field
+// or it is degenerate here).
+GM_D bool fluid_frame_vec(bool zone_has_b, const double g[4][4], double u[4], double bh[4])
 {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) { u[m] = zr[Z_U0 + m]; bh[m] = zr[Z_B0 + m]; }
     double un = sqrt(-dot4(g, u, u));
 #pragma unroll
     for (int m = 0; m < 4; ++m) u[m] /= un;
@@ -61,11 +59,19 @@ GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], doubl
 #pragma unroll
     for (int m = 0; m < 4; ++m) bh[m] += bu * u[m];
     double bb = dot4(g, bh, bh);
-    bool has_b = (bb > 0.0) && (zr[Z_HASB] != 0.0);
+    bool has_b = (bb > 0.0) && zone_has_b;
     double inv = has_b ? 1.0 / sqrt(bb) : 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) bh[m] = has_b ? bh[m] * inv : 0.0;
     return has_b;
+}
+
+// Same from a packed FP64 zone record.
+GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], double bh[4])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { u[m] = zr[Z_U0 + m]; bh[m] = zr[Z_B0 + m]; }
+    return fluid_frame_vec(zr[Z_HASB] != 0.0, g, u, bh);
 }
 
 // Flat spacetime: the normalised vectors were stored by the zone preparation.

@@ -16,6 +16,7 @@
 // ledgers and counters accumulate in LDS and are merged into HBM per block.
 #pragma once
 
+#include "gm_emis32.h"
 #include "gm_frame.h"
 #include "gm_kerr.h"
 
@@ -40,6 +41,7 @@ struct TraceRec {
 struct TArgs {
     // instance geometry and plasma
     const double *zrec;
+    const float *zrec32;           // FP32 records (precision form)
     int n[3];
     double xs[3], dx[3], inv_dx[3], xe[3];
     double C;                      // h ell / (m_e c^2): converts d(lambda) to cm s
@@ -69,6 +71,8 @@ struct TArgs {
     long long max_steps;
     double L_unit_cm;
     ShTable sh;
+    ShTable32 sh32;
+    float ln_c2_2h;                // ln(c^2 / (2 h)), set on the host from the CGS constants
     // Kerr (modified Kerr-Schild): spin, polar slope, horizon, capture and
     // record radii, corrector, reciprocal step scales (dx1, dx2, min(dx3, pi dx2))
     double a_spin, h_slope, r_h, r_capture, r_record;
@@ -150,12 +154,23 @@ GM_D int zone_ks(const TArgs &A, double x1, double x2, double x3)
     return ((int)f1 * A.n[1] + (int)f2) * A.n[2] + (int)f3;
 }
 
+// Bias of a point (Scattering section): constant, Theta_e^2-scaled, or
+// growing with the generation and falling with the density; clamped.
+GM_D double bias_at(const TArgs &A, double theta, double ne, int n_sc)
+{
+    double b;
+    if (A.bias_mode == 0) b = A.bias_value;
+    else if (A.bias_mode == 1) b = A.bias_value * theta * theta;
+    else b = (double)((n_sc + 1) * (n_sc + 1)) / (ne * kSigT * A.bias_value * A.L_unit_cm);
+    return fmin(fmax(b, 1.0), A.bias_max);
+}
+
 // Invariant absorption and scattering coefficients (nu alpha) at a point
 // (Absorption and Scattering sections): alpha = j / B_nu (Kirchhoff),
 // alpha_sc = n_e sigma_h; and the bias at that point.  g is the metric at
 // the point; FLAT zones carry their unit u and field direction already.
 template <bool FLAT>
-GM_D Coef coefficients_at(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
+GM_D Coef coefficients_at64(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
@@ -185,20 +200,59 @@ GM_D Coef coefficients_at(const TArgs &A, int z, const double g[4][4], const dou
         }
     }
     if (A.scattering) c.nus = nuf * ne * kSigT * sigma_hot(A.sh, zr[Z_LNTH], ef);
-    double b;
-    if (A.bias_mode == 0) b = A.bias_value;
-    else if (A.bias_mode == 1) b = A.bias_value * zr[Z_TH] * zr[Z_TH];
-    else b = (double)((n_sc + 1) * (n_sc + 1)) / (ne * kSigT * A.bias_value * A.L_unit_cm);
-    c.b = fmin(fmax(b, 1.0), A.bias_max);
+    c.b = bias_at(A, zr[Z_TH], ne, n_sc);
     return c;
 }
 
-template <class M>
+// The same in the FP32 form: frame products in double, then emissivity,
+// absorption and the hot cross section as FP32 logarithms and one exp each.
+template <bool FLAT>
+GM_D Coef coefficients_at32(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
+{
+    Coef c{0.0, 0.0, 1.0, true};
+    if (z < 0) return c;
+    const float *zf = A.zrec32 + (size_t)z * F_STRIDE;
+    float nef = zf[F_NE];
+    if (!(nef > 0.0f)) return c;
+    c.vacuum = false;
+    double u[4], bh[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { u[m] = (double)zf[F_U0 + m]; bh[m] = (double)zf[F_B0 + m]; }
+    bool has_b = zf[F_HASB] != 0.0f;
+    if (!FLAT) has_b = fluid_frame_vec(has_b, g, u, bh);
+    double ef = -dot4(g, k, u);
+    float lnnu = __logf((float)(ef * (kMeC2 / kH)));
+    float lnA = zf[F_LNA];
+    if (has_b && lnA > -1e30f) {
+        double cth = fmin(fmax(dot4(g, k, bh) / ef, -1.0), 1.0);
+        float s2 = (float)(1.0 - cth * cth);
+        if (s2 > 0.0f) {
+            float lns = 0.5f * __logf(s2);
+            float lnj = lnA + lns + ln_g_shape32(lnnu + zf[F_LNINVNUC] - lns);
+            float x = (float)ef * zf[F_INVTH];
+            // nu alpha = j (e^{h nu/kT} - 1) c^2 / (2 h nu^2)
+            c.nua = (double)__expf(lnj + ln_expm1_32(x) + A.ln_c2_2h - 2.0f * lnnu);
+        }
+    }
+    if (A.scattering)
+        c.nus = (double)__expf(lnnu + zf[F_LNNESIG] + ln_sigma_hot32(A.sh32, zf[F_LNTH], __logf((float)ef)));
+    c.b = bias_at(A, (double)zf[F_TH], (double)nef, n_sc);
+    return c;
+}
+
+template <bool FLAT, bool F32 = false>
+GM_D Coef coefficients_at(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
+{
+    if constexpr (F32) return coefficients_at32<FLAT>(A, z, g, k, n_sc);
+    else return coefficients_at64<FLAT>(A, z, g, k, n_sc);
+}
+
+template <class M, bool F32 = false>
 GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, int n_sc)
 {
     double g[4][4];
     M::gcov(x, g);
-    return coefficients_at<true>(A, z, g, k, n_sc);
+    return coefficients_at<true, F32>(A, z, g, k, n_sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,7 +261,7 @@ GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, 
 // direction by rejection against j(pi/2), fluid-frame tetrad, weight w(nu),
 // remaining optical depth, opacities at the birth point.
 // ---------------------------------------------------------------------------
-template <class M>
+template <class M, bool F32>
 __global__ __launch_bounds__(256) void birth_kernel(TArgs A)
 {
     extern __shared__ double lds[];
@@ -284,7 +338,7 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs A)
         // flat: opacities at the birth point now; Kerr: the tracker's first
         // evaluation of a loaded photon computes them with the acceleration
         Coef c{0.0, 0.0, 1.0, true};
-        if constexpr (!M::kCurved) c = coefficients<M>(A, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
+        if constexpr (!M::kCurved) c = coefficients<M, F32>(A, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
         // write generation-0 queue entry q
         const PhotonQ &Q = A.dst;
 #pragma unroll
@@ -395,7 +449,7 @@ GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind)
 // that ends keeps its state in the idle lane; its bookkeeping (tally,
 // ledger, trace) runs in the wave's next refill pass together with the
 // other lanes that ended, instead of diverging from the stepping lanes.
-template <int WAVES>
+template <int WAVES, bool F32>
 __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
 {
     extern __shared__ double lds[];
@@ -454,7 +508,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
             }
             int zn = zone_cart(A, xn[0], xn[1], xn[2]);
             double xv[4] = {0.0, xn[0], xn[1], xn[2]};
-            Coef c1 = coefficients<Minkowski>(A, zn, xv, ph.k, ph.n_sc);
+            Coef c1 = coefficients<Minkowski, F32>(A, zn, xv, ph.k, ph.n_sc);
             if (restart) {
                 ph.nua = c1.nua; ph.nus = c1.nus;
                 if (!c1.vacuum) ph.b = c1.b;
@@ -583,6 +637,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
 // (gamma, mu), electron azimuth, scattering angle and azimuth, then the
 // child's own optical-depth draw.
 // ---------------------------------------------------------------------------
+template <bool F32>
 __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs A)
 {
     extern __shared__ double lds[];
@@ -621,7 +676,7 @@ __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs A)
         lds_inc(&B.stats[S_CHILDREN], 1);
         lds_inc(&B.stats[S_GEN0 + min(n_sc, 15)], 1);
         double x1 = -log(1.0 - rng_uniform(r, A.key0, A.key1));
-        Coef c = coefficients<Minkowski>(A, zone_cart(A, x[1], x[2], x[3]), x, kc, n_sc);
+        Coef c = coefficients<Minkowski, F32>(A, zone_cart(A, x[1], x[2], x[3]), x, kc, n_sc);
 #pragma unroll
         for (int m = 0; m < 4; ++m) Q.k[m][i] = kc[m];
         Q.wb[i] = wchild;

@@ -135,7 +135,7 @@ GM_D int plasma_zone(const TArgs &A, int z)
 // corrector; Absorption and Scattering sections).  Scheduling as in the
 // flat tracker: lanes idle until enough of the wave is idle, then claim
 // queue entries together and run the finished photons' bookkeeping.
-template <int WAVES>
+template <int WAVES, bool F32>
 __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs A)
 {
     extern __shared__ double lds[];
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs A)
             double g[4][4];
             kerr_full(K, g);
             const int zn = zone_ks(A, P[0], P[1], P[2]);
-            Coef c1 = coefficients_at<false>(A, zn, g, kn, ph.n_sc);
+            Coef c1 = coefficients_at<false, F32>(A, zn, g, kn, ph.n_sc);
             if (mode != MODE_STEP) {
                 // restart at the scattering point, or first evaluation of a
                 // loaded photon: fresh acceleration and opacities here
