@@ -26,6 +26,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -127,6 +129,10 @@ def main():
     ap.add_argument("--refill-min", type=int, default=8)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--ttx-seeds", type=int, default=3,
+                    help="seeds of the time-to-1%% measurement (0 = skip)")
+    ap.add_argument("--ttx-ref-rounds", type=int, default=1024,
+                    help="N_s rounds of the plain reference spectrum")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus %d requested); multi-GPU sharding is "
@@ -240,6 +246,31 @@ def main():
             "kernel_time_share": track_ms * 1e-3 / elapsed,
         },
     }
+    # time to 1 % spectral error, plain method, on the tau_T = 0.1 instance
+    ttx = None
+    if args.ttx_seeds > 0:
+        from paper_2602_13198_amd import convergence as CV
+        iw = len(wls) - 1
+        wl = wls[iw]
+        L_ref, cnt_ref, rse_ref, n_ref = CV.reference(ctx, wl, iw, args.ttx_ref_rounds, 100000)
+        mask = CV.error_mask(cnt_ref, rse_ref)
+        runs = [CV.time_to_error(ctx, wl, iw, L_ref, mask, 200000 + 1000 * k,
+                                 wl.emit["n_target"]) for k in range(args.ttx_seeds)]
+        secs = [r["seconds"] for r in runs if r["seconds"] is not None]
+        ttx = {
+            "workload": "scattering sphere tau_T=0.1 (b=10), plain uniform bias, FP64",
+            "target_eps_err": 0.01,
+            "plain": {"seconds_median": float(np.median(secs)) if len(secs) == len(runs) else None,
+                      "seconds": [r["seconds"] for r in runs],
+                      "superphotons": [r["superphotons"] for r in runs],
+                      "final_eps": [r["final_eps"] for r in runs]},
+            "learned": None,
+            "reference": {"rounds": args.ttx_ref_rounds, "superphotons": n_ref,
+                          "masked_bins": int(mask.sum()),
+                          "mask": "bins holding >= 1e3 superphotons and a relative standard "
+                                  "error <= 10% per N_s=1e6 round",
+                          "rounds_of": "N_s = 1e6, seeds disjoint from the reference"},
+        }
     n32 = int(tot32[0] + tot32[1])
     out["forms"] = {
         "f32_emissivity": {
@@ -250,6 +281,8 @@ def main():
             "speedup_vs_f64": (n32 / el32) / value,
         }
     }
+    if ttx is not None:
+        out["time_to_1pct"] = ttx
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wls, args.cpu_roots)
     ctx.close()
