@@ -131,6 +131,8 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--ttx-seeds", type=int, default=3,
                     help="seeds of the time-to-1%% measurement (0 = skip)")
+    ap.add_argument("--ttx-anchor", type=float, default=None,
+                    help="quantile of the predicted importance at which the learned b equals the plain b")
     ap.add_argument("--ttx-ref-rounds", type=int, default=1024,
                     help="N_s rounds of the plain reference spectrum")
     args = ap.parse_args()
@@ -257,14 +259,43 @@ def main():
         runs = [CV.time_to_error(ctx, wl, iw, L_ref, mask, 200000 + 1000 * k,
                                  wl.emit["n_target"]) for k in range(args.ttx_seeds)]
         secs = [r["seconds"] for r in runs if r["seconds"] is not None]
+        # the learned form: records from two plain rounds (disjoint seeds), the
+        # network trained on the library's matrix-core kernels, the table built
+        # by its inference kernel (counted in the learned time)
+        from paper_2602_13198_amd.learned import LearnedBias, collect_records
+        torch.cuda.synchronize()
+        tt0 = time.perf_counter()
+        bin_w = np.where(mask, 1.0 / np.maximum(L_ref, 1e-300), 0.0)
+        Xr, Tr = collect_records(ctx, wl, iw, 2, 300000, bin_weight=bin_w)
+        lb = LearnedBias(seed=1)
+        fit_hist = lb.fit(ctx, Xr, Tr, steps=600, anchor_quantile=args.ttx_anchor)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - tt0
+        tt1 = time.perf_counter()
+        lb.apply(ctx, wl, iw, b_plain=wl.track["bias_value"], b_max=1e3)
+        t_table = time.perf_counter() - tt1
+        learned_over = dict(bias_mode=3, bias_max=1e3)
+        runs_l = [CV.time_to_error(ctx, wl, iw, L_ref, mask, 400000 + 1000 * k, wl.emit["n_target"],
+                                   track_overrides=learned_over) for k in range(args.ttx_seeds)]
+        secs_l = [r["seconds"] for r in runs_l if r["seconds"] is not None]
+        med_p = float(np.median(secs)) if len(secs) == len(runs) else None
+        med_l = float(np.median(secs_l)) + t_table if len(secs_l) == len(runs_l) else None
         ttx = {
             "workload": "scattering sphere tau_T=0.1 (b=10), plain uniform bias, FP64",
             "target_eps_err": 0.01,
-            "plain": {"seconds_median": float(np.median(secs)) if len(secs) == len(runs) else None,
+            "plain": {"seconds_median": med_p,
                       "seconds": [r["seconds"] for r in runs],
                       "superphotons": [r["superphotons"] for r in runs],
                       "final_eps": [r["final_eps"] for r in runs]},
-            "learned": None,
+            "learned": {"seconds_median": med_l,
+                        "seconds": [r["seconds"] for r in runs_l],
+                        "superphotons": [r["superphotons"] for r in runs_l],
+                        "final_eps": [r["final_eps"] for r in runs_l],
+                        "table_build_s": t_table,
+                        "training_one_off_s": t_train, "training_records": int(len(Xr)),
+                        "training_loss_first_last": [fit_hist[0][1], fit_hist[-1][1]],
+                        "bias": "b = exp(learned ln b[zone][ln eps]), clamped to [1, 1e3]"},
+            "plain_over_learned": (med_p / med_l) if (med_p and med_l) else None,
             "reference": {"rounds": args.ttx_ref_rounds, "superphotons": n_ref,
                           "masked_bins": int(mask.sum()),
                           "mask": "bins holding >= 1e3 superphotons and a relative standard "

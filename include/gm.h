@@ -89,6 +89,10 @@ typedef struct {
 #define GM_BIAS_CONST  0    /* b = bias_value                                    */
 #define GM_BIAS_THETA2 1    /* b = bias_value * Theta_e^2                        */
 #define GM_BIAS_GEN2   2    /* b = (n_sc+1)^2 / (n_e sigma_T bias_value ell)     */
+#define GM_BIAS_LEARNED 3   /* b = exp of the instance's learned table ln b[zone]
+                               interpolated in ln eps (gm_set_bias_table);
+                               bias_value is ignored.  Any b >= 1 keeps the
+                               estimator unbiased (child w/b, parent w(1-1/b)). */
 
 #define GM_PRECISION_F64 0  /* all transport arithmetic in double                 */
 #define GM_PRECISION_F32_EMISSIVITY 1
@@ -227,6 +231,57 @@ gm_status gm_set_tuning(gm_ctx *ctx, int track_waves, int refill_min);
  * launches since timing was last enabled (synchronises on the events). */
 gm_status gm_set_timing(gm_ctx *ctx, int enable);
 gm_status gm_read_timing(gm_ctx *ctx, double *track_ms, uint64_t *track_launches);
+
+/* ---- learned form ----------------------------------------------------
+ * Not a passage of the paper: the paper names bias tuning as future work
+ * (Conclusions).  A network 6 -> 64 -> 64 -> 2 (tanh hidden layers) is
+ * evaluated and trained with matrix-core kernels (BF16 operands, FP32
+ * accumulation, FP32 master weights and Adam state on the device).
+ * Parameter vector (float32, GM_MLP_PARAMS entries), in order:
+ * W1[6][64], b1[64], W2[64][64], b2[64], W3[64][2], b3[2]; a layer maps
+ * h -> tanh(h W + b) (the last without tanh).  Feature rows are 8 floats
+ * (6 features, 2 ignored), outputs and targets 2 floats per row. */
+#define GM_MLP_PARAMS 4738
+
+/* Set the parameters from a host vector; resets the Adam state. */
+gm_status gm_mlp_set_params(gm_ctx *ctx, const float *host_params);
+/* Copy the FP32 parameters to a host vector (synchronises). */
+gm_status gm_mlp_get_params(gm_ctx *ctx, float *host_params);
+/* Outputs for n rows: X [n][8] and Y [n][2] are device buffers; stream-
+ * ordered, no synchronisation. */
+gm_status gm_mlp_forward(gm_ctx *ctx, const float *X, int64_t n, float *Y);
+/* Gradient of L = sum_rows sum_o C[r][o] (y[r][o] - T[r][o])^2 with respect
+ * to the parameters, into host vectors grad [GM_MLP_PARAMS] and loss [1]
+ * (either may be NULL).  X [n][8], T [n][2], C [n][2] are device buffers;
+ * the caller normalises C.  Synchronises. */
+gm_status gm_mlp_grad(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
+                      float *grad, float *loss);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) on the same loss with learning
+ * rate lr; loss (host, may be NULL: no synchronisation) receives the loss
+ * before the step. */
+gm_status gm_mlp_train_step(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
+                            float lr, float *loss);
+
+/* Learned bias table of an instance: ln b for every zone on n_eps nodes
+ * uniform in ln eps over [ln_eps_lo, ln_eps_hi] (eps the fluid-frame photon
+ * energy in m_e c^2), host array [nzones][n_eps], copied.  Used by
+ * GM_BIAS_LEARNED. */
+gm_status gm_set_bias_table(gm_ctx *ctx, int instance, const double *ln_b, int n_eps,
+                            double ln_eps_lo, double ln_eps_hi);
+
+/* Scattering-event log (training records of the learned form): one
+ * gm_event_rec per scattering event into a device buffer of `capacity`
+ * records (NULL disables); gm_event_count returns the count (synchronises). */
+typedef struct {
+    uint32_t s0, s1, s2;    /* the child's stream id (its trace record's key)     */
+    int32_t  zone;          /* zone whose plasma scattered                        */
+    double   eps;           /* incoming photon's fluid-frame energy, m_e c^2      */
+    double   w_child;       /* the child's weight                                 */
+    double   x[3];          /* event position (code coordinates)                  */
+    double   pad;
+} gm_event_rec;
+gm_status gm_set_event_log(gm_ctx *ctx, void *device_buffer, uint64_t capacity);
+gm_status gm_event_count(gm_ctx *ctx, uint64_t *n);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@
 #include "../../include/gm.h"
 #include "gm_emit.h"
 #include "gm_host_tables.h"
+#include "gm_mlp.h"
 #include "gm_track.h"
 #include "gm_track_ks.h"
 
@@ -19,6 +20,8 @@ using namespace gm;
 
 static_assert(sizeof(TraceRec) == sizeof(gm_trace_rec), "trace record layout");
 static_assert(sizeof(TraceRec) == 112, "trace record layout");
+static_assert(sizeof(EventRec) == sizeof(gm_event_rec), "event record layout");
+static_assert(kMlpParams == GM_MLP_PARAMS, "network parameter count");
 
 namespace {
 
@@ -84,6 +87,10 @@ struct Instance {
     int n_nu = 0, n_theta = 0;
     DevBuf<double> spec, ledger;
     DevBuf<unsigned long long> stats;
+    // learned bias table ln b [nz][lnb_n]
+    DevBuf<double> lnb;
+    int lnb_n = 0;
+    double lnb_lo = 0.0, lnb_hi = 0.0;
 };
 
 }  // namespace
@@ -117,10 +124,18 @@ struct gm_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     double track_ms = 0.0;
     unsigned long long track_launches = 0;
-    // trace
+    // trace and scattering-event log
     TraceRec *trace = nullptr;
     unsigned long long trace_cap = 0;
     DevBuf<unsigned long long> trace_n;
+    EventRec *evlog = nullptr;
+    unsigned long long evlog_cap = 0;
+    DevBuf<unsigned long long> evlog_n;
+    // learned form: network parameters (FP32 master, BF16 copies), Adam state
+    DevBuf<float> mlp_p, mlp_m, mlp_v, mlp_g, mlp_gpart;
+    DevBuf<short> mlp_pb;
+    bool mlp_ready = false;
+    long long mlp_t = 0;
 };
 
 static gm_status set_device(gm_ctx *c)
@@ -202,7 +217,7 @@ gm_status gm_create(gm_ctx **out, int device, void *hip_stream)
     c->n_cu = prop.multiProcessorCount;
     s = build_tables(c);
     if (s == GM_OK && (c->ctr.ensure(2 * 32) != hipSuccess || c->flags.ensure(4) != hipSuccess ||
-                       c->trace_n.ensure(1) != hipSuccess))
+                       c->trace_n.ensure(1) != hipSuccess || c->evlog_n.ensure(1) != hipSuccess))
         s = fail(GM_ENOMEM, "counters");
     if (s != GM_OK) { gm_destroy(c); return s; }
     *out = c;
@@ -219,7 +234,10 @@ gm_status gm_destroy(gm_ctx *c)
         I.w_node.release(); I.ln_w.release(); I.nbar.release(); I.fmax.release();
         I.partial.release(); I.count.release(); I.zone_of_root.release(); I.offset.release();
         I.tile.release(); I.roots.release(); I.spec.release(); I.ledger.release(); I.stats.release();
+        I.lnb.release();
     }
+    c->mlp_p.release(); c->mlp_m.release(); c->mlp_v.release(); c->mlp_g.release();
+    c->mlp_gpart.release(); c->mlp_pb.release(); c->evlog_n.release();
     c->gcheb.release(); c->sh_table.release(); c->sh_table32.release(); c->gl_x.release(); c->gl_w.release();
     for (int b = 0; b < 2; ++b) {
         for (auto &d : c->qd[b]) d.release();
@@ -555,6 +573,13 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     A.trace = c->trace;
     A.trace_n = c->trace_n.p;
     A.trace_cap = c->trace_cap;
+    A.evlog = c->evlog;
+    A.evlog_n = c->evlog_n.p;
+    A.evlog_cap = c->evlog_cap;
+    A.lnb = I.lnb.p;
+    A.lnb_n = I.lnb_n;
+    A.lnb_lo = I.lnb_lo;
+    A.lnb_inv_d = I.lnb_n > 1 ? (I.lnb_n - 1) / (I.lnb_hi - I.lnb_lo) : 0.0;
     A.overflow = c->flags.p;
     A.cap = c->child_cap;
     A.refill_min = c->refill_min;
@@ -621,7 +646,7 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     if (tp->n_nu < 1 || tp->n_theta < 1 || !(tp->nu_lo > 0.0) || !(tp->nu_hi > tp->nu_lo) ||
         !(tp->bias_max >= 1.0) || !(tp->step_h > 0.0) || tp->verlet_max_it < 1 || tp->n_sc_max < 0 ||
         tp->n_sc_max > 15 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0) || tp->max_steps < 1 ||
-        tp->bias_mode < 0 || tp->bias_mode > 2 || !(tp->bias_value > 0.0))
+        tp->bias_mode < 0 || tp->bias_mode > 3 || (tp->bias_mode < 3 && !(tp->bias_value > 0.0)))
         return fail(GM_EINVAL, "bad track parameters");
     if (tp->precision != GM_PRECISION_F64 && tp->precision != GM_PRECISION_F32_EMISSIVITY)
         return fail(GM_EINVAL, "precision %d", tp->precision);
@@ -630,6 +655,10 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     bool any = false;
     for (auto &I : c->inst) any |= I.pending;
     if (!any) return fail(GM_ESTATE, "no superphotons made since the last track");
+    if (tp->bias_mode == GM_BIAS_LEARNED)
+        for (int i = 0; i < GM_MAX_INSTANCES; ++i)
+            if (c->inst[i].pending && (!c->inst[i].lnb.p || c->inst[i].lnb_n < 2))
+                return fail(GM_ESTATE, "instance %d has no learned bias table", i);
     if (tp->scattering) {
         s = ensure_sigma_hot(c);
         if (s != GM_OK) return s;
@@ -780,6 +809,158 @@ gm_status gm_eval_G(gm_ctx *c, const double *hx, double *hy, int n)
     dx.release();
     dy.release();
     if (e != hipSuccess) return fail(GM_EDEVICE, "eval_G: %s", hipGetErrorString(e));
+    return GM_OK;
+}
+
+gm_status gm_set_event_log(gm_ctx *c, void *buf, uint64_t capacity)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (buf && capacity == 0) return fail(GM_EINVAL, "zero capacity");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    c->evlog = (EventRec *)buf;
+    c->evlog_cap = buf ? capacity : 0;
+    HIPCHK(hipMemsetAsync(c->evlog_n.p, 0, sizeof(unsigned long long), c->stream));
+    return GM_OK;
+}
+
+gm_status gm_event_count(gm_ctx *c, uint64_t *n)
+{
+    if (!c || !n) return fail(GM_EINVAL, "NULL argument");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    unsigned long long v = 0;
+    HIPCHK(hipMemcpyAsync(&v, c->evlog_n.p, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *n = v;
+    return GM_OK;
+}
+
+gm_status gm_set_bias_table(gm_ctx *c, int instance, const double *ln_b, int n_eps, double ln_eps_lo,
+                            double ln_eps_hi)
+{
+    if (!c || !ln_b) return fail(GM_EINVAL, "NULL argument");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    Instance &I = c->inst[instance];
+    if (!I.loaded) return fail(GM_ESTATE, "instance %d has no zones", instance);
+    if (n_eps < 2 || n_eps > 4096 || !(ln_eps_hi > ln_eps_lo)) return fail(GM_EINVAL, "bad bias table shape");
+    const size_t n = (size_t)I.nz * n_eps;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(ln_b[i])) return fail(GM_EINVAL, "bias table entry %zu not finite", i);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    if (I.lnb.ensure(n) != hipSuccess) return fail(GM_ENOMEM, "bias table");
+    HIPCHK(hipMemcpyAsync(I.lnb.p, ln_b, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    I.lnb_n = n_eps;
+    I.lnb_lo = ln_eps_lo;
+    I.lnb_hi = ln_eps_hi;
+    return GM_OK;
+}
+
+static gm_status mlp_buffers(gm_ctx *c)
+{
+    if (c->mlp_p.ensure(kMlpParams) != hipSuccess || c->mlp_m.ensure(kMlpParams) != hipSuccess ||
+        c->mlp_v.ensure(kMlpParams) != hipSuccess || c->mlp_g.ensure(kMlpParams + 1) != hipSuccess ||
+        c->mlp_pb.ensure(kMlpBf16) != hipSuccess)
+        return fail(GM_ENOMEM, "network buffers");
+    return GM_OK;
+}
+
+gm_status gm_mlp_set_params(gm_ctx *c, const float *params)
+{
+    if (!c || !params) return fail(GM_EINVAL, "NULL argument");
+    for (int i = 0; i < kMlpParams; ++i)
+        if (!std::isfinite(params[i])) return fail(GM_EINVAL, "parameter %d not finite", i);
+    gm_status s = set_device(c);
+    if (s == GM_OK) s = mlp_buffers(c);
+    if (s != GM_OK) return s;
+    HIPCHK(hipMemcpyAsync(c->mlp_p.p, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemsetAsync(c->mlp_m.p, 0, kMlpParams * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(c->mlp_v.p, 0, kMlpParams * sizeof(float), c->stream));
+    mlp_sync_bf16_kernel<<<(kMlpBf16 + 255) / 256, 256, 0, c->stream>>>(c->mlp_p.p, c->mlp_pb.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->mlp_t = 0;
+    c->mlp_ready = true;
+    return GM_OK;
+}
+
+gm_status gm_mlp_get_params(gm_ctx *c, float *params)
+{
+    if (!c || !params) return fail(GM_EINVAL, "NULL argument");
+    if (!c->mlp_ready) return fail(GM_ESTATE, "network parameters not set");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    HIPCHK(hipMemcpyAsync(params, c->mlp_p.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_mlp_forward(gm_ctx *c, const float *X, int64_t n, float *Y)
+{
+    if (!c || (n > 0 && (!X || !Y)) || n < 0) return fail(GM_EINVAL, "bad argument");
+    if (!c->mlp_ready) return fail(GM_ESTATE, "network parameters not set");
+    if (n == 0) return GM_OK;
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    MlpArgs M{};
+    M.X = X; M.Y = Y; M.n = n; M.P = c->mlp_p.p; M.Pb = c->mlp_pb.p;
+    const long long rows_per_block = 16LL * kMlpWaves;
+    mlp_forward_kernel<<<(unsigned)((n + rows_per_block - 1) / rows_per_block), 64 * kMlpWaves, 0, c->stream>>>(M);
+    HIPCHK(hipGetLastError());
+    return GM_OK;
+}
+
+// Gradient (and loss) of the weighted squared loss over n rows into mlp_g.
+static gm_status mlp_gradient(gm_ctx *c, const float *X, const float *T, const float *C, int64_t n)
+{
+    const long long nb = (n + kMlpGradRows - 1) / kMlpGradRows;
+    if (c->mlp_gpart.ensure((size_t)nb * (kMlpParams + 1)) != hipSuccess) return fail(GM_ENOMEM, "gradient partials");
+    MlpArgs M{};
+    M.X = X; M.T = T; M.C = C; M.n = n; M.P = c->mlp_p.p; M.Pb = c->mlp_pb.p;
+    M.gpart = c->mlp_gpart.p; M.loss_scale = 1.0f;
+    mlp_grad_kernel<<<(unsigned)nb, 64 * kMlpGradWaves, 0, c->stream>>>(M);
+    HIPCHK(hipGetLastError());
+    mlp_reduce_kernel<<<(kMlpParams + 1 + 255) / 256, 256, 0, c->stream>>>(c->mlp_gpart.p, (int)nb, c->mlp_g.p);
+    HIPCHK(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status gm_mlp_grad(gm_ctx *c, const float *X, const float *T, const float *C, int64_t n, float *grad,
+                      float *loss)
+{
+    if (!c || !X || !T || !C || n <= 0 || n > (1LL << 31)) return fail(GM_EINVAL, "bad argument");
+    if (!c->mlp_ready) return fail(GM_ESTATE, "network parameters not set");
+    gm_status s = set_device(c);
+    if (s == GM_OK) s = mlp_gradient(c, X, T, C, n);
+    if (s != GM_OK) return s;
+    if (grad) HIPCHK(hipMemcpyAsync(grad, c->mlp_g.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (loss) HIPCHK(hipMemcpyAsync(loss, c->mlp_g.p + kMlpParams, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_mlp_train_step(gm_ctx *c, const float *X, const float *T, const float *C, int64_t n, float lr,
+                            float *loss)
+{
+    if (!c || !X || !T || !C || n <= 0 || n > (1LL << 31) || !(lr > 0.0f)) return fail(GM_EINVAL, "bad argument");
+    if (!c->mlp_ready) return fail(GM_ESTATE, "network parameters not set");
+    gm_status s = set_device(c);
+    if (s == GM_OK) s = mlp_gradient(c, X, T, C, n);
+    if (s != GM_OK) return s;
+    c->mlp_t += 1;
+    AdamArgs A{};
+    A.P = c->mlp_p.p; A.m = c->mlp_m.p; A.v = c->mlp_v.p; A.g = c->mlp_g.p; A.Pb = c->mlp_pb.p;
+    A.lr = lr; A.beta1 = 0.9f; A.beta2 = 0.999f; A.eps = 1e-8f;
+    A.bc1 = (float)(1.0 - std::pow(0.9, (double)c->mlp_t));
+    A.bc2 = (float)(1.0 - std::pow(0.999, (double)c->mlp_t));
+    mlp_adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, c->stream>>>(A);
+    HIPCHK(hipGetLastError());
+    if (loss) {
+        HIPCHK(hipMemcpyAsync(loss, c->mlp_g.p + kMlpParams, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
     return GM_OK;
 }
 

@@ -30,6 +30,17 @@ struct PhotonQ {
     int32_t *n_sc, *zone;
 };
 
+// One scattering event of the event log (training records of the learned
+// form): the child's stream, the zone and the incoming photon's fluid-frame
+// energy at the event, the child's weight and the event position.  64 bytes.
+struct EventRec {
+    uint32_t s0, s1, s2;
+    int32_t zone;
+    double eps, w_child;
+    double x[3];
+    double pad;
+};
+
 struct TraceRec {
     uint32_t s0, s1, s2;
     int32_t n_sc, kind, i_nu, i_theta;
@@ -81,10 +92,17 @@ struct TArgs {
     double inv_sc[3];
     // scheduling: claim new photons once this many lanes of a wave idle
     int refill_min;
-    // optional trace
+    // optional trace and scattering-event log
     TraceRec *trace;
     unsigned long long *trace_n;
     unsigned long long trace_cap;
+    EventRec *evlog;
+    unsigned long long *evlog_n;
+    unsigned long long evlog_cap;
+    // learned bias: ln b per zone on ln(eps) nodes (bias mode 3)
+    const double *lnb;
+    int lnb_n;
+    double lnb_lo, lnb_inv_d;
 };
 
 struct Coef {
@@ -154,14 +172,25 @@ GM_D int zone_ks(const TArgs &A, double x1, double x2, double x3)
     return ((int)f1 * A.n[1] + (int)f2) * A.n[2] + (int)f3;
 }
 
-// Bias of a point (Scattering section): constant, Theta_e^2-scaled, or
-// growing with the generation and falling with the density; clamped.
-GM_D double bias_at(const TArgs &A, double theta, double ne, int n_sc)
+// Bias of a point (Scattering section): constant, Theta_e^2-scaled,
+// growing with the generation and falling with the density, or learned
+// (ln b of the zone interpolated linearly in ln eps on its node table);
+// clamped to [1, bias_max].  Any b >= 1 keeps the estimator unbiased: the
+// child carries w/b, the parent keeps w(1 - 1/b).
+GM_D double bias_at(const TArgs &A, int z, double theta, double ne, int n_sc, double eps)
 {
     double b;
     if (A.bias_mode == 0) b = A.bias_value;
     else if (A.bias_mode == 1) b = A.bias_value * theta * theta;
-    else b = (double)((n_sc + 1) * (n_sc + 1)) / (ne * kSigT * A.bias_value * A.L_unit_cm);
+    else if (A.bias_mode == 2) b = (double)((n_sc + 1) * (n_sc + 1)) / (ne * kSigT * A.bias_value * A.L_unit_cm);
+    else {
+        double a = (log(eps) - A.lnb_lo) * A.lnb_inv_d;
+        a = fmin(fmax(a, 0.0), (double)(A.lnb_n - 1));
+        int i = min((int)a, A.lnb_n - 2);
+        double f = a - (double)i;
+        const double *t = A.lnb + (size_t)z * A.lnb_n + i;
+        b = exp((1.0 - f) * t[0] + f * t[1]);
+    }
     return fmin(fmax(b, 1.0), A.bias_max);
 }
 
@@ -200,7 +229,7 @@ GM_D Coef coefficients_at64(const TArgs &A, int z, const double g[4][4], const d
         }
     }
     if (A.scattering) c.nus = nuf * ne * kSigT * sigma_hot(A.sh, zr[Z_LNTH], ef);
-    c.b = bias_at(A, zr[Z_TH], ne, n_sc);
+    c.b = bias_at(A, z, zr[Z_TH], ne, n_sc, ef);
     return c;
 }
 
@@ -236,7 +265,7 @@ GM_D Coef coefficients_at32(const TArgs &A, int z, const double g[4][4], const d
     }
     if (A.scattering)
         c.nus = (double)__expf(lnnu + zf[F_LNNESIG] + ln_sigma_hot32(A.sh32, zf[F_LNTH], __logf((float)ef)));
-    c.b = bias_at(A, (double)zf[F_TH], (double)nef, n_sc);
+    c.b = bias_at(A, z, (double)zf[F_TH], (double)nef, n_sc, ef);
     return c;
 }
 
@@ -630,6 +659,20 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
     lds_flush(A, B, nspec);
 }
 
+// Append a scattering event to the log (when one is set and has room).
+GM_D void log_event(const TArgs &A, const Rng &child, int z, double eps, double w_child, const double *x)
+{
+    unsigned long long i = atomicAdd(A.evlog_n, 1ull);
+    if (i >= A.evlog_cap) return;
+    EventRec &e = A.evlog[i];
+    e.s0 = child.s0; e.s1 = child.s1; e.s2 = child.s2;
+    e.zone = z;
+    e.eps = eps;
+    e.w_child = w_child;
+    e.x[0] = x[0]; e.x[1] = x[1]; e.x[2] = x[2];
+    e.pad = 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Scattering events -> child photons (Scattering section), one thread per
 // event of the generation just tracked.  Draws come from the child's stream
@@ -671,6 +714,7 @@ __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs A)
 #pragma unroll
             for (int m = 0; m < 4; ++m) kc[m] = ks[m];
         }
+        if (A.evlog && z >= 0) log_event(A, r, z, -dot4(g, ks, A.zrec + (size_t)z * Z_STRIDE + Z_U0), wchild, x + 1);
         lds_add(&B.ledger[L_E_COMPTON], wchild * (e_inf(g, kc) - e_inf(g, ks)) * kMeC2);
         lds_inc(&B.stats[S_SCATTER], 1);
         lds_inc(&B.stats[S_CHILDREN], 1);

@@ -401,6 +401,10 @@ __global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs A)
             double u[4], bh[4], e[4][4];
             bool has_b = fluid_frame(zr, g, u, bh);
             double eps = scatter_tetrad(g, u, bh, has_b, ks, e);
+            if (A.evlog) {
+                double xe[3] = {Q.x[0][i], Q.x[1][i], Q.x[2][i]};
+                log_event(A, r, z, eps, wchild, xe);
+            }
             double kf[4];
             ScatterCount cnt{0, 0};
             scatter_in_frame(r, A.key0, A.key1, zr[Z_TH], eps, kf, cnt);

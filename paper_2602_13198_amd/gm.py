@@ -34,11 +34,20 @@ TRACE_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("n_sc", "<
                         ("x", "<f8", 4), ("k", "<f8", 4)])
 TRACE_BYTES = 112
 
+EVENT_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("zone", "<i4"),
+                        ("eps", "<f8"), ("w_child", "<f8"), ("x", "<f8", 3), ("pad", "<f8")])
+EVENT_BYTES = 64
+MLP_PARAMS = 4738
+BIAS_LEARNED = 3
+PRECISION_F64, PRECISION_F32_EMISSIVITY = 0, 1
+
 # Every function the header declares (checked by the CPU symbol test).
 EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make_superphotons",
            "gm_track_scatter", "gm_read_spectrum", "gm_read_emission", "gm_set_trace",
            "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G", "gm_set_timing",
-           "gm_read_timing", "gm_set_tuning"]
+           "gm_read_timing", "gm_set_tuning", "gm_mlp_set_params", "gm_mlp_get_params",
+           "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_set_bias_table",
+           "gm_set_event_log", "gm_event_count"]
 
 
 class GmGrid(C.Structure):
@@ -95,6 +104,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_set_timing": (i, [vp, i]),
         "gm_read_timing": (i, [vp, dp, C.POINTER(C.c_uint64)]),
         "gm_set_tuning": (i, [vp, i, i]),
+        "gm_mlp_set_params": (i, [vp, vp]),
+        "gm_mlp_get_params": (i, [vp, vp]),
+        "gm_mlp_forward": (i, [vp, vp, C.c_int64, vp]),
+        "gm_mlp_grad": (i, [vp, vp, vp, vp, C.c_int64, vp, vp]),
+        "gm_mlp_train_step": (i, [vp, vp, vp, vp, C.c_int64, C.c_float, vp]),
+        "gm_set_bias_table": (i, [vp, i, dp, i, C.c_double, C.c_double]),
+        "gm_set_event_log": (i, [vp, vp, u64]),
+        "gm_event_count": (i, [vp, C.POINTER(C.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -251,6 +268,72 @@ class Context:
         m = min(int(n.value), cap)
         raw = self._trace[: m * TRACE_BYTES].cpu().numpy()
         return raw.view(TRACE_DTYPE).copy()
+
+    def set_event_log(self, capacity: int):
+        if capacity <= 0:
+            self._evlog = None
+            _check(load_library().gm_set_event_log(self._h, None, 0))
+            return
+        self._evlog = torch.empty(capacity * EVENT_BYTES, dtype=torch.uint8,
+                                  device="cuda:%d" % self.device)
+        _check(load_library().gm_set_event_log(self._h, C.c_void_p(self._evlog.data_ptr()), int(capacity)))
+
+    def read_event_log(self) -> np.ndarray:
+        n = C.c_uint64(0)
+        _check(load_library().gm_event_count(self._h, C.byref(n)))
+        cap = self._evlog.numel() // EVENT_BYTES
+        m = min(int(n.value), cap)
+        raw = self._evlog[: m * EVENT_BYTES].cpu().numpy()
+        return raw.view(EVENT_DTYPE).copy()
+
+    # ---- learned form: the network ----
+    def mlp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        _check(load_library().gm_mlp_set_params(self._h, C.c_void_p(p.ctypes.data)))
+
+    def mlp_get_params(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, np.float32)
+        _check(load_library().gm_mlp_get_params(self._h, C.c_void_p(p.ctypes.data)))
+        return p
+
+    @staticmethod
+    def _dev_rows(a, width):
+        t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)) if not torch.is_tensor(a) else a
+        t = t.to(device="cuda", dtype=torch.float32).contiguous()
+        assert t.dim() == 2 and t.shape[1] == width
+        return t
+
+    def mlp_forward(self, X):
+        """X: [n][8] (numpy or torch); returns a device tensor [n][2]."""
+        Xd = self._dev_rows(X, 8)
+        Y = torch.empty((Xd.shape[0], 2), dtype=torch.float32, device=Xd.device)
+        _check(load_library().gm_mlp_forward(self._h, C.c_void_p(Xd.data_ptr()), int(Xd.shape[0]),
+                                             C.c_void_p(Y.data_ptr())))
+        return Y
+
+    def mlp_grad(self, X, T, Cw):
+        Xd, Td, Cd = self._dev_rows(X, 8), self._dev_rows(T, 2), self._dev_rows(Cw, 2)
+        g = np.zeros(MLP_PARAMS, np.float32)
+        L = np.zeros(1, np.float32)
+        _check(load_library().gm_mlp_grad(self._h, C.c_void_p(Xd.data_ptr()), C.c_void_p(Td.data_ptr()),
+                                          C.c_void_p(Cd.data_ptr()), int(Xd.shape[0]),
+                                          C.c_void_p(g.ctypes.data), C.c_void_p(L.ctypes.data)))
+        return g, float(L[0])
+
+    def mlp_train_step(self, Xd, Td, Cd, lr: float, want_loss: bool = False):
+        """One Adam step on device tensors (see _dev_rows); returns the loss
+        before the step when asked (synchronises then)."""
+        L = np.zeros(1, np.float32)
+        _check(load_library().gm_mlp_train_step(self._h, C.c_void_p(Xd.data_ptr()), C.c_void_p(Td.data_ptr()),
+                                                C.c_void_p(Cd.data_ptr()), int(Xd.shape[0]), float(lr),
+                                                C.c_void_p(L.ctypes.data) if want_loss else None))
+        return float(L[0]) if want_loss else None
+
+    def set_bias_table(self, instance: int, ln_b, ln_eps_lo: float, ln_eps_hi: float):
+        t = np.ascontiguousarray(ln_b, dtype=np.float64)
+        _check(load_library().gm_set_bias_table(self._h, int(instance), _dp(t), int(t.shape[1]),
+                                                float(ln_eps_lo), float(ln_eps_hi)))
 
     def sigma_hot_table(self) -> np.ndarray:
         t = np.zeros((64, 256))

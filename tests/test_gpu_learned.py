@@ -1,0 +1,146 @@
+"""The learned form on the GPU: the matrix-core network kernels against the
+FP64 oracle network (BF16 operand rounding emulated in the oracle), training
+on the library's kernels, and the learned bias leaving the spectrum
+unbiased."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from paper_2602_13198_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_13198_amd import gm as _gm
+    _gm.load_library()
+    return _gm
+
+
+@pytest.fixture(scope="module")
+def ctx(gm):
+    c = gm.Context(0)
+    yield c
+    c.close()
+
+
+def forward_bf16(p, X):
+    """Oracle forward with the operands of every product rounded to BF16, as
+    the matrix cores see them (accumulation and biases in full precision)."""
+    Wd = OM.unpack(p)
+    x = OM.bf16(X[:, :6])
+    h1 = np.tanh(x @ OM.bf16(Wd["W1"]) + Wd["b1"])
+    h2 = np.tanh(OM.bf16(h1) @ OM.bf16(Wd["W2"]) + Wd["b2"])
+    return OM.bf16(h2) @ OM.bf16(Wd["W3"]) + Wd["b3"]
+
+
+def _case(seed, n):
+    rng = np.random.default_rng(seed)
+    p = OM.init(seed)
+    p[OM.N_PARAMS - 2:] = [0.3, -0.2]
+    X = np.zeros((n, 8))
+    X[:, :6] = rng.standard_normal((n, 6))
+    T = rng.standard_normal((n, 2))
+    C = rng.uniform(0.5, 1.0, (n, 2)) / n
+    return p.astype(np.float32).astype(np.float64), X, T, C
+
+
+@pytest.mark.parametrize("n", [1, 16, 1000, 4097])
+def test_forward_matches_oracle(ctx, n):
+    p, X, _, _ = _case(1, n)
+    ctx.mlp_set_params(p)
+    y = ctx.mlp_forward(X).cpu().numpy()
+    ref = forward_bf16(p, X)
+    assert np.all(np.abs(y - ref) <= 2e-2 * (np.abs(ref) + 0.1)), np.max(np.abs(y - ref))
+    # and close to the exact FP64 network
+    y64, _ = OM.forward(p, X)
+    assert np.max(np.abs(y - y64)) < 0.1 * max(1.0, np.max(np.abs(y64)))
+
+
+@pytest.mark.parametrize("n", [16, 333, 4096])
+def test_gradient_matches_oracle(ctx, n):
+    p, X, T, C = _case(2, n)
+    ctx.mlp_set_params(p)
+    g, L = ctx.mlp_grad(X, T, C)
+    g64, L64 = OM.grad(p, X, T, C)
+    assert abs(L - L64) <= 3e-2 * L64
+    rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    print("n=%d gradient relative error %.3e" % (n, rel))
+    assert rel < 5e-2
+    # per block of parameters too
+    for name, (a, b) in {"W1": (0, 384), "W2": (448, 4544), "W3": (4608, 4736)}.items():
+        r = np.linalg.norm(g[a:b] - g64[a:b]) / np.linalg.norm(g64[a:b])
+        assert r < 8e-2, (name, r)
+
+
+def test_training_reduces_loss(ctx):
+    """A smooth regression target: 400 Adam steps on the library's kernels
+    cut the loss by more than 10x; the oracle's FP64 Adam on the same data
+    reaches a comparable loss."""
+    import torch
+    rng = np.random.default_rng(3)
+    n = 4096
+    X = np.zeros((n, 8), np.float32)
+    X[:, :6] = rng.standard_normal((n, 6))
+    T = np.stack([np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2], np.tanh(X[:, 3] - X[:, 4])], 1).astype(np.float32)
+    C = np.full((n, 2), 1.0 / n, np.float32)
+    p0 = OM.init(4)
+    ctx.mlp_set_params(p0)
+    Xd, Td, Cd = (torch.as_tensor(a, device="cuda") for a in (X, T, C))
+    L0 = ctx.mlp_train_step(Xd, Td, Cd, 3e-3, want_loss=True)
+    for _ in range(398):
+        ctx.mlp_train_step(Xd, Td, Cd, 3e-3)
+    L1 = ctx.mlp_train_step(Xd, Td, Cd, 3e-3, want_loss=True)
+    assert L1 < 0.1 * L0, (L0, L1)
+    p, m, v = p0.copy(), np.zeros(OM.N_PARAMS), np.zeros(OM.N_PARAMS)
+    for t in range(1, 400):
+        g, _ = OM.grad(p, X, T, C)
+        p, m, v = OM.adam_step(p, m, v, g, t, 3e-3)
+    Lo = OM.loss(p, X, T, C)
+    print("loss: start %.4f  gpu after 399 steps %.4f  oracle %.4f" % (L0, L1, Lo))
+    assert L1 < 3 * Lo + 1e-3
+
+
+def test_learned_bias_keeps_the_spectrum(gm, ctx):
+    """Scattering sphere tau_T = 0.1: a network trained on plain-run records
+    sets the bias per (zone, eps); the spectrum agrees with the plain
+    method's in every bin holding >= 1e3 superphotons in both, within 5
+    combined standard deviations (different seeds)."""
+    from paper_2602_13198_amd.learned import LearnedBias, collect_records
+    wl = W.scattering_sphere(0.1, n_target=2e5, seed=0)
+    c = gm.Context(0)
+    c.load_zones(wl)
+    X, T = collect_records(c, wl, 0, 2, 500)
+    print("records %d, dropped as non-finite %d; X range %s .. %s; T range %s .. %s"
+          % (len(X), getattr(collect_records, "dropped", 0), X[:, :6].min(0), X[:, :6].max(0),
+             T.min(0), T.max(0)))
+    assert len(X) > 10000
+    assert getattr(collect_records, "dropped", 0) <= 1e-3 * len(X)      # subnormal child weights
+    lb = LearnedBias(seed=1)
+    hist = lb.fit(c, X, T, steps=300, batch=8192, lr=3e-3)
+    assert hist[-1][1] < hist[0][1]
+    tab = lb.apply(c, wl, 0, b_plain=10.0, b_max=1e3)
+    assert np.all(np.isfinite(tab)) and tab.min() >= 0.0
+    def spec(track, seeds):
+        tot = 0
+        for s in seeds:
+            c.make_superphotons(dict(wl.emit, seed=s))
+            c.track_scatter(track)
+        sp, _ = c.read_spectrum(0, reset=True)
+        return sp, len(seeds)
+    s_p, k = spec(wl.track, range(1000, 1010))
+    s_l, _ = spec(dict(wl.track, bias_mode=gm.BIAS_LEARNED, bias_max=1e3), range(2000, 2010))
+    use = (s_p[..., 2] >= 1000) & (s_l[..., 2] >= 1000)
+    assert use.sum() > 50
+    a, b = s_p[..., 0][use] / k, s_l[..., 0][use] / k
+    sa, sb = np.sqrt(s_p[..., 1][use]) / k, np.sqrt(s_l[..., 1][use]) / k
+    z = np.abs(a - b) / np.sqrt(sa ** 2 + sb ** 2)
+    print("learned vs plain: %d bins, max |z| %.2f, mean z^2 %.2f" % (use.sum(), z.max(), np.mean(z ** 2)))
+    assert z.max() < 5.0 and np.mean(z ** 2) < 2.0
+    c.close()
