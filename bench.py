@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--track-waves", type=int, default=0,
                     help="waves/SIMD variant of the tracker (2-4); 0 = autotune")
     ap.add_argument("--refill-min", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=64,
+                    help="instances per shared launch with --track-waves (1 = one at a time)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--ttx-seeds", type=int, default=3,
@@ -148,14 +150,15 @@ def main():
     ctx = gm.Context(0)
     for i, wl in enumerate(wls):
         ctx.load_zones(wl, i)
+        ctx.set_instance_bias(i, wl.track)          # b = 1/tau_T per instance
     torch.cuda.synchronize()
 
     def one_step(seed, precision=0):
-        tot = None
+        # every instance makes its roots, then one track call runs them all
+        # (shared launches up to the batch limit)
         for i, wl in enumerate(wls):
             ctx.make_superphotons(dict(wl.emit, seed=seed), instance=i)
-            st = ctx.track_scatter(dict(wl.track, precision=precision))
-            tot = st if tot is None else tot + st
+        tot = ctx.track_scatter(dict(wls[0].track, precision=precision))
         for i in range(len(wls)):
             ctx.read_spectrum(i, reset=True)
         return tot
@@ -169,15 +172,17 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    tuning = {"track_waves": args.track_waves, "refill_min": args.refill_min, "autotuned": False}
+    tuning = {"track_waves": args.track_waves, "refill_min": args.refill_min,
+              "batch": args.batch, "autotuned": False}
     if args.track_waves:
         ctx.set_tuning(args.track_waves, args.refill_min)
+        ctx.set_batch(args.batch)
     else:
         from paper_2602_13198_amd.autotune import autotune
-        (w_, r_), table = autotune(ctx, one_step,
-                                   log=lambda m: print(m, file=sys.stderr, flush=True))
-        tuning = {"track_waves": w_, "refill_min": r_, "autotuned": True,
-                  "candidates": [[a, b, round(c, 3), round(d, 3)] for a, b, c, d in table]}
+        (w_, r_, b_), table = autotune(ctx, one_step,
+                                       log=lambda m: print(m, file=sys.stderr, flush=True))
+        tuning = {"track_waves": w_, "refill_min": r_, "batch": b_, "autotuned": True,
+                  "candidates": [[a, b, c, round(d, 3), round(e, 3)] for a, b, c, d, e in table]}
     for w in range(args.warmup):
         one_step(1000 + w)
     torch.cuda.synchronize()
@@ -275,9 +280,11 @@ def main():
         lb.apply(ctx, wl, iw, b_plain=wl.track["bias_value"], b_max=1e3)
         t_table = time.perf_counter() - tt1
         learned_over = dict(bias_mode=3, bias_max=1e3)
+        ctx.set_instance_bias(iw, None)                # the learned table decides
         runs_l = [CV.time_to_error(ctx, wl, iw, L_ref, mask, 400000 + 1000 * k, wl.emit["n_target"],
                                    track_overrides=learned_over) for k in range(args.ttx_seeds)]
         secs_l = [r["seconds"] for r in runs_l if r["seconds"] is not None]
+        ctx.set_instance_bias(iw, wl.track)
         med_p = float(np.median(secs)) if len(secs) == len(runs) else None
         med_l = float(np.median(secs_l)) + t_table if len(secs_l) == len(runs_l) else None
         ttx = {

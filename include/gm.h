@@ -225,6 +225,20 @@ gm_status gm_eval_G(gm_ctx *ctx, const double *host_x, double *host_out, int n);
  * the number of idle lanes at which a wave claims new photons. */
 gm_status gm_set_tuning(gm_ctx *ctx, int track_waves, int refill_min);
 
+/* Instances per launch (1..GM_MAX_INSTANCES, default all): gm_track_scatter
+ * tracks the pending instances of one metric together -- one birth launch
+ * and per generation one tracking and one scattering launch over all their
+ * photons -- in groups of at most this many whose per-block tallies fit
+ * the 64 KiB LDS budget.  Results do not depend on it. */
+gm_status gm_set_batch(gm_ctx *ctx, int max_instances);
+
+/* Scattering bias of one instance (GM_BIAS_*, value, maximum), overriding
+ * the bias of the track parameters for it, so that instances with
+ * different biases share launches; bias_mode < 0 removes the override.
+ * Scattering section of the paper (bias b >= 1). */
+gm_status gm_set_instance_bias(gm_ctx *ctx, int instance, int bias_mode, double bias_value,
+                               double bias_max);
+
 /* Event timing of the tracking kernel: with timing enabled, every launch of
  * the tracking kernel is bracketed by HIP events on the context's stream.
  * gm_read_timing returns the summed event durations (ms) and the number of

@@ -1,27 +1,30 @@
-"""Launch-parameter autotuner for the tracking kernel.
+"""Launch-parameter autotuner for the transport launches.
 
 Results never depend on the tuning (photon histories are keyed by their
 random streams), so the tuner only compares time: for each candidate
-(waves per SIMD of the compiled tracker variant, idle-lane refill threshold)
-it runs the caller's step once untimed and `repeats` times timed, reading the
-summed tracking-kernel event time from the library, and keeps the fastest.
+(waves per SIMD of the compiled tracker variant, idle-lane refill threshold,
+instances per shared launch) it runs the caller's step once untimed and
+`repeats` times timed, and keeps the one with the shortest wall time; the
+summed tracking-kernel event time is logged beside it.
 """
 from __future__ import annotations
 
 import itertools
 import time
 
-DEFAULT_CANDIDATES = list(itertools.product((2, 3, 4), (4, 8, 16, 32)))
+DEFAULT_CANDIDATES = list(itertools.product((2, 3, 4), (8, 16, 32), (1, 64)))
 
 
 def autotune(ctx, step, candidates=None, repeats: int = 1, log=None):
     """ctx: gm.Context; step(seed) runs one full make/track/read step.
-    Returns (best (waves, refill), list of (waves, refill, track_ms, wall_ms))."""
+    Returns (best (waves, refill, batch), list of (waves, refill, batch,
+    track_ms, wall_ms))."""
     import torch
     table = []
     seed = 900000
-    for waves, refill in (candidates or DEFAULT_CANDIDATES):
+    for waves, refill, batch in (candidates or DEFAULT_CANDIDATES):
         ctx.set_tuning(waves, refill)
+        ctx.set_batch(batch)
         step(seed)
         seed += 1
         torch.cuda.synchronize()
@@ -34,9 +37,11 @@ def autotune(ctx, step, candidates=None, repeats: int = 1, log=None):
         wall = (time.perf_counter() - t0) * 1e3 / repeats
         ms, _ = ctx.read_timing()
         ctx.set_timing(False)
-        table.append((waves, refill, ms / repeats, wall))
+        table.append((waves, refill, batch, ms / repeats, wall))
         if log:
-            log("tune waves=%d refill=%d: track %.2f ms, step %.2f ms" % (waves, refill, ms / repeats, wall))
-    best = min(table, key=lambda r: r[3])
+            log("tune waves=%d refill=%d batch=%d: track %.2f ms, step %.2f ms"
+                % (waves, refill, batch, ms / repeats, wall))
+    best = min(table, key=lambda r: r[4])
     ctx.set_tuning(best[0], best[1])
-    return (best[0], best[1]), table
+    ctx.set_batch(best[2])
+    return (best[0], best[1], best[2]), table

@@ -87,6 +87,9 @@ struct Instance {
     int n_nu = 0, n_theta = 0;
     DevBuf<double> spec, ledger;
     DevBuf<unsigned long long> stats;
+    // per-instance bias overriding the track call's (bias_mode < 0: none)
+    int bias_mode = -1;
+    double bias_value = 0.0, bias_max = 0.0;
     // learned bias table ln b [nz][lnb_n]
     DevBuf<double> lnb;
     int lnb_n = 0;
@@ -111,13 +114,16 @@ struct gm_ctx {
     unsigned long long child_cap = 0;
     DevBuf<double> qd[2][13];
     DevBuf<uint32_t> qu[2][4];
-    DevBuf<int32_t> qi[2][2];
+    DevBuf<int32_t> qi[2][3];
     DevBuf<unsigned long long> ctr;             // [gen][2]: count, cursor
     DevBuf<int> flags;                          // [0] overflow, [1] status
     // tuning of the tracking launch (waves per SIMD of the compiled variant,
-    // idle lanes before a wave claims new photons)
+    // idle lanes before a wave claims new photons, instances per launch)
     int track_waves = 2;
     int refill_min = 8;
+    int max_batch = GM_MAX_INSTANCES;
+    DevBuf<TArgs> inst_args;
+    DevBuf<unsigned long long> root_off;
     // optional event timing of the tracking launches
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -236,6 +242,7 @@ gm_status gm_destroy(gm_ctx *c)
         I.tile.release(); I.roots.release(); I.spec.release(); I.ledger.release(); I.stats.release();
         I.lnb.release();
     }
+    c->inst_args.release(); c->root_off.release();
     c->mlp_p.release(); c->mlp_m.release(); c->mlp_v.release(); c->mlp_g.release();
     c->mlp_gpart.release(); c->mlp_pb.release(); c->evlog_n.release();
     c->gcheb.release(); c->sh_table.release(); c->sh_table32.release(); c->gl_x.release(); c->gl_w.release();
@@ -360,9 +367,16 @@ static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint
         I.tile.ensure((size_t)nz / kScanTile + 2) != hipSuccess || I.roots.ensure(2) != hipSuccess)
         return fail(GM_ENOMEM, "emission buffers");
     const double lnmin = std::log(p->nu_min), span = std::log(p->nu_max / p->nu_min);
-    std::vector<double> nus(nw);
-    for (int k = 0; k < nw; ++k) nus[k] = std::exp(lnmin + span * k / (nw - 1));
-    HIPCHK(hipMemcpyAsync(I.nu_nodes.p, nus.data(), nw * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // the weight table, expected counts and rejection bounds depend on the
+    // zones and on everything in the parameters but the seed: reuse them
+    const bool reuse = I.made && I.ep.n_target == p->n_target && I.ep.nu_min == p->nu_min &&
+                       I.ep.nu_max == p->nu_max && I.ep.n_wnodes == p->n_wnodes &&
+                       I.ep.w_floor_rel == p->w_floor_rel;
+    if (!reuse) {
+        std::vector<double> nus(nw);
+        for (int k = 0; k < nw; ++k) nus[k] = std::exp(lnmin + span * k / (nw - 1));
+        HIPCHK(hipMemcpyAsync(I.nu_nodes.p, nus.data(), nw * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    }
     EmitArgs E;
     E.zrec = I.zrec.p; E.vol = I.vol.p; E.emits = I.emits.p; E.nu_nodes = I.nu_nodes.p;
     E.nz = nz; E.nw = nw; E.G = c->G; E.partial = I.partial.p; E.n_blocks = nblk;
@@ -370,9 +384,14 @@ static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint
     E.w_floor_rel = p->w_floor_rel; E.nbar = I.nbar.p; E.fmax = I.fmax.p; E.count = I.count.p;
     E.key0 = (uint32_t)p->seed; E.key1 = (uint32_t)(p->seed >> 32); E.inst = instance;
     E.status = c->flags.p + 1;
-    phi_partial_kernel<<<nblk, 256, 0, c->stream>>>(E);
-    weight_table_kernel<<<1, 256, 0, c->stream>>>(E);
-    count_kernel<<<nblk, 256, 0, c->stream>>>(E);
+    if (reuse) {
+        recount_kernel<<<nblk, 256, 0, c->stream>>>(E);
+    } else {
+        I.made = false;          // until this make succeeds, nothing is reusable
+        phi_partial_kernel<<<nblk, 256, 0, c->stream>>>(E);
+        weight_table_kernel<<<1, 256, 0, c->stream>>>(E);
+        count_kernel<<<nblk, 256, 0, c->stream>>>(E);
+    }
     const int ntile = (nz + kScanTile - 1) / kScanTile;
     scan_tiles_kernel<<<ntile, 256, 0, c->stream>>>(I.count.p, nz, I.tile.p);
     scan_sums_kernel<<<1, 256, 0, c->stream>>>(I.tile.p, ntile, I.offset.p + nz);
@@ -447,7 +466,7 @@ static PhotonQ queue(gm_ctx *c, int b)
     q.w = c->qd[b][7].p; q.wb = c->qd[b][8].p; q.x1 = c->qd[b][9].p;
     q.nua = c->qd[b][10].p; q.nus = c->qd[b][11].p; q.b = c->qd[b][12].p;
     q.s0 = c->qu[b][0].p; q.s1 = c->qu[b][1].p; q.s2 = c->qu[b][2].p; q.blk = c->qu[b][3].p;
-    q.n_sc = c->qi[b][0].p; q.zone = c->qi[b][1].p;
+    q.n_sc = c->qi[b][0].p; q.zone = c->qi[b][1].p; q.inst = c->qi[b][2].p;
     return q;
 }
 
@@ -490,9 +509,10 @@ __global__ void reset_counters_kernel(unsigned long long *ctr, int n, int *overf
     if (i == 0) *overflow = 0;
 }
 
-static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, std::vector<long long> &acc)
+// Tally buffers of an instance for a track call (allocated or reshaped when
+// needed; stats cleared).
+static gm_status prepare_instance(gm_ctx *c, Instance &I, const gm_track_params *tp)
 {
-    Instance &I = c->inst[ii];
     const size_t nspec = (size_t)tp->n_theta * tp->n_nu * 3;
     const bool reshape = I.spec.p && (I.n_nu != tp->n_nu || I.n_theta != tp->n_theta);
     if (reshape && I.dirty) return fail(GM_EINVAL, "tally shape changed without a reset read");
@@ -507,28 +527,14 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     I.n_theta = tp->n_theta;
     I.dirty = true;
     HIPCHK(hipMemsetAsync(I.stats.p, 0, S_N * sizeof(unsigned long long), c->stream));
+    return GM_OK;
+}
 
-    const size_t lds_track = (size_t)(L_N + S_N) * 8 + nspec * 8;
-    const size_t lds_small = (size_t)(L_N + S_N) * 8;
-    if (lds_track > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %zu bins exceeds the LDS tally", nspec / 3);
-    const bool kerr = I.grid.metric == GM_METRIC_KS_MKS;
-    const bool f32 = tp->precision == GM_PRECISION_F32_EMISSIVITY;
-    using KernelFn = void (*)(TArgs);
-    static const KernelFn track_fns[2][2][3] = {
-        {{track_kernel_flat<2, false>, track_kernel_flat<3, false>, track_kernel_flat<4, false>},
-         {track_kernel_flat<2, true>, track_kernel_flat<3, true>, track_kernel_flat<4, true>}},
-        {{track_kernel_ks<2, false>, track_kernel_ks<3, false>, track_kernel_ks<4, false>},
-         {track_kernel_ks<2, true>, track_kernel_ks<3, true>, track_kernel_ks<4, true>}}};
-    const KernelFn track_fn = track_fns[kerr][f32][c->track_waves - 2];
-    const KernelFn birth_fn = kerr ? (KernelFn)birth_kernel<KerrMKS, false>
-                                   : f32 ? (KernelFn)birth_kernel<Minkowski, true> : (KernelFn)birth_kernel<Minkowski, false>;
-    const KernelFn scatter_fn = kerr ? (KernelFn)scatter_kernel_ks
-                                     : f32 ? (KernelFn)scatter_kernel_flat<true> : (KernelFn)scatter_kernel_flat<false>;
-    int occ = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_fn, 256, lds_track));
-    occ = std::max(occ, 1);
-    const int grid = c->n_cu * occ;
-
+// The argument block of one instance (its geometry, plasma, emission and
+// tally pointers, plus the transport parameters shared by the launch).
+static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
+{
+    Instance &I = c->inst[ii];
     TArgs A{};
     A.zrec = I.zrec.p;
     A.zrec32 = I.zrec32.p;
@@ -560,10 +566,10 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     A.ln_nu_lo = std::log(tp->nu_lo);
     A.inv_dln_nu = 1.0 / (std::log(tp->nu_hi / tp->nu_lo) / tp->n_nu);
     A.scattering = tp->scattering;
-    A.bias_mode = tp->bias_mode;
+    A.bias_mode = I.bias_mode >= 0 ? I.bias_mode : tp->bias_mode;
     A.n_sc_max = tp->n_sc_max;
-    A.bias_value = tp->bias_value;
-    A.bias_max = tp->bias_max;
+    A.bias_value = I.bias_mode >= 0 ? I.bias_value : tp->bias_value;
+    A.bias_max = I.bias_mode >= 0 ? I.bias_max : tp->bias_max;
     A.step_h = tp->step_h;
     A.roulette_frac = tp->roulette_frac;
     A.roulette_p = tp->roulette_p;
@@ -593,37 +599,92 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
     A.inv_sc[0] = 1.0 / I.grid.dx[0];
     A.inv_sc[1] = 1.0 / I.grid.dx[1];
     A.inv_sc[2] = 1.0 / std::min(I.grid.dx[2], kPi * I.grid.dx[1]);
+    return A;
+}
+
+// Track the pending roots of a set of instances of one metric in shared
+// launches: one birth, and per generation one tracking and one scattering
+// launch over the photons of all of them (each photon carries its
+// instance), root ranges chunked by queue capacity.
+static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_track_params *tp,
+                             std::vector<long long> &acc)
+{
+    const int n_inst = (int)ids.size();
+    const size_t nspec = (size_t)tp->n_theta * tp->n_nu * 3;
+    const size_t lds_track = (size_t)n_inst * (L_N + S_N + nspec) * 8;
+    const size_t lds_small = (size_t)n_inst * (L_N + S_N) * 8;
+    const bool kerr = c->inst[ids[0]].grid.metric == GM_METRIC_KS_MKS;
+    const bool f32 = tp->precision == GM_PRECISION_F32_EMISSIVITY;
+    using KernelFn = void (*)(TArgs);
+#define GM_TRACK_VARIANTS(K, F, B) {K<2, F, B>, K<3, F, B>, K<4, F, B>}
+    static const KernelFn track_fns[2][2][2][3] = {
+        {{GM_TRACK_VARIANTS(track_kernel_flat, false, false), GM_TRACK_VARIANTS(track_kernel_flat, false, true)},
+         {GM_TRACK_VARIANTS(track_kernel_flat, true, false), GM_TRACK_VARIANTS(track_kernel_flat, true, true)}},
+        {{GM_TRACK_VARIANTS(track_kernel_ks, false, false), GM_TRACK_VARIANTS(track_kernel_ks, false, true)},
+         {GM_TRACK_VARIANTS(track_kernel_ks, true, false), GM_TRACK_VARIANTS(track_kernel_ks, true, true)}}};
+#undef GM_TRACK_VARIANTS
+    // one instance: the arguments travel as kernel arguments; several: per
+    // instance from device memory, one instance per pass of a wave
+    const KernelFn track_fn = track_fns[kerr][f32][n_inst > 1][c->track_waves - 2];
+    const KernelFn birth_fn = kerr ? (KernelFn)birth_kernel<KerrMKS, false>
+                                   : f32 ? (KernelFn)birth_kernel<Minkowski, true> : (KernelFn)birth_kernel<Minkowski, false>;
+    const KernelFn scatter_fn = kerr ? (KernelFn)scatter_kernel_ks
+                                     : f32 ? (KernelFn)scatter_kernel_flat<true> : (KernelFn)scatter_kernel_flat<false>;
+    int occ = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_fn, 256, lds_track));
+    occ = std::max(occ, 1);
+    const int grid = c->n_cu * occ;
+
+    std::vector<TArgs> args(n_inst);
+    std::vector<unsigned long long> off(n_inst + 1, 0);
+    for (int k = 0; k < n_inst; ++k) {
+        gm_status s = prepare_instance(c, c->inst[ids[k]], tp);
+        if (s != GM_OK) return s;
+        args[k] = fill_args(c, ids[k], tp);
+        off[k + 1] = off[k] + c->inst[ids[k]].n_roots;
+    }
+    if (c->inst_args.ensure(n_inst) != hipSuccess || c->root_off.ensure(n_inst + 1) != hipSuccess)
+        return fail(GM_ENOMEM, "launch arguments");
+    HIPCHK(hipMemcpyAsync(c->inst_args.p, args.data(), n_inst * sizeof(TArgs), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->root_off.p, off.data(), (n_inst + 1) * sizeof(unsigned long long),
+                          hipMemcpyHostToDevice, c->stream));
+    TArgs L = args[0];
+    L.insts = c->inst_args.p;
+    L.n_inst = n_inst;
+    L.root_off = c->root_off.p;
+    L.lds_stride = (int)(L_N + S_N + nspec);
 
     // generations 0 .. n_sc_max: only photons below the cap can scatter
     const int ngen = tp->scattering ? tp->n_sc_max + 1 : 1;
+    const unsigned long long total = off[n_inst];
     const unsigned long long chunk = std::max<unsigned long long>(1, c->child_cap / 2);
-    for (unsigned long long start = 0; start < I.n_roots; start += chunk) {
-        const unsigned long long cnt = std::min(chunk, I.n_roots - start);
+    for (unsigned long long start = 0; start < total; start += chunk) {
+        const unsigned long long cnt = std::min(chunk, total - start);
         reset_counters_kernel<<<1, 64, 0, c->stream>>>(c->ctr.p, 64, c->flags.p);
-        A.root_begin = start;
-        A.root_count = cnt;
-        A.dst = queue(c, 0);
-        A.src_count = c->ctr.p;                       // generation-0 count
-        birth_fn<<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(A);
+        L.root_begin = start;
+        L.root_count = cnt;
+        L.dst = queue(c, 0);
+        L.src_count = c->ctr.p;                       // generation-0 count
+        birth_fn<<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(L);
         HIPCHK(hipGetLastError());
         for (int g = 0; g < ngen; ++g) {
-            A.gen = g;
-            A.src = queue(c, g & 1);
-            A.dst = queue(c, (g + 1) & 1);
-            A.src_count = c->ctr.p + 2 * g;
-            A.src_cursor = c->ctr.p + 2 * g + 1;
-            A.dst_count = c->ctr.p + 2 * (g + 1);
+            L.gen = g;
+            L.src = queue(c, g & 1);
+            L.dst = queue(c, (g + 1) & 1);
+            L.src_count = c->ctr.p + 2 * g;
+            L.src_cursor = c->ctr.p + 2 * g + 1;
+            L.dst_count = c->ctr.p + 2 * (g + 1);
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (c->timing) {
                 gm_status ts = take_event_pair(c, e0, e1);
                 if (ts != GM_OK) return ts;
                 HIPCHK(hipEventRecord(e0, c->stream));
             }
-            track_fn<<<grid, 256, lds_track, c->stream>>>(A);
+            track_fn<<<grid, 256, lds_track, c->stream>>>(L);
             HIPCHK(hipGetLastError());
             if (c->timing) HIPCHK(hipEventRecord(e1, c->stream));
             if (g + 1 < ngen) {
-                scatter_fn<<<c->n_cu * 8, 256, lds_small, c->stream>>>(A);
+                scatter_fn<<<c->n_cu * 8, 256, lds_small, c->stream>>>(L);
                 HIPCHK(hipGetLastError());
             }
         }
@@ -632,11 +693,14 @@ static gm_status track_instance(gm_ctx *c, int ii, const gm_track_params *tp, st
         HIPCHK(hipStreamSynchronize(c->stream));
         if (ovf) return fail(GM_ENOMEM, "photon queue of %llu overflowed", c->child_cap);
     }
-    std::vector<unsigned long long> st(S_N);
-    HIPCHK(hipMemcpyAsync(st.data(), I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (int i = 0; i < S_N; ++i) acc[i] += (long long)st[i];
-    I.pending = false;
+    for (int k = 0; k < n_inst; ++k) {
+        Instance &I = c->inst[ids[k]];
+        std::vector<unsigned long long> st(S_N);
+        HIPCHK(hipMemcpyAsync(st.data(), I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < S_N; ++i) acc[i] += (long long)st[i];
+        I.pending = false;
+    }
     return GM_OK;
 }
 
@@ -655,10 +719,12 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     bool any = false;
     for (auto &I : c->inst) any |= I.pending;
     if (!any) return fail(GM_ESTATE, "no superphotons made since the last track");
-    if (tp->bias_mode == GM_BIAS_LEARNED)
-        for (int i = 0; i < GM_MAX_INSTANCES; ++i)
-            if (c->inst[i].pending && (!c->inst[i].lnb.p || c->inst[i].lnb_n < 2))
-                return fail(GM_ESTATE, "instance %d has no learned bias table", i);
+    for (int i = 0; i < GM_MAX_INSTANCES; ++i) {
+        const Instance &I = c->inst[i];
+        const int mode = I.bias_mode >= 0 ? I.bias_mode : tp->bias_mode;
+        if (I.pending && mode == GM_BIAS_LEARNED && (!I.lnb.p || I.lnb_n < 2))
+            return fail(GM_ESTATE, "instance %d has no learned bias table", i);
+    }
     if (tp->scattering) {
         s = ensure_sigma_hot(c);
         if (s != GM_OK) return s;
@@ -669,12 +735,24 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     need = std::min(need, 1ull << 26);
     s = ensure_children(c, need);
     if (s != GM_OK) return s;
+    // instances of one metric share launches, as many as their LDS tallies
+    // allow (and at most max_batch)
+    const size_t per_inst = (size_t)(L_N + S_N + (size_t)tp->n_theta * tp->n_nu * 3) * 8;
+    if (per_inst > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %d bins exceeds the LDS tally", tp->n_theta * tp->n_nu);
+    const int fit = (int)std::min<size_t>((64 * 1024) / per_inst, (size_t)c->max_batch);
     std::vector<long long> acc(S_N, 0);
-    for (int i = 0; i < GM_MAX_INSTANCES; ++i)
-        if (c->inst[i].pending) {
-            s = track_instance(c, i, tp, acc);
-            if (s != GM_OK) return s;
+    for (int metric = 0; metric < 2; ++metric) {
+        std::vector<int> ids;
+        for (int i = 0; i <= GM_MAX_INSTANCES; ++i) {
+            const bool take = i < GM_MAX_INSTANCES && c->inst[i].pending && c->inst[i].grid.metric == metric;
+            if (take) ids.push_back(i);
+            if (!ids.empty() && ((int)ids.size() == fit || i == GM_MAX_INSTANCES)) {
+                s = track_batch(c, ids, tp, acc);
+                if (s != GM_OK) return s;
+                ids.clear();
+            }
         }
+    }
     if (stats)
         for (int i = 0; i < S_N; ++i) stats[i] = acc[i];
     return GM_OK;
@@ -763,6 +841,29 @@ gm_status gm_set_tuning(gm_ctx *c, int track_waves, int refill_min)
     if (refill_min < 1 || refill_min > 64) return fail(GM_EINVAL, "refill_min %d not in 1..64", refill_min);
     c->track_waves = track_waves;
     c->refill_min = refill_min;
+    return GM_OK;
+}
+
+gm_status gm_set_instance_bias(gm_ctx *c, int instance, int bias_mode, double bias_value, double bias_max)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    if (bias_mode > 3 || (bias_mode >= 0 && !(bias_max >= 1.0)) ||
+        (bias_mode >= 0 && bias_mode < 3 && !(bias_value > 0.0)))
+        return fail(GM_EINVAL, "bad bias");
+    Instance &I = c->inst[instance];
+    I.bias_mode = bias_mode < 0 ? -1 : bias_mode;
+    I.bias_value = bias_value;
+    I.bias_max = bias_max;
+    return GM_OK;
+}
+
+gm_status gm_set_batch(gm_ctx *c, int max_instances)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (max_instances < 1 || max_instances > GM_MAX_INSTANCES)
+        return fail(GM_EINVAL, "max_instances %d not in 1..%d", max_instances, GM_MAX_INSTANCES);
+    c->max_batch = max_instances;
     return GM_OK;
 }
 

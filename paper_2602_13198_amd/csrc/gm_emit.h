@@ -187,6 +187,19 @@ __global__ __launch_bounds__(256) void count_kernel(EmitArgs E)
     E.count[z] = (uint32_t)fl + ((u < nb - fl) ? 1u : 0u);
 }
 
+// Stochastic rounding of the stored expected counts under a new seed (the
+// weight table, expected counts and rejection bounds do not depend on it).
+__global__ __launch_bounds__(256) void recount_kernel(EmitArgs E)
+{
+    int z = blockIdx.x * 256 + threadIdx.x;
+    if (z >= E.nz) return;
+    double nb = E.nbar[z];
+    double fl = floor(nb);
+    Rng r{(uint32_t)z, 0u, ((uint32_t)E.inst << 8) | 2u, 0u};
+    double u = rng_uniform(r, E.key0, E.key1);
+    E.count[z] = (uint32_t)fl + ((u < nb - fl) ? 1u : 0u);
+}
+
 // ---------------------------------------------------------------------------
 // Exclusive scan of the zone counts into 64-bit photon offsets.
 // ---------------------------------------------------------------------------

@@ -27,7 +27,7 @@ struct PhotonQ {
     double *x[3], *k[4];
     double *w, *wb, *x1, *nua, *nus, *b;
     uint32_t *s0, *s1, *s2, *blk;
-    int32_t *n_sc, *zone;
+    int32_t *n_sc, *zone, *inst;
 };
 
 // One scattering event of the event log (training records of the learned
@@ -71,6 +71,13 @@ struct TArgs {
     unsigned long long *src_count, *src_cursor, *dst_count;
     unsigned long long cap;
     int *overflow;
+    // batched launch: per-instance argument blocks (instance fields; the
+    // queue fields of a launch are those of the launch's own arguments),
+    // combined root offsets [n_inst + 1], LDS doubles per instance
+    const struct TArgs *insts;
+    int n_inst;
+    const unsigned long long *root_off;
+    int lds_stride;
     // tallies of the instance
     double *spec, *ledger;
     unsigned long long *stats;
@@ -119,32 +126,63 @@ struct BlockAcc {
 GM_D void lds_add(double *p, double v) { atomicAdd(p, v); }
 GM_D void lds_inc(unsigned long long *p, unsigned long long v) { atomicAdd(p, v); }
 
-GM_D BlockAcc lds_setup(double *lds, int nspec)
+// LDS holds one accumulator block (ledger, counters, tally) per instance of
+// the launch, `stride` doubles apart.
+GM_D void lds_zero(double *lds, int n_inst, int stride)
+{
+    for (int i = threadIdx.x; i < n_inst * stride; i += blockDim.x) lds[i] = 0.0;
+    __syncthreads();
+}
+
+GM_D BlockAcc lds_acc(double *lds, int stride, int inst)
 {
     BlockAcc B;
-    B.ledger = lds;
-    B.stats = reinterpret_cast<unsigned long long *>(lds + L_N);
-    B.spec = lds + L_N + S_N;
-    for (int i = threadIdx.x; i < L_N + S_N + nspec; i += blockDim.x) lds[i] = 0.0;
-    __syncthreads();
+    double *base = lds + (size_t)inst * stride;
+    B.ledger = base;
+    B.stats = reinterpret_cast<unsigned long long *>(base + L_N);
+    B.spec = base + L_N + S_N;
     return B;
 }
 
-GM_D void lds_flush(const TArgs &A, const BlockAcc &B, int nspec)
+GM_D void lds_flush_all(const TArgs &L, double *lds, int stride)
 {
     __syncthreads();
-    for (int i = threadIdx.x; i < nspec; i += blockDim.x) {
-        double v = B.spec[i];
-        if (v != 0.0) atomicAdd(&A.spec[i], v);
+    const int nspec = stride - L_N - S_N;
+    for (int ii = 0; ii < L.n_inst; ++ii) {
+        const TArgs &A = L.insts[ii];
+        BlockAcc B = lds_acc(lds, stride, ii);
+        for (int i = threadIdx.x; i < nspec; i += blockDim.x) {
+            double v = B.spec[i];
+            if (v != 0.0) atomicAdd(&A.spec[i], v);
+        }
+        for (int i = threadIdx.x; i < L_N; i += blockDim.x) {
+            double v = B.ledger[i];
+            if (v != 0.0) atomicAdd(&A.ledger[i], v);
+        }
+        for (int i = threadIdx.x; i < S_N; i += blockDim.x) {
+            unsigned long long v = B.stats[i];
+            if (v) atomicAdd(&A.stats[i], v);
+        }
     }
-    for (int i = threadIdx.x; i < L_N; i += blockDim.x) {
-        double v = B.ledger[i];
-        if (v != 0.0) atomicAdd(&A.ledger[i], v);
+}
+
+// Instance of a root in the launch's combined root range (binary search of
+// the combined offsets).
+GM_D int inst_of_root(const TArgs &L, unsigned long long g)
+{
+    int lo = 0, hi = L.n_inst;               // root_off[lo] <= g < root_off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (L.root_off[mid] <= g) lo = mid; else hi = mid;
     }
-    for (int i = threadIdx.x; i < S_N; i += blockDim.x) {
-        unsigned long long v = B.stats[i];
-        if (v) atomicAdd(&A.stats[i], v);
-    }
+    return lo;
+}
+
+// The instance of the first lane of `mask`, as a wave-uniform value.
+GM_D int uniform_inst(uint64_t mask, int inst)
+{
+    int first = __ffsll((unsigned long long)mask) - 1;
+    return __builtin_amdgcn_readfirstlane(__shfl(inst, first));
 }
 
 // Zone holding a Cartesian point, or -1 outside the grid (vacuum).
@@ -291,14 +329,18 @@ GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, 
 // remaining optical depth, opacities at the birth point.
 // ---------------------------------------------------------------------------
 template <class M, bool F32>
-__global__ __launch_bounds__(256) void birth_kernel(TArgs A)
+__global__ __launch_bounds__(256) void birth_kernel(TArgs L)
 {
     extern __shared__ double lds[];
-    const int nspec = 0;
-    BlockAcc B = lds_setup(lds, nspec);
+    const int stride = L_N + S_N;
+    lds_zero(lds, L.n_inst, stride);
     unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < A.root_count) {
-        unsigned long long p = A.root_begin + q;
+    if (q < L.root_count) {
+        const unsigned long long gq = L.root_begin + q;
+        const int ii = inst_of_root(L, gq);
+        const TArgs &A = L.insts[ii];
+        BlockAcc B = lds_acc(lds, stride, ii);
+        unsigned long long p = gq - L.root_off[ii];
         uint32_t z = A.zone_of_root[p];
         const double *zr = A.zrec + (size_t)z * Z_STRIDE;
         Rng rng{(uint32_t)p, (uint32_t)(p >> 32), ((uint32_t)A.inst << 8) | 1u, 0u};
@@ -369,7 +411,8 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs A)
         Coef c{0.0, 0.0, 1.0, true};
         if constexpr (!M::kCurved) c = coefficients<M, F32>(A, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
         // write generation-0 queue entry q
-        const PhotonQ &Q = A.dst;
+        const PhotonQ &Q = L.dst;
+        Q.inst[q] = ii;
 #pragma unroll
         for (int m = 0; m < 3; ++m) Q.x[m][q] = x[m + 1];
 #pragma unroll
@@ -386,8 +429,8 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs A)
         lds_inc(&B.stats[S_DIR_TRIALS], dtr);
         lds_inc(&B.stats[S_GEN0], 1);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *A.src_count = A.root_count;
-    lds_flush(A, B, nspec);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *L.src_count = L.root_count;
+    lds_flush_all(L, lds, stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -399,7 +442,7 @@ struct Photon {
     double nua, nus, b;            // opacities and bias at the current point
     double acc_wabs, acc_wcap;     // weight lost to absorption / the generation cap
     Rng rng;
-    int n_sc;
+    int n_sc, inst;
     uint32_t steps, nsub;          // steps; partial steps to scattering points
 };
 
@@ -413,6 +456,7 @@ GM_D void load_photon(const PhotonQ &Q, unsigned long long i, Photon &ph)
     ph.nua = Q.nua[i]; ph.nus = Q.nus[i]; ph.b = Q.b[i];
     ph.rng = Rng{Q.s0[i], Q.s1[i], Q.s2[i], Q.blk[i]};
     ph.n_sc = Q.n_sc[i];
+    ph.inst = Q.inst[i];
     ph.steps = 0;
     ph.nsub = 0;
     ph.acc_wabs = ph.acc_wcap = 0.0;
@@ -478,33 +522,47 @@ GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind)
 // that ends keeps its state in the idle lane; its bookkeeping (tally,
 // ledger, trace) runs in the wave's next refill pass together with the
 // other lanes that ended, instead of diverging from the stepping lanes.
-template <int WAVES, bool F32>
-__global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
+template <int WAVES, bool F32, bool BATCHED>
+__global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
 {
     extern __shared__ double lds[];
-    const int nspec = A.n_theta * A.n_nu * 3;
-    BlockAcc B = lds_setup(lds, nspec);
-    const unsigned long long n_src = min(*A.src_count, A.cap);
+    const int stride = L.lds_stride;
+    lds_zero(lds, L.n_inst, stride);
+    const unsigned long long n_src = min(*L.src_count, L.cap);
     Photon ph;
+    ph.inst = 0;
     bool alive = false, exhausted = false, restart = false;
     int ended = 0;                          // end kind awaiting bookkeeping
     for (;;) {
         uint64_t idle = __ballot(!alive);
         int nidle = __popcll(idle);
-        if (nidle >= A.refill_min || nidle == 64) {
-            if (ended) {
-                finish(A, B, ph, ended);
+        if (nidle >= L.refill_min || nidle == 64) {
+            // bookkeeping of the lanes that ended (one instance at a time)
+            if constexpr (BATCHED) {
+                for (uint64_t todo = __ballot(ended != 0); todo;) {
+                    const int iu = uniform_inst(todo, ph.inst);
+                    const bool mine = ended != 0 && ph.inst == iu;
+                    todo &= ~__ballot(mine);
+                    if (mine) {
+                        BlockAcc B = lds_acc(lds, stride, iu);
+                        finish(L.insts[iu], B, ph, ended);
+                        ended = 0;
+                    }
+                }
+            } else if (ended) {
+                BlockAcc B = lds_acc(lds, stride, 0);
+                finish(L, B, ph, ended);
                 ended = 0;
             }
             if (!exhausted) {
                 unsigned long long base = 0;
-                if (lane_id() == 0) base = atomicAdd(A.src_cursor, (unsigned long long)nidle);
+                if (lane_id() == 0) base = atomicAdd(L.src_cursor, (unsigned long long)nidle);
                 base = bcast_u64(base, 0);
                 if (base + (unsigned long long)nidle >= n_src) exhausted = true;
                 if (!alive) {
                     unsigned long long idx = base + rank_in_mask(idle);
                     if (idx < n_src) {
-                        load_photon(A.src, idx, ph);
+                        load_photon(L.src, idx, ph);
                         alive = true;
                         restart = false;
                     }
@@ -516,11 +574,13 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
         double wchild = 0.0;
         int zs = -1;
         Rng crng{0u, 0u, 0u, 0u};
-        if (alive && !restart && (long long)ph.steps >= A.max_steps) {
+        if (alive && !restart && (long long)ph.steps >= L.max_steps) {
             ended = END_STUCK;
             alive = false;
         }
-        if (alive) {
+        // one step (or restart, or load evaluation) of this lane's photon
+        // with the arguments of its instance
+        auto advance = [&](const TArgs &A, BlockAcc &B) {
             // ---- the point where the opacities are needed ----
             double dl = 0.0;
             double xn[3];
@@ -628,6 +688,21 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
                     }
                 }
             }
+        };
+        if constexpr (BATCHED) {
+            // one instance at a time, with wave-uniform instance arguments
+            for (uint64_t todo = __ballot(alive); todo;) {
+                const int iu = uniform_inst(todo, ph.inst);
+                const bool mine = ((todo >> lane_id()) & 1ull) && ph.inst == iu;
+                todo &= ~__ballot(mine);
+                if (mine) {
+                    BlockAcc B = lds_acc(lds, stride, iu);
+                    advance(L.insts[iu], B);
+                }
+            }
+        } else if (alive) {
+            BlockAcc B = lds_acc(lds, stride, 0);
+            advance(L, B);
         }
         // ---- scattering events: one slot reservation per wave; the event
         // holds the scattering point and the incoming wavevector (the
@@ -635,12 +710,13 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
         uint64_t smask = __ballot(scat);
         if (smask) {
             unsigned long long base = 0;
-            if (lane_id() == 0) base = atomicAdd(A.dst_count, (unsigned long long)__popcll(smask));
+            if (lane_id() == 0) base = atomicAdd(L.dst_count, (unsigned long long)__popcll(smask));
             base = bcast_u64(base, 0);
             if (scat) {
                 unsigned long long i = base + rank_in_mask(smask);
-                if (i < A.cap) {
-                    const PhotonQ &Q = A.dst;
+                if (i < L.cap) {
+                    const PhotonQ &Q = L.dst;
+                    Q.inst[i] = ph.inst;
 #pragma unroll
                     for (int m = 0; m < 3; ++m) Q.x[m][i] = ph.x[m];
 #pragma unroll
@@ -650,13 +726,28 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs A)
                     Q.n_sc[i] = ph.n_sc + 1;
                     Q.zone[i] = zs;
                 } else {
-                    atomicOr(A.overflow, 1);
+                    atomicOr(L.overflow, 1);
                 }
             }
         }
     }
-    if (ended) finish(A, B, ph, ended);
-    lds_flush(A, B, nspec);
+    if constexpr (BATCHED) {
+        for (uint64_t todo = __ballot(ended != 0); todo;) {
+            const int iu = uniform_inst(todo, ph.inst);
+            const bool mine = ended != 0 && ph.inst == iu;
+            todo &= ~__ballot(mine);
+            if (mine) {
+                BlockAcc B = lds_acc(lds, stride, iu);
+                finish(L.insts[iu], B, ph, ended);
+                ended = 0;
+            }
+        }
+    } else if (ended) {
+        BlockAcc B = lds_acc(lds, stride, 0);
+        finish(L, B, ph, ended);
+        ended = 0;
+    }
+    lds_flush_all(L, lds, stride);
 }
 
 // Append a scattering event to the log (when one is set and has room).
@@ -681,14 +772,18 @@ GM_D void log_event(const TArgs &A, const Rng &child, int z, double eps, double 
 // child's own optical-depth draw.
 // ---------------------------------------------------------------------------
 template <bool F32>
-__global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs A)
+__global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs L)
 {
     extern __shared__ double lds[];
-    BlockAcc B = lds_setup(lds, 0);
-    const unsigned long long n = min(*A.dst_count, A.cap);
-    const PhotonQ &Q = A.dst;
+    const int stride = L_N + S_N;
+    lds_zero(lds, L.n_inst, stride);
+    const unsigned long long n = min(*L.dst_count, L.cap);
+    const PhotonQ &Q = L.dst;
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (unsigned long long)gridDim.x * blockDim.x) {
+        const int ii = Q.inst[i];
+        const TArgs &A = L.insts[ii];
+        BlockAcc B = lds_acc(lds, stride, ii);
         double x[4] = {0.0, Q.x[0][i], Q.x[1][i], Q.x[2][i]};
         double ks[4] = {Q.k[0][i], Q.k[1][i], Q.k[2][i], Q.k[3][i]};
         int z = Q.zone[i];
@@ -728,7 +823,7 @@ __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs A)
         Q.nua[i] = c.nua; Q.nus[i] = c.nus; Q.b[i] = c.b;
         Q.blk[i] = r.block;
     }
-    lds_flush(A, B, 0);
+    lds_flush_all(L, lds, stride);
 }
 
 }  // namespace gm

@@ -34,7 +34,7 @@ struct PhotonK {
     double acc_wcap, acc_ecap;     // ... extinguished at the generation cap
     double acc_edrift;             // sum of w * (change of e_inf) along steps
     Rng rng;
-    int n_sc;
+    int n_sc, inst;
     int zone_end;                  // zone of the end of the step that found a scattering
     uint32_t steps, vit;
 };
@@ -50,6 +50,7 @@ GM_D void load_photon_ks(const PhotonQ &Q, unsigned long long i, PhotonK &ph)
     ph.w = Q.w[i]; ph.wb = Q.wb[i]; ph.x1 = Q.x1[i];
     ph.rng = Rng{Q.s0[i], Q.s1[i], Q.s2[i], Q.blk[i]};
     ph.n_sc = Q.n_sc[i];
+    ph.inst = Q.inst[i];
     ph.steps = 0;
     ph.vit = 0;
     ph.acc_wabs = ph.acc_eabs = ph.acc_wcap = ph.acc_ecap = ph.acc_edrift = 0.0;
@@ -135,34 +136,48 @@ GM_D int plasma_zone(const TArgs &A, int z)
 // corrector; Absorption and Scattering sections).  Scheduling as in the
 // flat tracker: lanes idle until enough of the wave is idle, then claim
 // queue entries together and run the finished photons' bookkeeping.
-template <int WAVES, bool F32>
-__global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs A)
+template <int WAVES, bool F32, bool BATCHED>
+__global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 {
     extern __shared__ double lds[];
-    const int nspec = A.n_theta * A.n_nu * 3;
-    BlockAcc B = lds_setup(lds, nspec);
-    const unsigned long long n_src = min(*A.src_count, A.cap);
+    const int stride = L.lds_stride;
+    lds_zero(lds, L.n_inst, stride);
+    const unsigned long long n_src = min(*L.src_count, L.cap);
     PhotonK ph;
+    ph.inst = 0;
     bool alive = false, exhausted = false;
     int mode = MODE_STEP;
     int ended = 0;
     for (;;) {
         uint64_t idle = __ballot(!alive);
         int nidle = __popcll(idle);
-        if (nidle >= A.refill_min || nidle == 64) {
-            if (ended) {
-                finish_ks(A, B, ph, ended);
+        if (nidle >= L.refill_min || nidle == 64) {
+            // bookkeeping of the lanes that ended (one instance at a time)
+            if constexpr (BATCHED) {
+                for (uint64_t todo = __ballot(ended != 0); todo;) {
+                    const int iu = uniform_inst(todo, ph.inst);
+                    const bool mine = ended != 0 && ph.inst == iu;
+                    todo &= ~__ballot(mine);
+                    if (mine) {
+                        BlockAcc B = lds_acc(lds, stride, iu);
+                        finish_ks(L.insts[iu], B, ph, ended);
+                        ended = 0;
+                    }
+                }
+            } else if (ended) {
+                BlockAcc B = lds_acc(lds, stride, 0);
+                finish_ks(L, B, ph, ended);
                 ended = 0;
             }
             if (!exhausted) {
                 unsigned long long base = 0;
-                if (lane_id() == 0) base = atomicAdd(A.src_cursor, (unsigned long long)nidle);
+                if (lane_id() == 0) base = atomicAdd(L.src_cursor, (unsigned long long)nidle);
                 base = bcast_u64(base, 0);
                 if (base + (unsigned long long)nidle >= n_src) exhausted = true;
                 if (!alive) {
                     unsigned long long idx = base + rank_in_mask(idle);
                     if (idx < n_src) {
-                        load_photon_ks(A.src, idx, ph);
+                        load_photon_ks(L.src, idx, ph);
                         alive = true;
                         mode = MODE_LOAD;
                     }
@@ -174,11 +189,13 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs A)
         double wchild = 0.0;
         int zs = -1;
         Rng crng{0u, 0u, 0u, 0u};
-        if (alive && mode == MODE_STEP && (long long)ph.steps >= A.max_steps) {
+        if (alive && mode == MODE_STEP && (long long)ph.steps >= L.max_steps) {
             ended = END_STUCK;
             alive = false;
         }
-        if (alive) {
+        // one step (or restart, or load evaluation) of this lane's photon
+        // with the arguments of its instance
+        auto advance = [&](const TArgs &A, BlockAcc &B) {
             // ---- the point of this iteration ----
             double P[3], kn[4], an[4], a_fresh[4] = {0.0, 0.0, 0.0, 0.0};
             double dl = 0.0;
@@ -344,18 +361,34 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs A)
                     alive = false;
                 }
             }
+        };
+        if constexpr (BATCHED) {
+            // one instance at a time, with wave-uniform instance arguments
+            for (uint64_t todo = __ballot(alive); todo;) {
+                const int iu = uniform_inst(todo, ph.inst);
+                const bool mine = ((todo >> lane_id()) & 1ull) && ph.inst == iu;
+                todo &= ~__ballot(mine);
+                if (mine) {
+                    BlockAcc B = lds_acc(lds, stride, iu);
+                    advance(L.insts[iu], B);
+                }
+            }
+        } else if (alive) {
+            BlockAcc B = lds_acc(lds, stride, 0);
+            advance(L, B);
         }
         // ---- scattering events (the parent now sits at the scattering
         // point with the wavevector it scattered) ----
         uint64_t smask = __ballot(scat);
         if (smask) {
             unsigned long long base = 0;
-            if (lane_id() == 0) base = atomicAdd(A.dst_count, (unsigned long long)__popcll(smask));
+            if (lane_id() == 0) base = atomicAdd(L.dst_count, (unsigned long long)__popcll(smask));
             base = bcast_u64(base, 0);
             if (scat) {
                 unsigned long long i = base + rank_in_mask(smask);
-                if (i < A.cap) {
-                    const PhotonQ &Q = A.dst;
+                if (i < L.cap) {
+                    const PhotonQ &Q = L.dst;
+                    Q.inst[i] = ph.inst;
 #pragma unroll
                     for (int m = 0; m < 3; ++m) Q.x[m][i] = ph.x[m];
 #pragma unroll
@@ -365,27 +398,46 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs A)
                     Q.n_sc[i] = ph.n_sc + 1;
                     Q.zone[i] = zs;
                 } else {
-                    atomicOr(A.overflow, 1);
+                    atomicOr(L.overflow, 1);
                 }
             }
         }
     }
-    if (ended) finish_ks(A, B, ph, ended);
-    lds_flush(A, B, nspec);
+    if constexpr (BATCHED) {
+        for (uint64_t todo = __ballot(ended != 0); todo;) {
+            const int iu = uniform_inst(todo, ph.inst);
+            const bool mine = ended != 0 && ph.inst == iu;
+            todo &= ~__ballot(mine);
+            if (mine) {
+                BlockAcc B = lds_acc(lds, stride, iu);
+                finish_ks(L.insts[iu], B, ph, ended);
+                ended = 0;
+            }
+        }
+    } else if (ended) {
+        BlockAcc B = lds_acc(lds, stride, 0);
+        finish_ks(L, B, ph, ended);
+        ended = 0;
+    }
+    lds_flush_all(L, lds, stride);
 }
 
 // Scattering events -> child photons in Kerr spacetime, one thread per
 // event: fluid frame at the scattering point, electron and angle draws from
 // the child's stream, then the child's optical-depth draw.  The child's
 // opacities and acceleration are evaluated when the tracker loads it.
-__global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs A)
+__global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs L)
 {
     extern __shared__ double lds[];
-    BlockAcc B = lds_setup(lds, 0);
-    const unsigned long long n = min(*A.dst_count, A.cap);
-    const PhotonQ &Q = A.dst;
+    const int stride = L_N + S_N;
+    lds_zero(lds, L.n_inst, stride);
+    const unsigned long long n = min(*L.dst_count, L.cap);
+    const PhotonQ &Q = L.dst;
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (unsigned long long)gridDim.x * blockDim.x) {
+        const int ii = Q.inst[i];
+        const TArgs &A = L.insts[ii];
+        BlockAcc B = lds_acc(lds, stride, ii);
         double ks[4] = {Q.k[0][i], Q.k[1][i], Q.k[2][i], Q.k[3][i]};
         int z = Q.zone[i];
         int n_sc = Q.n_sc[i];
@@ -427,7 +479,7 @@ __global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs A)
         Q.x1[i] = x1;
         Q.blk[i] = r.block;
     }
-    lds_flush(A, B, 0);
+    lds_flush_all(L, lds, stride);
 }
 
 }  // namespace gm

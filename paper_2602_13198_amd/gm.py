@@ -47,7 +47,8 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G", "gm_set_timing",
            "gm_read_timing", "gm_set_tuning", "gm_mlp_set_params", "gm_mlp_get_params",
            "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_set_bias_table",
-           "gm_set_event_log", "gm_event_count"]
+           "gm_set_event_log", "gm_event_count", "gm_set_batch",
+           "gm_set_instance_bias"]
 
 
 class GmGrid(C.Structure):
@@ -112,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_set_bias_table": (i, [vp, i, dp, i, C.c_double, C.c_double]),
         "gm_set_event_log": (i, [vp, vp, u64]),
         "gm_event_count": (i, [vp, C.POINTER(C.c_uint64)]),
+        "gm_set_batch": (i, [vp, i]),
+        "gm_set_instance_bias": (i, [vp, i, i, C.c_double, C.c_double]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -342,6 +345,19 @@ class Context:
 
     def set_tuning(self, track_waves: int = 2, refill_min: int = 8):
         _check(load_library().gm_set_tuning(self._h, int(track_waves), int(refill_min)))
+
+    def set_instance_bias(self, instance: int, track: dict | None):
+        """Per-instance bias from a track dict (bias_mode, bias_value,
+        bias_max); None removes the override."""
+        if track is None:
+            _check(load_library().gm_set_instance_bias(self._h, int(instance), -1, 0.0, 0.0))
+            return
+        _check(load_library().gm_set_instance_bias(self._h, int(instance), int(track.get("bias_mode", 0)),
+                                                   float(track.get("bias_value", 1.0)),
+                                                   float(track.get("bias_max", 1e6))))
+
+    def set_batch(self, max_instances: int):
+        _check(load_library().gm_set_batch(self._h, int(max_instances)))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().gm_set_timing(self._h, int(enable)))

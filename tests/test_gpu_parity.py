@@ -139,6 +139,33 @@ def test_full_size_sampled(gm, oracle_lib):
     assert abs(wr) < 1e-12 and abs(er) < 1e-12
 
 
+def test_emission_tables_reused_across_seeds(gm):
+    """A second make with only the seed changed reuses the weight table and
+    expected counts; its counts equal those of a fresh context."""
+    wl = W.scattering_sphere(0.1, n_target=1e5, seed=0)
+    c = gm.Context(0)
+    c.load_zones(wl)
+    c.make_superphotons(wl.emit)
+    n2 = c.make_superphotons(dict(wl.emit, seed=77))
+    e2 = c.read_emission()
+    bad = dict(wl.emit, nu_min=1e20, nu_max=1e21)
+    with pytest.raises(gm.GmError):
+        c.make_superphotons(bad)                    # a failed make leaves nothing reusable
+    n3 = c.make_superphotons(dict(wl.emit, seed=77))
+    e3 = c.read_emission()
+    c.close()
+    f = gm.Context(0)
+    f.load_zones(wl)
+    nf = f.make_superphotons(dict(wl.emit, seed=77))
+    ef = f.read_emission()
+    f.close()
+    assert n2 == nf == n3
+    for e in (e2, e3):
+        np.testing.assert_array_equal(e["counts"], ef["counts"])
+        np.testing.assert_array_equal(e["nbar"], ef["nbar"])
+        np.testing.assert_array_equal(e["ln_w"], ef["ln_w"])
+
+
 def test_tally_accumulates_and_resets(gm):
     wl = W.strictly_thin_sphere(n_target=3000, seed=11)
     c = gm.Context(0)
@@ -194,3 +221,38 @@ def test_histories_do_not_depend_on_tuning(gm):
         assert np.array_equal(tr.view(np.uint8), ref[0].view(np.uint8)), (waves, refill)
         np.testing.assert_allclose(spec, ref[1], rtol=1e-12, atol=0)
         np.testing.assert_allclose(led, ref[2], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("kind", ["flat", "kerr"])
+def test_batched_launch_equals_separate(gm, kind):
+    """Several instances tracked in shared launches give, instance by
+    instance, bitwise the same photon histories as tracking each alone, and
+    the same tallies up to summation order."""
+    if kind == "flat":
+        wls = [W.scattering_sphere(t, n_target=3000, seed=4, instance=i) for i, t in enumerate((1e-3, 1e-2, 1e-1))]
+    else:
+        wls = [W.torus(n1=64, n2=32, step_h=0.125, n_target=1500, seed=5 + i).with_emit(instance=i)
+               for i in range(2)]
+    out = {}
+    for batch in (1, 64):
+        c = gm.Context(0)
+        c.set_batch(batch)
+        for i, wl in enumerate(wls):
+            c.load_zones(wl, i)
+            c.set_instance_bias(i, wl.track)
+            c.make_superphotons(wl.emit, i)
+        c.set_trace(400000)
+        st = c.track_scatter(wls[0].track)
+        specs = [c.read_spectrum(i) for i in range(len(wls))]
+        tr = np.sort(c.read_trace(), order=["s2", "s1", "s0"])
+        c.close()
+        out[batch] = (st, specs, tr)
+    (s1, p1, t1), (s2, p2, t2) = out[1], out[64]
+    if kind == "flat":                 # each instance kept its own bias
+        assert np.unique(t2["n_sc"]).size > 1
+    assert len(t1) == len(t2) > 1000
+    assert np.array_equal(t1.view(np.uint8), t2.view(np.uint8))
+    np.testing.assert_array_equal(s1, s2)
+    for (a, la), (b, lb) in zip(p1, p2):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(la, lb, rtol=1e-12, atol=1e-300)
