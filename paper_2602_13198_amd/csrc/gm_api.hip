@@ -123,7 +123,7 @@ struct gm_ctx {
     int refill_min = 8;
     int max_batch = GM_MAX_INSTANCES;
     DevBuf<TArgs> inst_args;
-    DevBuf<unsigned long long> root_off;
+    DevBuf<unsigned long long> root_off, inst_ctr;
     // optional event timing of the tracking launches
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -242,7 +242,7 @@ gm_status gm_destroy(gm_ctx *c)
         I.tile.release(); I.roots.release(); I.spec.release(); I.ledger.release(); I.stats.release();
         I.lnb.release();
     }
-    c->inst_args.release(); c->root_off.release();
+    c->inst_args.release(); c->root_off.release(); c->inst_ctr.release();
     c->mlp_p.release(); c->mlp_m.release(); c->mlp_v.release(); c->mlp_g.release();
     c->mlp_gpart.release(); c->mlp_pb.release(); c->evlog_n.release();
     c->gcheb.release(); c->sh_table.release(); c->sh_table32.release(); c->gl_x.release(); c->gl_w.release();
@@ -506,7 +506,7 @@ __global__ void reset_counters_kernel(unsigned long long *ctr, int n, int *overf
 {
     int i = threadIdx.x;
     if (i < n) ctr[i] = 0ull;
-    if (i == 0) *overflow = 0;
+    if (i == 0 && overflow) *overflow = 0;
 }
 
 // Tally buffers of an instance for a track call (allocated or reshaped when
@@ -628,8 +628,12 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     const KernelFn track_fn = track_fns[kerr][f32][n_inst > 1][c->track_waves - 2];
     const KernelFn birth_fn = kerr ? (KernelFn)birth_kernel<KerrMKS, false>
                                    : f32 ? (KernelFn)birth_kernel<Minkowski, true> : (KernelFn)birth_kernel<Minkowski, false>;
-    const KernelFn scatter_fn = kerr ? (KernelFn)scatter_kernel_ks
-                                     : f32 ? (KernelFn)scatter_kernel_flat<true> : (KernelFn)scatter_kernel_flat<false>;
+    const bool batched = n_inst > 1;
+    static const KernelFn scatter_fns[2][2][2] = {
+        {{scatter_kernel_flat<false, false>, scatter_kernel_flat<false, true>},
+         {scatter_kernel_flat<true, false>, scatter_kernel_flat<true, true>}},
+        {{scatter_kernel_ks<false>, scatter_kernel_ks<true>}, {scatter_kernel_ks<false>, scatter_kernel_ks<true>}}};
+    const KernelFn scatter_fn = scatter_fns[kerr][f32][batched];
     int occ = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_fn, 256, lds_track));
     occ = std::max(occ, 1);
@@ -643,7 +647,8 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
         args[k] = fill_args(c, ids[k], tp);
         off[k + 1] = off[k] + c->inst[ids[k]].n_roots;
     }
-    if (c->inst_args.ensure(n_inst) != hipSuccess || c->root_off.ensure(n_inst + 1) != hipSuccess)
+    if (c->inst_args.ensure(n_inst) != hipSuccess || c->root_off.ensure(n_inst + 1) != hipSuccess ||
+        c->inst_ctr.ensure(2 * GM_MAX_INSTANCES) != hipSuccess)
         return fail(GM_ENOMEM, "launch arguments");
     HIPCHK(hipMemcpyAsync(c->inst_args.p, args.data(), n_inst * sizeof(TArgs), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->root_off.p, off.data(), (n_inst + 1) * sizeof(unsigned long long),
@@ -653,6 +658,8 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     L.n_inst = n_inst;
     L.root_off = c->root_off.p;
     L.lds_stride = (int)(L_N + S_N + nspec);
+    L.inst_count = c->inst_ctr.p;
+    L.inst_cursor = c->inst_ctr.p + GM_MAX_INSTANCES;
 
     // generations 0 .. n_sc_max: only photons below the cap can scatter
     const int ngen = tp->scattering ? tp->n_sc_max + 1 : 1;
@@ -669,8 +676,13 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
         HIPCHK(hipGetLastError());
         for (int g = 0; g < ngen; ++g) {
             L.gen = g;
-            L.src = queue(c, g & 1);
-            L.dst = queue(c, (g + 1) & 1);
+            // one instance: the queues alternate and children replace their
+            // events in place; batched: photons always come from queue 0 and
+            // events go to queue 1, from where the scattering kernel writes
+            // the children back to queue 0 grouped by instance
+            L.src = queue(c, batched ? 0 : (g & 1));
+            L.dst = queue(c, batched ? 1 : ((g + 1) & 1));
+            L.out = queue(c, 0);
             L.src_count = c->ctr.p + 2 * g;
             L.src_cursor = c->ctr.p + 2 * g + 1;
             L.dst_count = c->ctr.p + 2 * (g + 1);
@@ -684,6 +696,10 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
             HIPCHK(hipGetLastError());
             if (c->timing) HIPCHK(hipEventRecord(e1, c->stream));
             if (g + 1 < ngen) {
+                if (batched) {
+                    reset_counters_kernel<<<1, 2 * GM_MAX_INSTANCES, 0, c->stream>>>(c->inst_ctr.p, 2 * GM_MAX_INSTANCES, nullptr);
+                    count_events_kernel<<<c->n_cu * 4, 256, 0, c->stream>>>(L);
+                }
                 scatter_fn<<<c->n_cu * 8, 256, lds_small, c->stream>>>(L);
                 HIPCHK(hipGetLastError());
             }

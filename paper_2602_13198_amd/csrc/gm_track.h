@@ -78,6 +78,11 @@ struct TArgs {
     int n_inst;
     const unsigned long long *root_off;
     int lds_stride;
+    // batched scattering: per-instance event counts and slot cursors of the
+    // generation, and the queue the children are written to, grouped by
+    // instance (the generation's consumed source queue)
+    unsigned long long *inst_count, *inst_cursor;
+    PhotonQ out;
     // tallies of the instance
     double *spec, *ledger;
     unsigned long long *stats;
@@ -750,6 +755,51 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
     lds_flush_all(L, lds, stride);
 }
 
+// Events of the generation per instance (batched launches).
+__global__ __launch_bounds__(256) void count_events_kernel(TArgs L)
+{
+    __shared__ unsigned int hist[64];
+    if (threadIdx.x < 64) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const unsigned long long n = min(*L.dst_count, L.cap);
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        atomicAdd(&hist[L.dst.inst[i]], 1u);
+    __syncthreads();
+    if (threadIdx.x < L.n_inst && hist[threadIdx.x])
+        atomicAdd(&L.inst_count[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
+}
+
+// Batched scattering: the events of a block's 256-event window are given
+// slots in the output queue grouped by instance (per-block reservation per
+// instance); calls ev(i, slot) for every event of the window.  Every thread
+// of the block runs the same number of windows.
+template <class Ev>
+GM_D void for_events_grouped(const TArgs &L, unsigned long long n, Ev ev)
+{
+    __shared__ unsigned long long off[64], lbase[64];
+    __shared__ unsigned int lcount[64];
+    if (threadIdx.x == 0) {
+        unsigned long long acc = 0;
+        for (int k = 0; k < L.n_inst; ++k) { off[k] = acc; acc += L.inst_count[k]; }
+    }
+    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < n;
+         base += (unsigned long long)gridDim.x * blockDim.x) {
+        if (threadIdx.x < 64) lcount[threadIdx.x] = 0u;
+        __syncthreads();
+        const unsigned long long i = base + threadIdx.x;
+        const bool valid = i < n;
+        const int ii = valid ? L.dst.inst[i] : 0;
+        const unsigned int local = valid ? atomicAdd(&lcount[ii], 1u) : 0u;
+        __syncthreads();
+        if (threadIdx.x < L.n_inst && lcount[threadIdx.x])
+            lbase[threadIdx.x] = off[threadIdx.x] + atomicAdd(&L.inst_cursor[threadIdx.x], (unsigned long long)lcount[threadIdx.x]);
+        __syncthreads();
+        if (valid) ev(i, lbase[ii] + local);
+        __syncthreads();
+    }
+}
+
 // Append a scattering event to the log (when one is set and has room).
 GM_D void log_event(const TArgs &A, const Rng &child, int z, double eps, double w_child, const double *x)
 {
@@ -771,7 +821,7 @@ GM_D void log_event(const TArgs &A, const Rng &child, int z, double eps, double 
 // (gamma, mu), electron azimuth, scattering angle and azimuth, then the
 // child's own optical-depth draw.
 // ---------------------------------------------------------------------------
-template <bool F32>
+template <bool F32, bool BATCHED>
 __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs L)
 {
     extern __shared__ double lds[];
@@ -779,8 +829,8 @@ __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs L)
     lds_zero(lds, L.n_inst, stride);
     const unsigned long long n = min(*L.dst_count, L.cap);
     const PhotonQ &Q = L.dst;
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
+    // event i -> child: in place, or (batched) complete record at slot o of L.out
+    auto event = [&](unsigned long long i, unsigned long long o) {
         const int ii = Q.inst[i];
         const TArgs &A = L.insts[ii];
         BlockAcc B = lds_acc(lds, stride, ii);
@@ -816,12 +866,28 @@ __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs L)
         lds_inc(&B.stats[S_GEN0 + min(n_sc, 15)], 1);
         double x1 = -log(1.0 - rng_uniform(r, A.key0, A.key1));
         Coef c = coefficients<Minkowski, F32>(A, zone_cart(A, x[1], x[2], x[3]), x, kc, n_sc);
+        const PhotonQ &O = BATCHED ? L.out : Q;
+        if (BATCHED) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) Q.k[m][i] = kc[m];
-        Q.wb[i] = wchild;
-        Q.x1[i] = x1;
-        Q.nua[i] = c.nua; Q.nus[i] = c.nus; Q.b[i] = c.b;
-        Q.blk[i] = r.block;
+            for (int m = 0; m < 3; ++m) O.x[m][o] = x[m + 1];
+            O.w[o] = wchild;
+            O.s0[o] = Q.s0[i]; O.s1[o] = Q.s1[i]; O.s2[o] = Q.s2[i];
+            O.n_sc[o] = n_sc;
+            O.inst[o] = ii;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) O.k[m][o] = kc[m];
+        O.wb[o] = wchild;
+        O.x1[o] = x1;
+        O.nua[o] = c.nua; O.nus[o] = c.nus; O.b[o] = c.b;
+        O.blk[o] = r.block;
+    };
+    if constexpr (BATCHED) {
+        for_events_grouped(L, n, event);
+    } else {
+        for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (unsigned long long)gridDim.x * blockDim.x)
+            event(i, i);
     }
     lds_flush_all(L, lds, stride);
 }

@@ -426,6 +426,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 // event: fluid frame at the scattering point, electron and angle draws from
 // the child's stream, then the child's optical-depth draw.  The child's
 // opacities and acceleration are evaluated when the tracker loads it.
+template <bool BATCHED>
 __global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs L)
 {
     extern __shared__ double lds[];
@@ -433,8 +434,8 @@ __global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs L)
     lds_zero(lds, L.n_inst, stride);
     const unsigned long long n = min(*L.dst_count, L.cap);
     const PhotonQ &Q = L.dst;
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
+    // event i -> child: in place, or (batched) complete record at slot o of L.out
+    auto event = [&](unsigned long long i, unsigned long long o) {
         const int ii = Q.inst[i];
         const TArgs &A = L.insts[ii];
         BlockAcc B = lds_acc(lds, stride, ii);
@@ -473,11 +474,27 @@ __global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs L)
         lds_inc(&B.stats[S_CHILDREN], 1);
         lds_inc(&B.stats[S_GEN0 + min(n_sc, 15)], 1);
         double x1 = -log(1.0 - rng_uniform(r, A.key0, A.key1));
+        const PhotonQ &O = BATCHED ? L.out : Q;
+        if (BATCHED) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) Q.k[m][i] = kc[m];
-        Q.wb[i] = wchild;
-        Q.x1[i] = x1;
-        Q.blk[i] = r.block;
+            for (int m = 0; m < 3; ++m) O.x[m][o] = Q.x[m][i];
+            O.w[o] = wchild;
+            O.s0[o] = Q.s0[i]; O.s1[o] = Q.s1[i]; O.s2[o] = Q.s2[i];
+            O.n_sc[o] = n_sc;
+            O.inst[o] = ii;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) O.k[m][o] = kc[m];
+        O.wb[o] = wchild;
+        O.x1[o] = x1;
+        O.blk[o] = r.block;
+    };
+    if constexpr (BATCHED) {
+        for_events_grouped(L, n, event);
+    } else {
+        for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (unsigned long long)gridDim.x * blockDim.x)
+            event(i, i);
     }
     lds_flush_all(L, lds, stride);
 }
