@@ -35,38 +35,32 @@ TAUS = (1e-3, 1e-2, 1e-1)
 N_S = 1e6
 FP64_PEAK_TFLOPS = 78.6
 
-# Algorithmic FP64 operations per event of the method (counting convention:
-# + - * / sqrt and each elementary function = 1, fused multiply-add = 2;
-# comparisons, min/max, floor and integer work not counted).  The breakdown
-# of each figure is tabulated in the design doc.
+# Algorithmic FP64 operations of the tracking kernel per event (counting
+# convention: + - * / sqrt and each elementary function = 1, fused
+# multiply-add = 2; comparisons, min/max, floor and integer work not
+# counted).  The breakdown of each figure is tabulated in the design doc.  Only
+# the tracking kernel's own work is counted: birth and scattering kernels
+# are timed apart.
 FLOPS_PER = {
-    "step": 135,          # one flat step incl. opacities at the new point
-    "root": 350,          # birth of a root: position, tetrad, wavevector, opacities
-    "nu_trial": 85,       # one frequency rejection trial (angle integral via Chebyshev)
-    "dir_trial": 18,      # one direction rejection trial
-    "child": 110,         # start of a child: optical-depth draw, opacities
-    "scatter": 510,       # one scattering event: tetrad, boosts, child, parent update
-    "e_trial": 58,        # one electron (gamma, mu) trial of the scattering sampler
-    "ang_trial": 15,      # one Klein-Nishina angle trial
+    "step": 32,           # flat step: length 4, push 6, zone index 6, optical depths 8, updates 8
+    "opacity": 64,        # one opacity evaluation at a point: frame products 17, pitch angle 5,
+                          # g(X) and j 11, Kirchhoff nu alpha 9, sigma_h lookup and nu alpha_sc 22
+    "split": 20,          # scattering decision that splits: fraction, sub-step, absorption, split
 }
 STAT_INDEX = {"ROOTS": 0, "CHILDREN": 1, "STEPS": 2, "SCATTER": 4, "NU_TRIALS": 12,
-              "DIR_TRIALS": 13, "E_TRIALS": 14, "ANG_TRIALS": 15}
+              "DIR_TRIALS": 13, "E_TRIALS": 14, "ANG_TRIALS": 15, "OPACITY_EVALS": 32}
 
 
 def algorithmic_flops(st) -> float:
+    """Work of the tracking launches of a step from the library's counters."""
     return (FLOPS_PER["step"] * st[STAT_INDEX["STEPS"]]
-            + FLOPS_PER["root"] * st[STAT_INDEX["ROOTS"]]
-            + FLOPS_PER["nu_trial"] * st[STAT_INDEX["NU_TRIALS"]]
-            + FLOPS_PER["dir_trial"] * st[STAT_INDEX["DIR_TRIALS"]]
-            + FLOPS_PER["child"] * st[STAT_INDEX["CHILDREN"]]
-            + FLOPS_PER["scatter"] * st[STAT_INDEX["SCATTER"]]
-            + FLOPS_PER["e_trial"] * st[STAT_INDEX["E_TRIALS"]]
-            + FLOPS_PER["ang_trial"] * st[STAT_INDEX["ANG_TRIALS"]])
+            + FLOPS_PER["opacity"] * st[STAT_INDEX["OPACITY_EVALS"]]
+            + FLOPS_PER["split"] * st[STAT_INDEX["SCATTER"]])
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("gm_track.h", "gm_frame.h", "gm_physics.h", "gm_common.h"):
+    for f in ("gm_track.h", "gm_frame.h", "gm_physics.h", "gm_common.h", "gm_emis32.h", "gm_kerr.h"):
         h.update(open(os.path.join(ROOT, "paper_2602_13198_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -237,6 +231,7 @@ def main():
             "superphotons_per_step": n_sp / args.steps,
             "roots_per_step": int(totals[0]) / args.steps,
             "steps_per_superphoton": float(totals[2]) / max(n_sp, 1),
+            "opacity_evals_per_step": float(totals[32]) / max(float(totals[2]), 1.0),
             "tuning": tuning,
         },
         "roofline": {

@@ -136,7 +136,10 @@ enum {
     GM_S_OVERSHOOT, GM_S_NU_TRIALS, GM_S_DIR_TRIALS, GM_S_E_TRIALS, GM_S_ANG_TRIALS,
     GM_S_GEN0  /* GM_S_GEN0 + g: photons of generation g, g < 16 */
 };
-#define GM_S_N (GM_S_GEN0 + 16)
+/* opacity evaluations of the tracking kernels (flat spacetime evaluates
+ * once per zone entered: the opacities depend on the zone and on k only) */
+#define GM_S_COEF_EVALS (GM_S_GEN0 + 16)
+#define GM_S_N (GM_S_GEN0 + 17)
 
 /* Termination kinds in trace records. */
 #define GM_END_ESCAPE   1

@@ -37,7 +37,7 @@ enum { L_W_EMIT = 0, L_E_EMIT, L_W_ESC, L_E_ESC, L_W_OOB, L_E_OOB, L_W_ABS, L_E_
        L_E_COMPTON, L_E_DRIFT, L_N };
 enum { S_ROOTS = 0, S_CHILDREN, S_STEPS, S_VERLET_IT, S_SCATTER, S_ROUL_KILL, S_ROUL_SURVIVE,
        S_CAPTURED, S_ESCAPED, S_OOB, S_STUCK, S_OVERSHOOT, S_NU_TRIALS, S_DIR_TRIALS,
-       S_E_TRIALS, S_ANG_TRIALS, S_GEN0, S_N = S_GEN0 + 16 };
+       S_E_TRIALS, S_ANG_TRIALS, S_GEN0, S_COEF = S_GEN0 + 16, S_N };
 enum { END_ESCAPE = 1, END_OOB, END_CAPTURE, END_ROULETTE, END_STUCK, END_SPLIT };
 
 // ---------------------------------------------------------------------------

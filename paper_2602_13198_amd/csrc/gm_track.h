@@ -16,6 +16,8 @@
 // ledgers and counters accumulate in LDS and are merged into HBM per block.
 #pragma once
 
+#include <climits>
+
 #include "gm_emis32.h"
 #include "gm_frame.h"
 #include "gm_kerr.h"
@@ -449,6 +451,12 @@ struct Photon {
     Rng rng;
     int n_sc, inst;
     uint32_t steps, nsub;          // steps; partial steps to scattering points
+    // opacities and bias of the last zone evaluated: in flat spacetime they
+    // depend only on the zone, k (fixed for a photon) and n_sc, so a step
+    // ending in the same zone reuses them (bitwise the same values)
+    int cz, ncoef;
+    bool cvac;
+    double cnua, cnus, cb;
 };
 
 GM_D void load_photon(const PhotonQ &Q, unsigned long long i, Photon &ph)
@@ -464,6 +472,8 @@ GM_D void load_photon(const PhotonQ &Q, unsigned long long i, Photon &ph)
     ph.inst = Q.inst[i];
     ph.steps = 0;
     ph.nsub = 0;
+    ph.cz = INT_MIN;
+    ph.ncoef = 0;
     ph.acc_wabs = ph.acc_wcap = 0.0;
 }
 
@@ -517,6 +527,7 @@ GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind)
     }
     lds_inc(&B.stats[S_STEPS], ph.steps);
     lds_inc(&B.stats[S_VERLET_IT], ph.steps + ph.nsub);   // flat: one corrector pass per (partial) step
+    lds_inc(&B.stats[S_COEF], (unsigned long long)ph.ncoef);
     write_trace(A, ph, kind, inu, ith);
 }
 
@@ -601,8 +612,16 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
                 for (int m = 0; m < 3; ++m) xn[m] = ph.x[m] + ph.k[m + 1] * dl;
             }
             int zn = zone_cart(A, xn[0], xn[1], xn[2]);
-            double xv[4] = {0.0, xn[0], xn[1], xn[2]};
-            Coef c1 = coefficients<Minkowski, F32>(A, zn, xv, ph.k, ph.n_sc);
+            Coef c1;
+            if (zn == ph.cz) {
+                c1 = Coef{ph.cnua, ph.cnus, ph.cb, ph.cvac};
+            } else {
+                double xv[4] = {0.0, xn[0], xn[1], xn[2]};
+                c1 = coefficients<Minkowski, F32>(A, zn, xv, ph.k, ph.n_sc);
+                ph.cz = zn;
+                ph.cnua = c1.nua; ph.cnus = c1.nus; ph.cb = c1.b; ph.cvac = c1.vacuum;
+                ph.ncoef += 1;
+            }
             if (restart) {
                 ph.nua = c1.nua; ph.nus = c1.nus;
                 if (!c1.vacuum) ph.b = c1.b;

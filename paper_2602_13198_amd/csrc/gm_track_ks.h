@@ -37,6 +37,7 @@ struct PhotonK {
     int n_sc, inst;
     int zone_end;                  // zone of the end of the step that found a scattering
     uint32_t steps, vit;
+    int ncoef;                     // opacity evaluations (one per iteration)
 };
 
 enum { MODE_STEP = 0, MODE_SUBSTEP = 1, MODE_LOAD = 2 };
@@ -53,6 +54,7 @@ GM_D void load_photon_ks(const PhotonQ &Q, unsigned long long i, PhotonK &ph)
     ph.inst = Q.inst[i];
     ph.steps = 0;
     ph.vit = 0;
+    ph.ncoef = 0;
     ph.acc_wabs = ph.acc_eabs = ph.acc_wcap = ph.acc_ecap = ph.acc_edrift = 0.0;
 }
 
@@ -107,6 +109,7 @@ GM_D void finish_ks(const TArgs &A, BlockAcc &B, const PhotonK &ph, int kind)
     }
     lds_inc(&B.stats[S_STEPS], ph.steps);
     lds_inc(&B.stats[S_VERLET_IT], ph.vit);
+    lds_inc(&B.stats[S_COEF], (unsigned long long)ph.ncoef);
     write_trace_ks(A, ph, kind, inu, ith);
 }
 
@@ -276,6 +279,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
             kerr_full(K, g);
             const int zn = zone_ks(A, P[0], P[1], P[2]);
             Coef c1 = coefficients_at<false, F32>(A, zn, g, kn, ph.n_sc);
+            ph.ncoef += 1;
             if (mode != MODE_STEP) {
                 // restart at the scattering point, or first evaluation of a
                 // loaded photon: fresh acceleration and opacities here

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgm.so")
 GM_MAX_INSTANCES = 64
 L_N = 18
 S_GEN0 = 16
-S_N = S_GEN0 + 16
+S_COEF_EVALS = S_GEN0 + 16
+S_N = S_GEN0 + 17
 LEDGER_NAMES = ["W_EMIT", "E_EMIT", "W_ESC", "E_ESC", "W_OOB", "E_OOB", "W_ABS", "E_ABS",
                 "W_CAPT", "E_CAPT", "W_CAPLOSS", "E_CAPLOSS", "W_ROUL", "E_ROUL", "W_STUCK",
                 "E_STUCK", "E_COMPTON", "E_DRIFT"]
