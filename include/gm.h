@@ -232,7 +232,7 @@ gm_status gm_set_tuning(gm_ctx *ctx, int track_waves, int refill_min);
  * tracks the pending instances of one metric together -- one birth launch
  * and per generation one tracking and one scattering launch over all their
  * photons -- in groups of at most this many whose per-block tallies fit
- * the 64 KiB LDS budget.  Results do not depend on it. */
+ * the 56 KiB LDS tally budget.  Results do not depend on it. */
 gm_status gm_set_batch(gm_ctx *ctx, int max_instances);
 
 /* Scattering bias of one instance (GM_BIAS_*, value, maximum), overriding

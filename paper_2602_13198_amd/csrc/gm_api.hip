@@ -611,7 +611,7 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
 {
     const int n_inst = (int)ids.size();
     const size_t nspec = (size_t)tp->n_theta * tp->n_nu * 3;
-    const size_t lds_track = (size_t)n_inst * (L_N + S_N + nspec) * 8;
+    const size_t lds_track = (size_t)n_inst * (L_N + S_N + nspec) * 8 + kEvBytesPerBlock;
     const size_t lds_small = (size_t)n_inst * (L_N + S_N) * 8;
     const bool kerr = c->inst[ids[0]].grid.metric == GM_METRIC_KS_MKS;
     const bool f32 = tp->precision == GM_PRECISION_F32_EMISSIVITY;
@@ -752,10 +752,12 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     s = ensure_children(c, need);
     if (s != GM_OK) return s;
     // instances of one metric share launches, as many as their LDS tallies
-    // allow (and at most max_batch)
+    // allow (and at most max_batch): 56 KiB of tallies and the event staging
+    // per block keep two blocks on a CU
     const size_t per_inst = (size_t)(L_N + S_N + (size_t)tp->n_theta * tp->n_nu * 3) * 8;
-    if (per_inst > 64 * 1024) return fail(GM_EUNSUPPORTED, "tally of %d bins exceeds the LDS tally", tp->n_theta * tp->n_nu);
-    const int fit = (int)std::min<size_t>((64 * 1024) / per_inst, (size_t)c->max_batch);
+    const size_t tally_budget = 56 * 1024;
+    if (per_inst > tally_budget) return fail(GM_EUNSUPPORTED, "tally of %d bins exceeds the LDS tally", tp->n_theta * tp->n_nu);
+    const int fit = (int)std::min<size_t>(tally_budget / per_inst, (size_t)c->max_batch);
     std::vector<long long> acc(S_N, 0);
     for (int metric = 0; metric < 2; ++metric) {
         std::vector<int> ids;

@@ -87,6 +87,13 @@ GM_HD Rng child_rng(const Rng &p, uint32_t block_at, uint32_t k0, uint32_t k1)
     return Rng{o.x, o.y, o.z | 0x80000000u, 0u};
 }
 
+// Keep a wave-uniform value in a vector register: the compiler otherwise
+// re-reads kernel arguments from memory inside long loops when scalar
+// registers run short, and waits for every re-read.
+GM_D void keep_vgpr(double &x) { asm volatile("" : "+v"(x)); }
+GM_D void keep_vgpr(int &x) { asm volatile("" : "+v"(x)); }
+GM_D void keep_vgpr(uint32_t &x) { asm volatile("" : "+v"(x)); }
+
 // ---------------------------------------------------------------------------
 // wave helpers (wave64)
 // ---------------------------------------------------------------------------

@@ -173,6 +173,86 @@ GM_D void lds_flush_all(const TArgs &L, double *lds, int stride)
     }
 }
 
+// Scattering events of a wave staged in LDS and written to the event queue
+// in batches: one queue reservation (a device-wide atomic, served beyond the
+// XCD's L2) per batch instead of one per step of the wave, and coalesced
+// stores of consecutive slots instead of scattered single-lane ones.  Each
+// wave of the block owns kEvCap slots after the block's tallies; `n` is
+// wave-uniform.
+constexpr int kEvCap = 64;
+constexpr int kEvDoubles = kEvCap * 8 + kEvCap * 6 / 2;   // 8 doubles + 6 ints per event
+constexpr size_t kEvBytesPerBlock = (size_t)(256 / 64) * kEvDoubles * 8;
+
+struct EvStage {
+    double *d;    // [8][kEvCap]: x1, x2, x3, k0..k3, w
+    int *i;       // [6][kEvCap]: instance, stream s0 s1 s2, generation, zone
+    int n;
+};
+
+GM_D EvStage ev_stage(double *lds, int n_inst, int stride)
+{
+    EvStage S;
+    S.d = lds + (size_t)n_inst * stride + (size_t)(threadIdx.x >> 6) * kEvDoubles;
+    S.i = reinterpret_cast<int *>(S.d + 8 * kEvCap);
+    S.n = 0;
+    return S;
+}
+
+// Write the wave's staged events to consecutive queue slots (whole wave).
+GM_D void ev_flush(const TArgs &L, EvStage &S)
+{
+    if (S.n == 0) return;
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(L.dst_count, (unsigned long long)S.n);
+    base = bcast_u64(base, 0);
+    const int l = lane_id();
+    if (l < S.n) {
+        const unsigned long long q = base + (unsigned long long)l;
+        if (q < L.cap) {
+            const PhotonQ &Q = L.dst;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) Q.x[m][q] = S.d[m * kEvCap + l];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) Q.k[m][q] = S.d[(3 + m) * kEvCap + l];
+            Q.w[q] = S.d[7 * kEvCap + l];
+            Q.inst[q] = S.i[l];
+            Q.s0[q] = (uint32_t)S.i[kEvCap + l];
+            Q.s1[q] = (uint32_t)S.i[2 * kEvCap + l];
+            Q.s2[q] = (uint32_t)S.i[3 * kEvCap + l];
+            Q.n_sc[q] = S.i[4 * kEvCap + l];
+            Q.zone[q] = S.i[5 * kEvCap + l];
+        } else {
+            atomicOr(L.overflow, 1);
+        }
+    }
+    S.n = 0;
+}
+
+// Stage the events of the lanes in `smask` (whole wave; `scat` is this
+// lane's bit): scattering point x, incoming wavevector k, child weight,
+// child stream, child generation and plasma zone.
+GM_D void ev_push(const TArgs &L, EvStage &S, uint64_t smask, bool scat, int inst, const double *x,
+                  const double *k, double w, const Rng &r, int n_sc, int zone)
+{
+    const int nn = __popcll(smask);
+    if (S.n + nn > kEvCap) ev_flush(L, S);
+    if (scat) {
+        const int j = S.n + (int)rank_in_mask(smask);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) S.d[m * kEvCap + j] = x[m];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) S.d[(3 + m) * kEvCap + j] = k[m];
+        S.d[7 * kEvCap + j] = w;
+        S.i[j] = inst;
+        S.i[kEvCap + j] = (int)r.s0;
+        S.i[2 * kEvCap + j] = (int)r.s1;
+        S.i[3 * kEvCap + j] = (int)r.s2;
+        S.i[4 * kEvCap + j] = n_sc;
+        S.i[5 * kEvCap + j] = zone;
+    }
+    S.n += nn;
+}
+
 // Instance of a root in the launch's combined root range (binary search of
 // the combined offsets).
 GM_D int inst_of_root(const TArgs &L, unsigned long long g)
@@ -248,7 +328,18 @@ GM_D Coef coefficients_at64(const TArgs &A, int z, const double g[4][4], const d
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
-    const double *zr = A.zrec + (size_t)z * Z_STRIDE;
+    // the whole 128-byte record in one round of 16-byte loads, before the
+    // vacuum test, so that the record costs one memory latency, not two
+    double zr[Z_STRIDE];
+    {
+        const double2 *src = reinterpret_cast<const double2 *>(A.zrec + (size_t)z * Z_STRIDE);
+#pragma unroll
+        for (int m = 0; m < Z_STRIDE / 2; ++m) {
+            double2 v = src[m];
+            zr[2 * m] = v.x;
+            zr[2 * m + 1] = v.y;
+        }
+    }
     double ne = zr[Z_NE];
     if (!(ne > 0.0)) return c;
     c.vacuum = false;
@@ -544,11 +635,28 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
     extern __shared__ double lds[];
     const int stride = L.lds_stride;
     lds_zero(lds, L.n_inst, stride);
+    EvStage ev = ev_stage(lds, L.n_inst, stride);
     const unsigned long long n_src = min(*L.src_count, L.cap);
     Photon ph;
     ph.inst = 0;
     bool alive = false, exhausted = false, restart = false;
     int ended = 0;                          // end kind awaiting bookkeeping
+    // one instance: the arguments every step reads, held in registers
+    TArgs Lh = L;
+    if constexpr (!BATCHED) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            keep_vgpr(Lh.inv_dx[j]); keep_vgpr(Lh.xs[j]); keep_vgpr(Lh.xe[j]); keep_vgpr(Lh.n[j]);
+        }
+        keep_vgpr(Lh.step_h); keep_vgpr(Lh.C); keep_vgpr(Lh.roulette_frac);
+        keep_vgpr(Lh.bias_value); keep_vgpr(Lh.bias_max);
+        keep_vgpr(Lh.scattering); keep_vgpr(Lh.n_sc_max); keep_vgpr(Lh.bias_mode);
+        keep_vgpr(Lh.key0); keep_vgpr(Lh.key1);
+        if constexpr (!F32) {
+            keep_vgpr(Lh.sh.lt0); keep_vgpr(Lh.sh.inv_dt);
+            keep_vgpr(Lh.sh.le0); keep_vgpr(Lh.sh.inv_de);
+        }
+    }
     for (;;) {
         uint64_t idle = __ballot(!alive);
         int nidle = __popcll(idle);
@@ -726,35 +834,15 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
             }
         } else if (alive) {
             BlockAcc B = lds_acc(lds, stride, 0);
-            advance(L, B);
+            advance(Lh, B);
         }
         // ---- scattering events: one slot reservation per wave; the event
         // holds the scattering point and the incoming wavevector (the
         // parent's own, unchanged in flat spacetime) ----
         uint64_t smask = __ballot(scat);
-        if (smask) {
-            unsigned long long base = 0;
-            if (lane_id() == 0) base = atomicAdd(L.dst_count, (unsigned long long)__popcll(smask));
-            base = bcast_u64(base, 0);
-            if (scat) {
-                unsigned long long i = base + rank_in_mask(smask);
-                if (i < L.cap) {
-                    const PhotonQ &Q = L.dst;
-                    Q.inst[i] = ph.inst;
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) Q.x[m][i] = ph.x[m];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) Q.k[m][i] = ph.k[m];
-                    Q.w[i] = wchild;
-                    Q.s0[i] = crng.s0; Q.s1[i] = crng.s1; Q.s2[i] = crng.s2;
-                    Q.n_sc[i] = ph.n_sc + 1;
-                    Q.zone[i] = zs;
-                } else {
-                    atomicOr(L.overflow, 1);
-                }
-            }
-        }
+        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, crng, ph.n_sc + 1, zs);
     }
+    ev_flush(L, ev);
     if constexpr (BATCHED) {
         for (uint64_t todo = __ballot(ended != 0); todo;) {
             const int iu = uniform_inst(todo, ph.inst);

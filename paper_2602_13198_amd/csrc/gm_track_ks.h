@@ -145,6 +145,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
     extern __shared__ double lds[];
     const int stride = L.lds_stride;
     lds_zero(lds, L.n_inst, stride);
+    EvStage ev = ev_stage(lds, L.n_inst, stride);
     const unsigned long long n_src = min(*L.src_count, L.cap);
     PhotonK ph;
     ph.inst = 0;
@@ -384,29 +385,9 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
         // ---- scattering events (the parent now sits at the scattering
         // point with the wavevector it scattered) ----
         uint64_t smask = __ballot(scat);
-        if (smask) {
-            unsigned long long base = 0;
-            if (lane_id() == 0) base = atomicAdd(L.dst_count, (unsigned long long)__popcll(smask));
-            base = bcast_u64(base, 0);
-            if (scat) {
-                unsigned long long i = base + rank_in_mask(smask);
-                if (i < L.cap) {
-                    const PhotonQ &Q = L.dst;
-                    Q.inst[i] = ph.inst;
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) Q.x[m][i] = ph.x[m];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) Q.k[m][i] = ph.k[m];
-                    Q.w[i] = wchild;
-                    Q.s0[i] = crng.s0; Q.s1[i] = crng.s1; Q.s2[i] = crng.s2;
-                    Q.n_sc[i] = ph.n_sc + 1;
-                    Q.zone[i] = zs;
-                } else {
-                    atomicOr(L.overflow, 1);
-                }
-            }
-        }
+        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, crng, ph.n_sc + 1, zs);
     }
+    ev_flush(L, ev);
     if constexpr (BATCHED) {
         for (uint64_t todo = __ballot(ended != 0); todo;) {
             const int iu = uniform_inst(todo, ph.inst);
