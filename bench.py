@@ -78,6 +78,86 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
+TRACK_KERNEL = "track_kernel_flat<2, false, false>"
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_traffic.json")
+TRACE_TXT = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_kernel_trace.txt")
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    if not f:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    return list(csv.DictReader(open(f[0])))
+
+
+def summarize_traffic(fetch_dir, write_dir, commands, copy_mib):
+    """Writes the HBM traffic summary of the tracking kernel from two
+    rocprofv3 --pmc runs of `bench.py --copy-mib N` (FETCH_SIZE, then
+    WRITE_SIZE): KiB per launch, each scaled by what the same counter reads
+    for the plain device copy of known size in the same run."""
+    out = {"kernel": TRACK_KERNEL,
+           "workload": "scattering synchrotron sphere, 3 x N_s=1e6 (tau_T 1e-3/1e-2/1e-1), "
+                       "one bench step = 15 tracking launches",
+           "kernel_source_hash": kernel_source_hash()}
+    factors = {}
+    for key, d in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _counter_rows(d)
+        mine = [float(r["Counter_Value"]) for r in rows if TRACK_KERNEL in r["Kernel_Name"]]
+        copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
+        copy_bytes = copy_mib * 2**20
+        # the copy reads and writes copy_bytes once each
+        factors[key] = (copy_bytes / 1024.0) / copy
+        out["%s_kib_per_launch_raw" % key] = sum(mine) / len(mine)
+        out["launches"] = len(mine)
+        out.setdefault("copy_calibration", {"bytes": copy_bytes})
+        out["copy_calibration"]["%s_kib_raw" % key] = copy
+        out["copy_calibration"]["%s_factor" % key] = factors[key]
+    out["bytes_per_launch"] = 1024.0 * (out["fetch_kib_per_launch_raw"] * factors["fetch"]
+                                        + out["write_kib_per_launch_raw"] * factors["write"])
+    out["commands"] = commands
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+def summarize_trace(trace_dir, bench_log, command):
+    """Writes the kernel-trace summary: rocprofv3 --stats table, one step's
+    launches, and the tracker's average launch time as bench.py measured it
+    with HIP events in the same run."""
+    import csv
+    import glob
+    stats = sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True))[0]
+    trace = sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True))[0]
+    line = [l for l in open(bench_log) if l.startswith("{")][-1]
+    b = json.loads(line)
+    rows = list(csv.DictReader(open(stats)))
+    mine = [r for r in rows if TRACK_KERNEL in r["Name"]]
+    lines = ["# rocprofv3 kernel trace: scattering synchrotron sphere (3 x N_s=1e6, tau_T 1e-3/1e-2/1e-1)",
+             "# command: " + command,
+             "# bench.py in the same run: %s superphotons/s under the profiler; avg %s launch "
+             "%.3f ms over %d timed launches (HIP events); rocprofv3 average over all %s launches: %.3f ms"
+             % ("%.4g" % b["value"], TRACK_KERNEL, b["roofline"]["avg_launch_ms"], b["roofline"]["launches"],
+                mine[0]["Calls"] if mine else "0", float(mine[0]["AverageNs"]) * 1e-6 if mine else float("nan")),
+             "# HBM traffic of the same kernel: track_kernel_scattering_sphere_traffic.json", "",
+             "## kernel_stats.csv (top 16)"]
+    lines.append(",".join(rows[0].keys()))
+    for r in rows[:16]:
+        lines.append(",".join(str(v) for v in r.values()))
+    tr = list(csv.DictReader(open(trace)))
+    tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+    lines += ["", "## the last 40 launches of the run: kernel | duration | grid (work-items)"]
+    for r in tr[-40:]:
+        lines.append("%s | %.3f ms | grid %s" % (
+            r["Kernel_Name"][:60], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6,
+            r.get("Grid_Size_X", r.get("Grid_Size", "?"))))
+    with open(TRACE_TXT, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:8]))
+
+
 def workloads():
     from paper_2602_13198_amd import workloads as W
     return [W.scattering_sphere(t, n_target=N_S, seed=0, instance=i) for i, t in enumerate(TAUS)]
@@ -131,7 +211,19 @@ def main():
                     help="quantile of the predicted importance at which the learned b equals the plain b")
     ap.add_argument("--ttx-ref-rounds", type=int, default=1024,
                     help="N_s rounds of the plain reference spectrum")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the tracker's HBM traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
+                    help="write the kernel-trace summary from a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--commands", nargs="*", default=[],
+                    help="the profiler command lines, recorded in the summaries")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.commands, args.copy_mib or 1024)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, " && ".join(args.commands))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus %d requested); multi-GPU sharding is "
               "described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
