@@ -78,6 +78,33 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
+ISSUE_JSON = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_fp64_issue.json")
+
+
+def measured_issue():
+    """Issued FP64 operations per tracking launch from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    try:
+        d = json.load(open(ISSUE_JSON))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("issued_fp64_flop_per_launch")
+
+
+def register_bound(ctx, waves, target_ms=40.0):
+    """Attained FP64 FMA rate at the tracker's waves per SIMD for 1, 2, 4 and
+    8 independent dependent-FMA chains per lane (library kernel, HIP events)."""
+    out = {}
+    for chains in (1, 2, 4, 8):
+        ms, _, _ = ctx.fma_chain_bound(waves, chains, 20000)
+        iters = max(20000, int(20000 * target_ms / max(ms, 1e-3)))
+        ms, tf, _ = ctx.fma_chain_bound(waves, chains, iters)
+        out[chains] = tf
+    return out
+
+
 TRACK_KERNEL = "track_kernel_flat<2, false, false>"
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_traffic.json")
 TRACE_TXT = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_kernel_trace.txt")
@@ -118,6 +145,36 @@ def summarize_traffic(fetch_dir, write_dir, commands, copy_mib):
                                         + out["write_kib_per_launch_raw"] * factors["write"])
     out["commands"] = commands
     with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+def summarize_issue(pmc_dir, commands):
+    """Writes the issued FP64 operations of the tracking kernel from one
+    rocprofv3 --pmc run of the FP64 VALU instruction counters: per wave
+    instruction 64 lanes for ADD, MUL and transcendental, 128 for FMA (masked
+    lanes and software-function instructions included)."""
+    rows = _counter_rows(pmc_dir)
+    acc, n = {}, {}
+    for r in rows:
+        if TRACK_KERNEL not in r["Kernel_Name"]:
+            continue
+        k = r["Counter_Name"]
+        acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+        n[k] = n.get(k, 0) + 1
+    per = {k: acc[k] / n[k] for k in acc}
+    issued = 64.0 * (per["SQ_INSTS_VALU_ADD_F64"] + per["SQ_INSTS_VALU_MUL_F64"]
+                     + per["SQ_INSTS_VALU_TRANS_F64"]) + 128.0 * per["SQ_INSTS_VALU_FMA_F64"]
+    out = {"kernel": TRACK_KERNEL,
+           "workload": "scattering synchrotron sphere, 3 x N_s=1e6 (tau_T 1e-3/1e-2/1e-1)",
+           "kernel_source_hash": kernel_source_hash(),
+           "launches": max(n.values()),
+           "per_launch": per,
+           "issued_fp64_flop_per_launch": issued,
+           "convention": "64 x (ADD_F64 + MUL_F64 + TRANS_F64) + 128 x FMA_F64 per wave instruction",
+           "commands": commands}
+    with open(ISSUE_JSON, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out, indent=1))
@@ -215,11 +272,16 @@ def main():
                     help="write the tracker's HBM traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
                     help="write the kernel-trace summary from a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--summarize-issue", metavar="PMC_DIR",
+                    help="write the tracker's issued FP64 operations from a rocprofv3 --pmc run and exit")
     ap.add_argument("--commands", nargs="*", default=[],
                     help="the profiler command lines, recorded in the summaries")
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic, args.commands, args.copy_mib or 1024)
+        return
+    if args.summarize_issue:
+        summarize_issue(args.summarize_issue, args.commands)
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, " && ".join(args.commands))
@@ -302,6 +364,8 @@ def main():
     flops = algorithmic_flops(totals)
     achieved = flops / launches / (track_ms / launches * 1e-3) / 1e12 if launches else 0.0
     traffic = measured_traffic()
+    issued = measured_issue()
+    bound = register_bound(ctx, tuning["track_waves"])
     out = {
         "metric": "superphotons/s",
         "value": value,
@@ -338,6 +402,17 @@ def main():
             "avg_launch_ms": track_ms / launches if launches else None,
             "algorithmic_flops_per_launch": flops / launches if launches else None,
             "kernel_time_share": track_ms * 1e-3 / elapsed,
+            # issued FP64 rate (counters of the committed profile, per launch,
+            # over this run's launch time), and the register-limited bound:
+            # FMA chains at the tracker's waves per SIMD
+            "issued_fp64_tflops": (issued / (track_ms / launches * 1e-3) / 1e12
+                                   if issued and launches else None),
+            "register_limited_bound": {
+                "waves_per_simd": tuning["track_waves"],
+                "tflops_by_chains": {str(k): v for k, v in bound.items()},
+                "frac_of_1_chain": achieved / bound[1],
+                "frac_of_2_chains": achieved / bound[2],
+            },
         },
     }
     # time to 1 % spectral error, plain method, on the tau_T = 0.1 instance

@@ -249,6 +249,20 @@ gm_status gm_set_instance_bias(gm_ctx *ctx, int instance, int bias_mode, double 
 gm_status gm_set_timing(gm_ctx *ctx, int enable);
 gm_status gm_read_timing(gm_ctx *ctx, double *track_ms, uint64_t *track_launches);
 
+/* Register-limited FP64 bound (measurement, not a passage of the paper):
+ * runs `chains` (1, 2, 4 or 8) independent chains of `iters` dependent FP64
+ * fused multiply-adds x <- fma(x, 0.9999999, 1e-7) per lane, started at
+ * x_c = (1 + 1e-9 t) + 1e-3 c (each operation rounded) for global lane t
+ * and chain c, on exactly
+ * `waves` waves per SIMD on every CU (grid = CUs x waves blocks of 256; each
+ * block reserves LDS so that no more blocks fit), and times one launch with
+ * HIP events after a short warm-up.  Returns the time (ms) and the attained
+ * rate (TFLOP/s, FMA = 2).  host_out (n_out doubles, may be NULL with
+ * n_out = 0) receives the sums over chains of the first n_out lanes.
+ * GM_EUNSUPPORTED if the LDS cannot pin that occupancy. */
+gm_status gm_fma_chain_bound(gm_ctx *ctx, int waves, int chains, int64_t iters, double *ms, double *tflops,
+                             double *host_out, int n_out);
+
 /* ---- learned form ----------------------------------------------------
  * Not a passage of the paper: the paper names bias tuning as future work
  * (Conclusions).  A network 6 -> 64 -> 64 -> 2 (tanh hidden layers) is

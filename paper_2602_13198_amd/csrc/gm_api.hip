@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/gm.h"
+#include "gm_bound.h"
 #include "gm_emit.h"
 #include "gm_host_tables.h"
 #include "gm_mlp.h"
@@ -907,6 +908,59 @@ gm_status gm_read_timing(gm_ctx *c, double *track_ms, uint64_t *track_launches)
     if (s != GM_OK) return s;
     if (track_ms) *track_ms = c->track_ms;
     if (track_launches) *track_launches = c->track_launches;
+    return GM_OK;
+}
+
+gm_status gm_fma_chain_bound(gm_ctx *c, int waves, int chains, int64_t iters, double *ms, double *tflops,
+                             double *host_out, int n_out)
+{
+    if (!c || waves < 1 || waves > 8 || iters < 1 || n_out < 0 || (n_out > 0 && !host_out))
+        return fail(GM_EINVAL, "bad argument");
+    using Fn = void (*)(double, double, long long, double *);
+    Fn fn = chains == 1 ? (Fn)fma_chain_kernel<1> : chains == 2 ? (Fn)fma_chain_kernel<2>
+          : chains == 4 ? (Fn)fma_chain_kernel<4> : chains == 8 ? (Fn)fma_chain_kernel<8> : nullptr;
+    if (!fn) return fail(GM_EINVAL, "chains must be 1, 2, 4 or 8");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    int lds_cu = 0;
+    HIPCHK(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device));
+    // at most `waves` blocks per CU: each reserves more than 1/(waves+1) of the LDS
+    size_t lds = std::min<size_t>((size_t)lds_cu / (size_t)waves, 64 * 1024) & ~(size_t)1023;
+    int occ = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, lds));
+    if (occ != waves)
+        return fail(GM_EUNSUPPORTED, "%d waves per SIMD cannot be pinned (%zu bytes of LDS per block give %d blocks per CU)",
+                    waves, lds, occ);
+    const int grid = c->n_cu * waves;
+    const size_t n = (size_t)grid * 256;
+    if (n_out > (int64_t)n) return fail(GM_EINVAL, "n_out above %zu", n);
+    DevBuf<double> out;
+    if (out.ensure(n) != hipSuccess) return fail(GM_ENOMEM, "bound buffer");
+    const double m = 0.9999999, a = 1e-7;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        fn<<<grid, 256, lds, c->stream>>>(m, a, (long long)std::min<int64_t>(iters, 1024), out.p);   // warm-up
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    if (e == hipSuccess) {
+        fn<<<grid, 256, lds, c->stream>>>(m, a, (long long)iters, out.p);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess && n_out > 0)
+        e = hipMemcpyAsync(host_out, out.p, (size_t)n_out * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    out.release();
+    if (e != hipSuccess) return fail(GM_EDEVICE, "fma chain bound: %s", hipGetErrorString(e));
+    if (ms) *ms = t;
+    if (tflops) *tflops = 2.0 * (double)chains * (double)iters * (double)n / ((double)t * 1e-3) * 1e-12;
     return GM_OK;
 }
 

@@ -49,7 +49,7 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_read_timing", "gm_set_tuning", "gm_mlp_set_params", "gm_mlp_get_params",
            "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_set_bias_table",
            "gm_set_event_log", "gm_event_count", "gm_set_batch",
-           "gm_set_instance_bias"]
+           "gm_set_instance_bias", "gm_fma_chain_bound"]
 
 
 class GmGrid(C.Structure):
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_event_count": (i, [vp, C.POINTER(C.c_uint64)]),
         "gm_set_batch": (i, [vp, i]),
         "gm_set_instance_bias": (i, [vp, i, i, C.c_double, C.c_double]),
+        "gm_fma_chain_bound": (i, [vp, i, i, C.c_int64, dp, dp, dp, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -368,6 +369,15 @@ class Context:
         ms, n = C.c_double(0.0), C.c_uint64(0)
         _check(load_library().gm_read_timing(self._h, C.byref(ms), C.byref(n)))
         return ms.value, int(n.value)
+
+    def fma_chain_bound(self, waves: int, chains: int, iters: int, n_out: int = 0):
+        """(ms, TFLOP/s, sums of the first n_out lanes) of the FP64 FMA-chain
+        kernel at `waves` waves per SIMD with `chains` chains per lane."""
+        ms, tf = C.c_double(0.0), C.c_double(0.0)
+        out = np.zeros(max(n_out, 1))
+        _check(load_library().gm_fma_chain_bound(self._h, int(waves), int(chains), int(iters), C.byref(ms),
+                                                 C.byref(tf), _dp(out) if n_out else None, int(n_out)))
+        return ms.value, tf.value, out[:n_out]
 
     def eval_G(self, x) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.float64)
