@@ -19,6 +19,10 @@ FLAGS = [
     # keep hand-free of packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # uniform-address LDS atomics (tallies, ledgers) issued per lane: the
+    # default rewrite into a per-lane readlane loop costs more VALU than the
+    # LDS unit's own serialisation of the conflicting lanes
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function",
 ]
 

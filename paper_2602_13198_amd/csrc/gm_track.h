@@ -180,12 +180,12 @@ GM_D void lds_flush_all(const TArgs &L, double *lds, int stride)
 // wave of the block owns kEvCap slots after the block's tallies; `n` is
 // wave-uniform.
 constexpr int kEvCap = 64;
-constexpr int kEvDoubles = kEvCap * 8 + kEvCap * 6 / 2;   // 8 doubles + 6 ints per event
+constexpr int kEvDoubles = kEvCap * 8 + kEvCap * 7 / 2;   // 8 doubles + 7 ints per event
 constexpr size_t kEvBytesPerBlock = (size_t)(256 / 64) * kEvDoubles * 8;
 
 struct EvStage {
     double *d;    // [8][kEvCap]: x1, x2, x3, k0..k3, w
-    int *i;       // [6][kEvCap]: instance, stream s0 s1 s2, generation, zone
+    int *i;       // [7][kEvCap]: instance, parent stream s0 s1 s2 and block, generation, zone
     int n;
 };
 
@@ -219,8 +219,9 @@ GM_D void ev_flush(const TArgs &L, EvStage &S)
             Q.s0[q] = (uint32_t)S.i[kEvCap + l];
             Q.s1[q] = (uint32_t)S.i[2 * kEvCap + l];
             Q.s2[q] = (uint32_t)S.i[3 * kEvCap + l];
-            Q.n_sc[q] = S.i[4 * kEvCap + l];
-            Q.zone[q] = S.i[5 * kEvCap + l];
+            Q.blk[q] = (uint32_t)S.i[4 * kEvCap + l];
+            Q.n_sc[q] = S.i[5 * kEvCap + l];
+            Q.zone[q] = S.i[6 * kEvCap + l];
         } else {
             atomicOr(L.overflow, 1);
         }
@@ -229,8 +230,9 @@ GM_D void ev_flush(const TArgs &L, EvStage &S)
 }
 
 // Stage the events of the lanes in `smask` (whole wave; `scat` is this
-// lane's bit): scattering point x, incoming wavevector k, child weight,
-// child stream, child generation and plasma zone.
+// lane's bit): scattering point x, incoming wavevector k, child weight, the
+// parent's stream and counter block at the event (the scattering kernel
+// derives the child's stream from them), child generation and plasma zone.
 GM_D void ev_push(const TArgs &L, EvStage &S, uint64_t smask, bool scat, int inst, const double *x,
                   const double *k, double w, const Rng &r, int n_sc, int zone)
 {
@@ -247,8 +249,9 @@ GM_D void ev_push(const TArgs &L, EvStage &S, uint64_t smask, bool scat, int ins
         S.i[kEvCap + j] = (int)r.s0;
         S.i[2 * kEvCap + j] = (int)r.s1;
         S.i[3 * kEvCap + j] = (int)r.s2;
-        S.i[4 * kEvCap + j] = n_sc;
-        S.i[5 * kEvCap + j] = zone;
+        S.i[4 * kEvCap + j] = (int)r.block;
+        S.i[5 * kEvCap + j] = n_sc;
+        S.i[6 * kEvCap + j] = zone;
     }
     S.n += nn;
 }
@@ -697,7 +700,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
         bool scat = false;
         double wchild = 0.0;
         int zs = -1;
-        Rng crng{0u, 0u, 0u, 0u};
+        Rng ev_rng{0u, 0u, 0u, 0u};
         if (alive && !restart && (long long)ph.steps >= L.max_steps) {
             ended = END_STUCK;
             alive = false;
@@ -764,7 +767,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
                         zs = zn;
                         if (zs >= 0 && !(A.zrec[(size_t)zs * Z_STRIDE + Z_NE] > 0.0)) zs = -1;
                     }
-                    crng = child_rng(ph.rng, ph.rng.block, A.key0, A.key1);
+                    ev_rng = ph.rng;              // the parent's stream at the event
                     // the parent continues from the scattering point; its
                     // opacities there are evaluated on the next iteration
                     ph.w *= (1.0 - 1.0 / b);
@@ -840,7 +843,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
         // holds the scattering point and the incoming wavevector (the
         // parent's own, unchanged in flat spacetime) ----
         uint64_t smask = __ballot(scat);
-        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, crng, ph.n_sc + 1, zs);
+        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, ev_rng, ph.n_sc + 1, zs);
     }
     ev_flush(L, ev);
     if constexpr (BATCHED) {
@@ -946,7 +949,8 @@ __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs L)
         int z = Q.zone[i];
         int n_sc = Q.n_sc[i];
         double wchild = Q.w[i];
-        Rng r{Q.s0[i], Q.s1[i], Q.s2[i], 0u};
+        Rng r = child_rng(Rng{Q.s0[i], Q.s1[i], Q.s2[i], 0u}, Q.blk[i], A.key0, A.key1);
+        const Rng r_child = r;
         double g[4][4];
         Minkowski::gcov(x, g);
         double kc[4];
@@ -978,10 +982,10 @@ __global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs L)
 #pragma unroll
             for (int m = 0; m < 3; ++m) O.x[m][o] = x[m + 1];
             O.w[o] = wchild;
-            O.s0[o] = Q.s0[i]; O.s1[o] = Q.s1[i]; O.s2[o] = Q.s2[i];
             O.n_sc[o] = n_sc;
             O.inst[o] = ii;
         }
+        O.s0[o] = r_child.s0; O.s1[o] = r_child.s1; O.s2[o] = r_child.s2;
 #pragma unroll
         for (int m = 0; m < 4; ++m) O.k[m][o] = kc[m];
         O.wb[o] = wchild;

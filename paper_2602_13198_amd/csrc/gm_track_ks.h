@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
         bool scat = false;
         double wchild = 0.0;
         int zs = -1;
-        Rng crng{0u, 0u, 0u, 0u};
+        Rng ev_rng{0u, 0u, 0u, 0u};
         if (alive && mode == MODE_STEP && (long long)ph.steps >= L.max_steps) {
             ended = END_STUCK;
             alive = false;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                 zs = plasma_zone(A, zone_ks(A, P[0], P[1], P[2]));
                 if (zs < 0) zs = plasma_zone(A, zone_ks(A, ph.x[0], ph.x[1], ph.x[2]));
                 if (zs < 0) zs = plasma_zone(A, ph.zone_end);
-                crng = child_rng(ph.rng, ph.rng.block, A.key0, A.key1);
+                ev_rng = ph.rng;              // the parent's stream at the event
                 ph.w *= (1.0 - 1.0 / b_sc);
                 ph.x1 = -log(1.0 - rng_uniform(ph.rng, A.key0, A.key1));
                 ph.e = e_here;
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
         // ---- scattering events (the parent now sits at the scattering
         // point with the wavevector it scattered) ----
         uint64_t smask = __ballot(scat);
-        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, crng, ph.n_sc + 1, zs);
+        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, ev_rng, ph.n_sc + 1, zs);
     }
     ev_flush(L, ev);
     if constexpr (BATCHED) {
@@ -428,7 +428,8 @@ __global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs L)
         int z = Q.zone[i];
         int n_sc = Q.n_sc[i];
         double wchild = Q.w[i];
-        Rng r{Q.s0[i], Q.s1[i], Q.s2[i], 0u};
+        Rng r = child_rng(Rng{Q.s0[i], Q.s1[i], Q.s2[i], 0u}, Q.blk[i], A.key0, A.key1);
+        const Rng r_child = r;
         KMetric K;
         kerr_metric<false>(A.a_spin, A.h_slope, Q.x[0][i], Q.x[1][i], K);
         double g[4][4];
@@ -464,10 +465,10 @@ __global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs L)
 #pragma unroll
             for (int m = 0; m < 3; ++m) O.x[m][o] = Q.x[m][i];
             O.w[o] = wchild;
-            O.s0[o] = Q.s0[i]; O.s1[o] = Q.s1[i]; O.s2[o] = Q.s2[i];
             O.n_sc[o] = n_sc;
             O.inst[o] = ii;
         }
+        O.s0[o] = r_child.s0; O.s1[o] = r_child.s1; O.s2[o] = r_child.s2;
 #pragma unroll
         for (int m = 0; m < 4; ++m) O.k[m][o] = kc[m];
         O.wb[o] = wchild;
