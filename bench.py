@@ -105,6 +105,40 @@ def register_bound(ctx, waves, target_ms=40.0):
     return out
 
 
+def kerr_torus_form(ctx, instance, runs=2):
+    """Superphotons/s on the synthetic Kerr torus (a = 0.9375, 256 x 128 MKS
+    zones, N_s = 1e7, 200 x 6 bins) in FP64 and in the FP32-emissivity form:
+    one untimed round, then `runs` timed make + track + read rounds each."""
+    import torch
+    from paper_2602_13198_amd import workloads as W
+    wl = W.torus(n_target=1e7)
+    ctx.load_zones(wl, instance)
+    out = {"workload": "Kerr torus a=0.9375, 256x128 modified Kerr-Schild zones, Fishbone-Moncrief "
+                       "torus with 5% log-normal perturbations, R-beta electrons (R_high=40), "
+                       "b = 1e3 Theta_e^2, N_s=1e7, 200x6 bins"}
+    for prec, key in ((0, "f64"), (1, "f32_emissivity")):
+        def one(seed):
+            ctx.make_superphotons(dict(wl.emit, seed=seed), instance=instance)
+            st = ctx.track_scatter(dict(wl.track, precision=prec))
+            ctx.read_spectrum(instance, reset=True)
+            return st
+        one(7000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tot = None
+        for r in range(runs):
+            st = one(7001 + r)
+            tot = st if tot is None else tot + st
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nsp = int(tot[0] + tot[1])
+        out[key] = {"value": nsp / dt, "unit": "superphotons/s", "seconds_per_round": dt / runs,
+                    "superphotons_per_round": nsp / runs, "steps_per_superphoton": float(tot[2]) / max(nsp, 1),
+                    "geodesic_steps_per_s": float(tot[2]) / dt}
+    out["f32_speedup"] = out["f32_emissivity"]["value"] / out["f64"]["value"]
+    return out
+
+
 TRACK_KERNEL = "track_kernel_flat<2, false, false>"
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_traffic.json")
 TRACE_TXT = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_kernel_trace.txt")
@@ -479,7 +513,8 @@ def main():
             "value": n32 / el32, "unit": "superphotons/s", "ms_per_step": el32 / args.steps * 1e3,
             "avg_track_launch_ms": ms32 / l32 if l32 else None,
             "speedup_vs_f64": (n32 / el32) / value,
-        }
+        },
+        "kerr_torus": kerr_torus_form(ctx, len(wls)),
     }
     if ttx is not None:
         out["time_to_1pct"] = ttx

@@ -839,9 +839,9 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
             BlockAcc B = lds_acc(lds, stride, 0);
             advance(Lh, B);
         }
-        // ---- scattering events: one slot reservation per wave; the event
-        // holds the scattering point and the incoming wavevector (the
-        // parent's own, unchanged in flat spacetime) ----
+        // ---- scattering events, staged per wave in LDS: the scattering
+        // point and the incoming wavevector (the parent's own, unchanged in
+        // flat spacetime) ----
         uint64_t smask = __ballot(scat);
         if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, ev_rng, ph.n_sc + 1, zs);
     }
