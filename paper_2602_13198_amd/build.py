@@ -38,5 +38,42 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+def resources() -> str:
+    """Per-kernel register, scratch, LDS and occupancy figures as the
+    compiler reports them for this build (-Rpass-analysis=kernel-resource-usage),
+    as a text table.  Dynamic LDS (tallies, event staging) is set per launch
+    and not part of these figures."""
+    import re
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        cmd = [HIPCC] + [f for f in FLAGS if f not in ("-shared", "-fPIC")] + [
+            "-c", "-Rpass-analysis=kernel-resource-usage", "-o", os.path.join(d, "gm.o"), SRC]
+        r = subprocess.run(cmd, capture_output=True, text=True, check=True)
+    rows, cur = [], None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark:\s+(Function Name|VGPRs Spill|VGPRs|AGPRs|TotalSGPRs|ScratchSize \[bytes/lane\]|"
+                      r"Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]): (\S+)", line)
+        if not m:
+            continue
+        k, v = m.group(1), m.group(2)
+        if k == "Function Name":
+            cur = {"name": v}
+            rows.append(cur)
+        elif cur is not None:
+            cur[{"VGPRs Spill": "Spill", "TotalSGPRs": "SGPRs"}.get(k, k.split(" ")[0])] = v
+    keep = [x for x in rows if "_ZN2gm" in x["name"] and "kernel" in x["name"]]
+    out = ["# kernel resources of libgm.so for gfx950 (compiler report)",
+           "# command: python -m paper_2602_13198_amd.build --resources",
+           "# kernel | VGPRs | AGPRs | SGPRs | VGPR spills | scratch B/lane | static LDS B/block | occupancy waves/SIMD"]
+    for x in keep:
+        out.append("%s | %s | %s | %s | %s | %s | %s | %s" % (
+            x["name"], x.get("VGPRs", "?"), x.get("AGPRs", "?"), x.get("SGPRs", "?"), x.get("Spill", "?"),
+            x.get("ScratchSize", "?"), x.get("LDS", "?"), x.get("Occupancy", "?")))
+    return "\n".join(out) + "\n"
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--resources" in sys.argv:
+        sys.stdout.write(resources())
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -932,7 +932,7 @@ GM_D void log_event(const TArgs &A, const Rng &child, int z, double eps, double 
 // child's own optical-depth draw.
 // ---------------------------------------------------------------------------
 template <bool F32, bool BATCHED>
-__global__ __launch_bounds__(256) void scatter_kernel_flat(TArgs L)
+__global__ __launch_bounds__(256, 2) void scatter_kernel_flat(TArgs L)
 {
     extern __shared__ double lds[];
     const int stride = L_N + S_N;

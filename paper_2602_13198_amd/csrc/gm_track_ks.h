@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 // the child's stream, then the child's optical-depth draw.  The child's
 // opacities and acceleration are evaluated when the tracker loads it.
 template <bool BATCHED>
-__global__ __launch_bounds__(256) void scatter_kernel_ks(TArgs L)
+__global__ __launch_bounds__(256, 2) void scatter_kernel_ks(TArgs L)
 {
     extern __shared__ double lds[];
     const int stride = L_N + S_N;
