@@ -235,6 +235,21 @@ gm_status gm_set_tuning(gm_ctx *ctx, int track_waves, int refill_min);
  * the 56 KiB LDS tally budget.  Results do not depend on it. */
 gm_status gm_set_batch(gm_ctx *ctx, int max_instances);
 
+/* Photon queues (scheduling; results do not depend on it beyond the order
+ * of FP64 tally sums).  gm_track_scatter runs the roots in chunks of half the
+ * queue capacity through all scattering generations.  A chunk whose
+ * children overflow a queue is undone -- tallies, ledgers, counters and the
+ * trace and event-log counts restored -- and redone in quarters; histories
+ * are keyed by their roots, so the redone chunk gives the same photons.
+ * GM_ENOMEM only if the cascade of a single root overflows.
+ * gm_set_queue_capacity fixes the capacity in entries (0 = automatic:
+ * max(2^22, 2 x pending roots), at most 2^26; otherwise 64 .. 2^27), 128
+ * bytes per entry per queue, two queues.  gm_queue_stats returns the
+ * capacity of the last gm_track_scatter and the number of chunks redone
+ * since the context was created. */
+gm_status gm_set_queue_capacity(gm_ctx *ctx, uint64_t entries);
+gm_status gm_queue_stats(gm_ctx *ctx, uint64_t *capacity, uint64_t *chunk_retries);
+
 /* Scattering bias of one instance (GM_BIAS_*, value, maximum), overriding
  * the bias of the track parameters for it, so that instances with
  * different biases share launches; bias_mode < 0 removes the override.

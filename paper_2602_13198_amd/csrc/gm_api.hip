@@ -112,7 +112,13 @@ struct gm_ctx {
     ShTable32 sh32{};
     bool sh_built = false;
     // photon queues (ping-pong between generations) and per-generation counters
-    unsigned long long child_cap = 0;
+    unsigned long long child_cap = 0;           // allocated entries per queue
+    unsigned long long queue_cap = 0;           // entries in use (<= child_cap)
+    unsigned long long queue_cap_set = 0;       // fixed by gm_set_queue_capacity, 0 = automatic
+    // accumulators of the instances of a root chunk, kept to redo the chunk
+    DevBuf<double> bak_d;
+    DevBuf<unsigned long long> bak_u;
+    unsigned long long chunk_retries = 0;
     DevBuf<double> qd[2][13];
     DevBuf<uint32_t> qu[2][4];
     DevBuf<int32_t> qi[2][3];
@@ -446,6 +452,7 @@ gm_status gm_make_superphotons(gm_ctx *c, int instance, const gm_emit_params *p,
 
 static gm_status ensure_children(gm_ctx *c, unsigned long long cap)
 {
+    c->queue_cap = cap;
     if (c->child_cap >= cap) return GM_OK;
     for (int b = 0; b < 2; ++b) {
         for (auto &d : c->qd[b])
@@ -588,7 +595,7 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
     A.lnb_lo = I.lnb_lo;
     A.lnb_inv_d = I.lnb_n > 1 ? (I.lnb_n - 1) / (I.lnb_hi - I.lnb_lo) : 0.0;
     A.overflow = c->flags.p;
-    A.cap = c->child_cap;
+    A.cap = c->queue_cap;
     A.refill_min = c->refill_min;
     A.a_spin = I.grid.a_spin;
     A.h_slope = I.grid.h_slope;
@@ -665,9 +672,26 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     // generations 0 .. n_sc_max: only photons below the cap can scatter
     const int ngen = tp->scattering ? tp->n_sc_max + 1 : 1;
     const unsigned long long total = off[n_inst];
-    const unsigned long long chunk = std::max<unsigned long long>(1, c->child_cap / 2);
-    for (unsigned long long start = 0; start < total; start += chunk) {
+    // roots in chunks of half the queue; a chunk whose scattering cascade
+    // overflows the queue is undone (tallies, ledgers, counters, trace and
+    // event-log counts restored) and redone in quarters -- every history is
+    // keyed by its root, so the redone chunk gives the same photons
+    unsigned long long chunk = std::max<unsigned long long>(1, c->queue_cap / 2);
+    const size_t nacc_d = nspec + L_N, nacc_u = S_N;
+    if (c->bak_d.ensure((size_t)n_inst * nacc_d) != hipSuccess ||
+        c->bak_u.ensure((size_t)n_inst * nacc_u + 2) != hipSuccess)
+        return fail(GM_ENOMEM, "chunk backup");
+    for (unsigned long long start = 0; start < total;) {
         const unsigned long long cnt = std::min(chunk, total - start);
+        for (int k = 0; k < n_inst; ++k) {
+            Instance &I = c->inst[ids[k]];
+            HIPCHK(hipMemcpyAsync(c->bak_d.p + k * nacc_d, I.spec.p, nspec * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(c->bak_d.p + k * nacc_d + nspec, I.ledger.p, L_N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(c->bak_u.p + k * nacc_u, I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        }
+        unsigned long long *bak_n = c->bak_u.p + (size_t)n_inst * nacc_u;
+        HIPCHK(hipMemcpyAsync(bak_n, c->trace_n.p, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(bak_n + 1, c->evlog_n.p, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
         reset_counters_kernel<<<1, 64, 0, c->stream>>>(c->ctr.p, 64, c->flags.p);
         L.root_begin = start;
         L.root_count = cnt;
@@ -708,7 +732,22 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
         int ovf = 0;
         HIPCHK(hipMemcpyAsync(&ovf, c->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        if (ovf) return fail(GM_ENOMEM, "photon queue of %llu overflowed", c->child_cap);
+        if (!ovf) {
+            start += cnt;
+            continue;
+        }
+        if (cnt == 1)
+            return fail(GM_ENOMEM, "the scattering cascade of one root overflows the photon queue of %llu", c->queue_cap);
+        for (int k = 0; k < n_inst; ++k) {
+            Instance &I = c->inst[ids[k]];
+            HIPCHK(hipMemcpyAsync(I.spec.p, c->bak_d.p + k * nacc_d, nspec * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(I.ledger.p, c->bak_d.p + k * nacc_d + nspec, L_N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(I.stats.p, c->bak_u.p + k * nacc_u, S_N * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHK(hipMemcpyAsync(c->trace_n.p, bak_n, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->evlog_n.p, bak_n + 1, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        c->chunk_retries += 1;
+        chunk = std::max<unsigned long long>(1, cnt / 4);
     }
     for (int k = 0; k < n_inst; ++k) {
         Instance &I = c->inst[ids[k]];
@@ -750,6 +789,7 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     for (auto &I : c->inst)
         if (I.pending) need = std::max(need, 2 * I.n_roots);
     need = std::min(need, 1ull << 26);
+    if (c->queue_cap_set) need = c->queue_cap_set;
     s = ensure_children(c, need);
     if (s != GM_OK) return s;
     // instances of one metric share launches, as many as their LDS tallies
@@ -874,6 +914,23 @@ gm_status gm_set_instance_bias(gm_ctx *c, int instance, int bias_mode, double bi
     I.bias_mode = bias_mode < 0 ? -1 : bias_mode;
     I.bias_value = bias_value;
     I.bias_max = bias_max;
+    return GM_OK;
+}
+
+gm_status gm_set_queue_capacity(gm_ctx *c, uint64_t entries)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (entries != 0 && (entries < 64 || entries > (1ull << 27)))
+        return fail(GM_EINVAL, "queue capacity %llu not 0 or in [64, 2^27]", (unsigned long long)entries);
+    c->queue_cap_set = entries;
+    return GM_OK;
+}
+
+gm_status gm_queue_stats(gm_ctx *c, uint64_t *capacity, uint64_t *chunk_retries)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (capacity) *capacity = c->queue_cap;
+    if (chunk_retries) *chunk_retries = c->chunk_retries;
     return GM_OK;
 }
 

@@ -49,7 +49,8 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_read_timing", "gm_set_tuning", "gm_mlp_set_params", "gm_mlp_get_params",
            "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_set_bias_table",
            "gm_set_event_log", "gm_event_count", "gm_set_batch",
-           "gm_set_instance_bias", "gm_fma_chain_bound"]
+           "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
+           "gm_queue_stats"]
 
 
 class GmGrid(C.Structure):
@@ -117,6 +118,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_set_batch": (i, [vp, i]),
         "gm_set_instance_bias": (i, [vp, i, i, C.c_double, C.c_double]),
         "gm_fma_chain_bound": (i, [vp, i, i, C.c_int64, dp, dp, dp, i]),
+        "gm_set_queue_capacity": (i, [vp, u64]),
+        "gm_queue_stats": (i, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -369,6 +372,16 @@ class Context:
         ms, n = C.c_double(0.0), C.c_uint64(0)
         _check(load_library().gm_read_timing(self._h, C.byref(ms), C.byref(n)))
         return ms.value, int(n.value)
+
+    def set_queue_capacity(self, entries: int = 0):
+        """Fix the photon-queue capacity (entries; 0 = automatic)."""
+        _check(load_library().gm_set_queue_capacity(self._h, int(entries)))
+
+    def queue_stats(self):
+        """(capacity of the last track call, chunks redone after an overflow)."""
+        cap, n = C.c_uint64(0), C.c_uint64(0)
+        _check(load_library().gm_queue_stats(self._h, C.byref(cap), C.byref(n)))
+        return int(cap.value), int(n.value)
 
     def fma_chain_bound(self, waves: int, chains: int, iters: int, n_out: int = 0):
         """(ms, TFLOP/s, sums of the first n_out lanes) of the FP64 FMA-chain

@@ -256,3 +256,32 @@ def test_batched_launch_equals_separate(gm, kind):
     for (a, la), (b, lb) in zip(p1, p2):
         np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
         np.testing.assert_allclose(la, lb, rtol=1e-12, atol=1e-300)
+
+
+def test_queue_overflow_redoes_chunks(gm):
+    """A scattering cascade that overflows a small photon queue is undone and
+    redone in smaller root chunks: the photon histories are bitwise those of
+    a run whose queue is large enough, the counters equal, and the tallies
+    equal up to summation order."""
+    wl = W.scattering_sphere(0.1, n_target=3000, seed=31)
+    track = dict(wl.track, bias_value=30.0)      # b tau_T = 3: the cascade triples per generation
+    out = {}
+    for cap in (0, 2048):
+        c = gm.Context(0)
+        c.set_queue_capacity(cap)
+        c.load_zones(wl)
+        c.make_superphotons(wl.emit)
+        c.set_trace(1_000_000)
+        st = c.track_scatter(track)
+        spec, led = c.read_spectrum()
+        tr = np.sort(c.read_trace(), order=["s2", "s1", "s0"])
+        qcap, retries = c.queue_stats()
+        c.close()
+        out[cap] = (st, spec, led, tr, qcap, retries)
+    big, small = out[0], out[2048]
+    assert big[5] == 0 and small[4] == 2048 and small[5] > 0, (big[4:], small[4:])
+    assert len(big[3]) > 20000 and np.unique(big[3]["n_sc"]).size == 5
+    assert np.array_equal(big[3].view(np.uint8), small[3].view(np.uint8))
+    np.testing.assert_array_equal(big[0], small[0])
+    np.testing.assert_allclose(small[1], big[1], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(small[2], big[2], rtol=1e-12, atol=1e-300)
