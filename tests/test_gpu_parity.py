@@ -285,3 +285,20 @@ def test_queue_overflow_redoes_chunks(gm):
     np.testing.assert_array_equal(big[0], small[0])
     np.testing.assert_allclose(small[1], big[1], rtol=1e-12, atol=0)
     np.testing.assert_allclose(small[2], big[2], rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("wl", [
+    W.sphere(n=1, n_target=300, seed=11, theta_e=4.0, n_e=1.5e9).with_track(
+        scattering=1, bias_value=10.0, n_nu=1, n_theta=1),                       # one zone, one bin
+    W.sphere(n=3, n_target=37, seed=12, theta_e=4.0, n_e=1.5e9).with_track(
+        scattering=1, bias_value=10.0),                                          # 28 roots: under one wave
+    W.scattering_sphere(0.1, n_target=70, seed=13, n=5),                         # ragged grid and lanes
+], ids=["grid1_bin1", "grid3_28roots", "grid5_50roots"])
+def test_degenerate_sizes_same_seed(gm, oracle_lib, wl):
+    """Tiny, ragged and single-bin cases: every photon of every generation
+    matches the oracle, and so do the tally and the ledger."""
+    g, ores, n, bad = _trace_parity(gm, oracle_lib, wl, cap=100000, max_bad_frac=0.0)
+    assert np.unique(g["trace"]["n_sc"]).size == 5
+    np.testing.assert_array_equal(g["spec"][..., 2], ores.spectrum[..., 2])
+    np.testing.assert_allclose(g["spec"][..., 0], ores.spectrum[..., 0], rtol=1e-9, atol=0)
+    np.testing.assert_allclose(g["ledger"], ores.ledger, rtol=1e-9, atol=1e-300)
