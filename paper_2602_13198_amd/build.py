@@ -19,6 +19,9 @@ FLAGS = [
     # keep hand-free of packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # fuse a*b+c only within one source expression, so that every compiled
+    # variant of a kernel rounds the same expression the same way
+    "-ffp-contract=on",
     # uniform-address LDS atomics (tallies, ledgers) issued per lane: the
     # default rewrite into a per-lane readlane loop costs more VALU than the
     # LDS unit's own serialisation of the conflicting lanes

@@ -124,6 +124,41 @@ struct Coef {
     bool vacuum;
 };
 
+// The instance fields a flat step reads.  A batched launch gathers them once
+// per change of a wave's instance instead of re-reading them field by field
+// from the per-instance argument blocks on every step.
+struct StepArgs {
+    const double *zrec;
+    const float *zrec32;
+    int n[3];
+    double xs[3], xe[3], inv_dx[3];
+    double C, step_h, roulette_frac, roulette_p;
+    int scattering, n_sc_max, bias_mode;
+    uint32_t key0, key1;
+    double bias_value, bias_max, L_unit_cm;
+    ShTable sh;
+    ShTable32 sh32;
+    float ln_c2_2h;
+    const double *lnb;
+    int lnb_n;
+    double lnb_lo, lnb_inv_d;
+};
+
+GM_D StepArgs step_args(const TArgs &T)
+{
+    StepArgs S;
+    S.zrec = T.zrec; S.zrec32 = T.zrec32;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { S.n[j] = T.n[j]; S.xs[j] = T.xs[j]; S.xe[j] = T.xe[j]; S.inv_dx[j] = T.inv_dx[j]; }
+    S.C = T.C; S.step_h = T.step_h; S.roulette_frac = T.roulette_frac; S.roulette_p = T.roulette_p;
+    S.scattering = T.scattering; S.n_sc_max = T.n_sc_max; S.bias_mode = T.bias_mode;
+    S.key0 = T.key0; S.key1 = T.key1;
+    S.bias_value = T.bias_value; S.bias_max = T.bias_max; S.L_unit_cm = T.L_unit_cm;
+    S.sh = T.sh; S.sh32 = T.sh32; S.ln_c2_2h = T.ln_c2_2h;
+    S.lnb = T.lnb; S.lnb_n = T.lnb_n; S.lnb_lo = T.lnb_lo; S.lnb_inv_d = T.lnb_inv_d;
+    return S;
+}
+
 // Per-block accumulators in LDS.
 struct BlockAcc {
     double *spec, *ledger;
@@ -271,12 +306,13 @@ GM_D int inst_of_root(const TArgs &L, unsigned long long g)
 // The instance of the first lane of `mask`, as a wave-uniform value.
 GM_D int uniform_inst(uint64_t mask, int inst)
 {
-    int first = __ffsll((unsigned long long)mask) - 1;
-    return __builtin_amdgcn_readfirstlane(__shfl(inst, first));
+    int first = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)mask) - 1);
+    return __builtin_amdgcn_readlane(inst, first);
 }
 
 // Zone holding a Cartesian point, or -1 outside the grid (vacuum).
-GM_D int zone_cart(const TArgs &A, double x1, double x2, double x3)
+template <class Args>
+GM_D int zone_cart(const Args &A, double x1, double x2, double x3)
 {
     double f1 = floor((x1 - A.xs[0]) * A.inv_dx[0]);
     double f2 = floor((x2 - A.xs[1]) * A.inv_dx[1]);
@@ -305,7 +341,8 @@ GM_D int zone_ks(const TArgs &A, double x1, double x2, double x3)
 // (ln b of the zone interpolated linearly in ln eps on its node table);
 // clamped to [1, bias_max].  Any b >= 1 keeps the estimator unbiased: the
 // child carries w/b, the parent keeps w(1 - 1/b).
-GM_D double bias_at(const TArgs &A, int z, double theta, double ne, int n_sc, double eps)
+template <class Args>
+GM_D double bias_at(const Args &A, int z, double theta, double ne, int n_sc, double eps)
 {
     double b;
     if (A.bias_mode == 0) b = A.bias_value;
@@ -326,8 +363,8 @@ GM_D double bias_at(const TArgs &A, int z, double theta, double ne, int n_sc, do
 // (Absorption and Scattering sections): alpha = j / B_nu (Kirchhoff),
 // alpha_sc = n_e sigma_h; and the bias at that point.  g is the metric at
 // the point; FLAT zones carry their unit u and field direction already.
-template <bool FLAT>
-GM_D Coef coefficients_at64(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
+template <bool FLAT, class Args>
+GM_D Coef coefficients_at64(const Args &A, int z, const double g[4][4], const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
@@ -374,8 +411,8 @@ GM_D Coef coefficients_at64(const TArgs &A, int z, const double g[4][4], const d
 
 // The same in the FP32 form: frame products in double, then emissivity,
 // absorption and the hot cross section as FP32 logarithms and one exp each.
-template <bool FLAT>
-GM_D Coef coefficients_at32(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
+template <bool FLAT, class Args>
+GM_D Coef coefficients_at32(const Args &A, int z, const double g[4][4], const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
@@ -408,15 +445,15 @@ GM_D Coef coefficients_at32(const TArgs &A, int z, const double g[4][4], const d
     return c;
 }
 
-template <bool FLAT, bool F32 = false>
-GM_D Coef coefficients_at(const TArgs &A, int z, const double g[4][4], const double *k, int n_sc)
+template <bool FLAT, bool F32 = false, class Args>
+GM_D Coef coefficients_at(const Args &A, int z, const double g[4][4], const double *k, int n_sc)
 {
     if constexpr (F32) return coefficients_at32<FLAT>(A, z, g, k, n_sc);
     else return coefficients_at64<FLAT>(A, z, g, k, n_sc);
 }
 
-template <class M, bool F32 = false>
-GM_D Coef coefficients(const TArgs &A, int z, const double *x, const double *k, int n_sc)
+template <class M, bool F32 = false, class Args>
+GM_D Coef coefficients(const Args &A, int z, const double *x, const double *k, int n_sc)
 {
     double g[4][4];
     M::gcov(x, g);
@@ -642,6 +679,8 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
     const unsigned long long n_src = min(*L.src_count, L.cap);
     Photon ph;
     ph.inst = 0;
+    StepArgs cur{};                         // batched: the step fields of the current instance
+    int cur_inst = -1;
     bool alive = false, exhausted = false, restart = false;
     int ended = 0;                          // end kind awaiting bookkeeping
     // one instance: the arguments every step reads, held in registers
@@ -707,7 +746,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
         }
         // one step (or restart, or load evaluation) of this lane's photon
         // with the arguments of its instance
-        auto advance = [&](const TArgs &A, BlockAcc &B) {
+        auto advance = [&](const auto &A, BlockAcc &B) {
             // ---- the point where the opacities are needed ----
             double dl = 0.0;
             double xn[3];
@@ -830,9 +869,13 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
                 const int iu = uniform_inst(todo, ph.inst);
                 const bool mine = ((todo >> lane_id()) & 1ull) && ph.inst == iu;
                 todo &= ~__ballot(mine);
+                if (iu != cur_inst) {
+                    cur = step_args(L.insts[iu]);
+                    cur_inst = iu;
+                }
                 if (mine) {
                     BlockAcc B = lds_acc(lds, stride, iu);
-                    advance(L.insts[iu], B);
+                    advance(cur, B);
                 }
             }
         } else if (alive) {
