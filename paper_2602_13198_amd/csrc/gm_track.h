@@ -679,7 +679,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
     const unsigned long long n_src = min(*L.src_count, L.cap);
     Photon ph;
     ph.inst = 0;
-    StepArgs cur{};                         // batched: the step fields of the current instance
+    StepArgs cur{};                         // batched: the step fields of this lane's instance
     int cur_inst = -1;
     bool alive = false, exhausted = false, restart = false;
     int ended = 0;                          // end kind awaiting bookkeeping
@@ -731,6 +731,12 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
                         load_photon(L.src, idx, ph);
                         alive = true;
                         restart = false;
+                        if constexpr (BATCHED) {
+                            if (ph.inst != cur_inst) {
+                                cur = step_args(L.insts[ph.inst]);
+                                cur_inst = ph.inst;
+                            }
+                        }
                     }
                 }
             }
@@ -864,19 +870,11 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
             }
         };
         if constexpr (BATCHED) {
-            // one instance at a time, with wave-uniform instance arguments
-            for (uint64_t todo = __ballot(alive); todo;) {
-                const int iu = uniform_inst(todo, ph.inst);
-                const bool mine = ((todo >> lane_id()) & 1ull) && ph.inst == iu;
-                todo &= ~__ballot(mine);
-                if (iu != cur_inst) {
-                    cur = step_args(L.insts[iu]);
-                    cur_inst = iu;
-                }
-                if (mine) {
-                    BlockAcc B = lds_acc(lds, stride, iu);
-                    advance(cur, B);
-                }
+            // every lane with its own instance's fields: one pass for the
+            // wave whatever instances its photons belong to
+            if (alive) {
+                BlockAcc B = lds_acc(lds, stride, ph.inst);
+                advance(cur, B);
             }
         } else if (alive) {
             BlockAcc B = lds_acc(lds, stride, 0);
