@@ -60,20 +60,26 @@ def algorithmic_flops(st) -> float:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("gm_track.h", "gm_frame.h", "gm_physics.h", "gm_common.h", "gm_emis32.h", "gm_kerr.h"):
+    for f in ("gm_track.h", "gm_frame.h", "gm_physics.h", "gm_common.h", "gm_emis32.h", "gm_kerr.h",
+              "gm_track_ks.h", "gm_api.hip"):
         h.update(open(os.path.join(ROOT, "paper_2602_13198_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def track_variant(waves: int, batch: int) -> str:
+    """Name of the compiled FP64 flat tracker a tuning selects."""
+    return "track_kernel_flat<%d, false, %s>" % (waves, "true" if batch > 1 else "false")
+
+
+def measured_traffic(variant):
     """HBM bytes per tracking launch from the committed counter summary, if
-    it was taken on the current kernel source (else None)."""
+    it was taken on the current kernel source and the same variant (else None)."""
     p = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_traffic.json")
     try:
         d = json.load(open(p))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != variant:
         return None
     return d.get("bytes_per_launch")
 
@@ -81,14 +87,15 @@ def measured_traffic():
 ISSUE_JSON = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_fp64_issue.json")
 
 
-def measured_issue():
+def measured_issue(variant):
     """Issued FP64 operations per tracking launch from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
+    summary, if it was taken on the current kernel source and the same
+    variant (else None)."""
     try:
         d = json.load(open(ISSUE_JSON))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != variant:
         return None
     return d.get("issued_fp64_flop_per_launch")
 
@@ -139,7 +146,9 @@ def kerr_torus_form(ctx, instance, runs=2):
     return out
 
 
-TRACK_KERNEL = "track_kernel_flat<2, false, false>"
+# the variant the committed profiles cover: 2 waves/SIMD, the three
+# instances in shared launches (what the autotuner picks on this workload)
+TRACK_KERNEL = track_variant(2, 64)
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_traffic.json")
 TRACE_TXT = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_kernel_trace.txt")
 
@@ -159,8 +168,8 @@ def summarize_traffic(fetch_dir, write_dir, commands, copy_mib):
     WRITE_SIZE): KiB per launch, each scaled by what the same counter reads
     for the plain device copy of known size in the same run."""
     out = {"kernel": TRACK_KERNEL,
-           "workload": "scattering synchrotron sphere, 3 x N_s=1e6 (tau_T 1e-3/1e-2/1e-1), "
-                       "one bench step = 15 tracking launches",
+           "workload": "scattering synchrotron sphere, 3 x N_s=1e6 (tau_T 1e-3/1e-2/1e-1) in shared "
+                       "launches, one bench step = 5 tracking launches",
            "kernel_source_hash": kernel_source_hash()}
     factors = {}
     for key, d in (("fetch", fetch_dir), ("write", write_dir)):
@@ -397,8 +406,9 @@ def main():
     value = n_sp / elapsed
     flops = algorithmic_flops(totals)
     achieved = flops / launches / (track_ms / launches * 1e-3) / 1e12 if launches else 0.0
-    traffic = measured_traffic()
-    issued = measured_issue()
+    variant = track_variant(tuning["track_waves"], tuning["batch"])
+    traffic = measured_traffic(variant)
+    issued = measured_issue(variant)
     bound = register_bound(ctx, tuning["track_waves"])
     out = {
         "metric": "superphotons/s",
@@ -431,7 +441,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "track_kernel_flat",
+            "kernel": variant,
             "launches": launches,
             "avg_launch_ms": track_ms / launches if launches else None,
             "algorithmic_flops_per_launch": flops / launches if launches else None,

@@ -243,7 +243,8 @@ gm_status gm_set_batch(gm_ctx *ctx, int max_instances);
  * are keyed by their roots, so the redone chunk gives the same photons.
  * GM_ENOMEM only if the cascade of a single root overflows.
  * gm_set_queue_capacity fixes the capacity in entries (0 = automatic:
- * max(2^22, 2 x pending roots), at most 2^26; otherwise 64 .. 2^27), 128
+ * max(2^22, 2 x the roots of all pending instances), at most 2^26;
+ * otherwise 64 .. 2^27), 128
  * bytes per entry per queue, two queues.  gm_queue_stats returns the
  * capacity of the last gm_track_scatter and the number of chunks redone
  * since the context was created. */

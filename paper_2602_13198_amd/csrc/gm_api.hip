@@ -785,9 +785,12 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
         s = ensure_sigma_hot(c);
         if (s != GM_OK) return s;
     }
-    unsigned long long need = 1ull << 22;
+    // room for the roots of every pending instance (shared launches run
+    // them as one chunk) and as many children per generation
+    unsigned long long pending = 0;
     for (auto &I : c->inst)
-        if (I.pending) need = std::max(need, 2 * I.n_roots);
+        if (I.pending) pending += I.n_roots;
+    unsigned long long need = std::max(1ull << 22, 2 * pending);
     need = std::min(need, 1ull << 26);
     if (c->queue_cap_set) need = c->queue_cap_set;
     s = ensure_children(c, need);
