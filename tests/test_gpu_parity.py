@@ -302,3 +302,44 @@ def test_degenerate_sizes_same_seed(gm, oracle_lib, wl):
     np.testing.assert_array_equal(g["spec"][..., 2], ores.spectrum[..., 2])
     np.testing.assert_allclose(g["spec"][..., 0], ores.spectrum[..., 0], rtol=1e-9, atol=0)
     np.testing.assert_allclose(g["ledger"], ores.ledger, rtol=1e-9, atol=1e-300)
+
+
+def test_bench_configuration_sampled(gm, oracle_lib):
+    """The benchmark's workload in the launch configuration it times: the
+    three scattering spheres (tau_T 1e-3, 1e-2, 1e-1, N_s = 1e6 each,
+    b = 1/tau_T) in shared launches, tracker at 2 waves/SIMD refilling at 16
+    idle lanes.  Every photon is traced on the GPU; the oracle recomputes
+    sampled root families of every instance."""
+    wls = [W.scattering_sphere(t, n_target=1e6, seed=0, instance=i) for i, t in enumerate((1e-3, 1e-2, 1e-1))]
+    c = gm.Context(0)
+    c.set_tuning(2, 16)
+    c.set_batch(64)
+    ns = []
+    for i, wl in enumerate(wls):
+        c.load_zones(wl, i)
+        c.set_instance_bias(i, wl.track)
+        ns.append(c.make_superphotons(wl.emit, i))
+    c.set_trace(8_000_000)
+    st = c.track_scatter(wls[0].track)
+    tr = c.read_trace()
+    leds = [c.read_spectrum(i)[1] for i in range(len(wls))]
+    c.close()
+    assert len(tr) == st[0] + st[1] and st[0] == sum(ns)
+
+    def key(a):
+        return (a["s0"].astype(np.uint64) << np.uint64(32)) | a["s1"].astype(np.uint64)
+    rng = np.random.default_rng(2)
+    for i, wl in enumerate(wls):
+        o = oracle_lib.Oracle()
+        o.load_zones(wl)
+        n = o.make_superphotons(wl.emit)
+        assert n == ns[i]
+        starts = np.sort(rng.choice(n - 30, 8, replace=False))
+        ora = np.concatenate([o.track_scatter(wl.track, int(s), int(s) + 30, trace_cap=100000) for s in starts])
+        o.close()
+        sub = tr[np.isin(key(tr), key(ora))]
+        m, bad = compare_traces(sub, ora, subset=True)
+        assert m == len(ora) and m >= 240, (i, m, len(ora))
+        assert len(bad) <= max(1, 1e-3 * m), describe(sub, ora, bad)
+        wr, er = ledger_residuals(leds[i])
+        assert abs(wr) < 1e-12 and abs(er) < 1e-12
