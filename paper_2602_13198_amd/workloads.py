@@ -139,6 +139,37 @@ def scattering_sphere(tau_T: float = 0.1, n_target=1e6, seed=0, n=32, instance=0
     return wl
 
 
+def corona_sphere(n_target=1e6, seed=0, n=32, instance=0, r_core=0.3, theta_core=4.0,
+                  tau_core=0.1, B_core=1.0, theta_shell=30.0, tau_shell=0.1, bias_value=10.0) -> Workload:
+    """Synchrotron core inside a hot scattering shell (a flat stand-in for an
+    accretion flow under a corona): zones whose centre lies within r_core R
+    hold the core (Theta_e = theta_core, radial Thomson depth tau_core,
+    field B_core along z); zones out to R hold the shell (Theta_e =
+    theta_shell, radial Thomson depth tau_shell over its thickness, no
+    field, so no emission); beyond R is vacuum.  Static plasma; thermal
+    Compton with a constant bias, up to four generations.  The shell's
+    inverse-Compton photons populate frequencies the core does not reach."""
+    R = 1e14
+    wl = sphere(n=n, theta_e=theta_core, n_e=1.0, B=B_core, n_target=n_target, seed=seed,
+                name="corona_sphere", scattering=1, bias_mode=BIAS_CONST, bias_value=bias_value,
+                n_sc_max=4)
+    c = (np.arange(n) + 0.5) * (2.0 / n) - 1.0
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2).reshape(-1)
+    core = r < r_core
+    shell = (r >= r_core) & (r < 1.0)
+    ne = np.zeros(n ** 3)
+    ne[core] = tau_core / (SIGMA_T * R * r_core)
+    ne[shell] = tau_shell / (SIGMA_T * R * (1.0 - r_core))
+    th = np.where(shell, float(theta_shell), float(theta_core))
+    Bf = np.where(core, float(B_core), 0.0)
+    wl = Workload(wl.name, wl.grid, ne, th, Bf, wl.ucon, wl.bcon, wl.emit, wl.track,
+                  meta=dict(R_cm=R, r_core=r_core, theta_core=theta_core, theta_shell=theta_shell,
+                            tau_core=tau_core, tau_shell=tau_shell))
+    wl.emit["instance"] = int(instance)
+    return wl
+
+
 # ---------------------------------------------------------------------------
 # Kerr accretion torus (stands in for the GRMHD snapshot of the paper's GRMHD
 # test section)

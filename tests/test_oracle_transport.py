@@ -199,3 +199,29 @@ def test_histories_independent_of_threads_and_subsets(oracle_lib):
     ts = o.track_scatter(wl.track, root_begin=200, root_end=260, trace_cap=10**6)
     full = {r.tobytes() for r in t1}
     assert len(ts) > 60 and all(r.tobytes() in full for r in ts)
+
+
+def test_corona_sphere_scatters_upward(oracle_lib):
+    """The core-and-corona workload: only the magnetised core emits, the
+    ledgers close, and each scattering generation escapes at a higher median
+    frequency than the one before (inverse Compton in the hot shell), the
+    first shift staying below the mean Thomson gain of the shell,
+    1 + 4 Theta K3/K2 (Theta = 30)."""
+    wl = W.corona_sphere(n_target=3000, seed=1)
+    o = oracle_lib.Oracle()
+    o.load_zones(wl)
+    o.make_superphotons(wl.emit)
+    counts = o.read_emission()["counts"]
+    assert counts.sum() > 0 and counts[wl.B == 0].sum() == 0
+    o.close()
+    res, _ = oracle_lib.run(wl, trace_cap=10 ** 6)
+    wr, er = ledger_residuals(res)
+    assert abs(wr) < 1e-12 and abs(er) < 1e-12
+    tr = res.trace
+    esc = tr[tr["kind"] == 1]
+    med = [np.median(esc["i_nu"][esc["n_sc"] == g]) for g in range(4)]
+    assert all(b > a for a, b in zip(med, med[1:])), med
+    th = 30.0
+    gain = 1 + 4 * th * sp.kv(3, 1 / th) / sp.kv(2, 1 / th)
+    dln = math.log10(wl.track["nu_hi"] / wl.track["nu_lo"]) / wl.track["n_nu"]
+    assert (med[1] - med[0]) * dln < math.log10(gain), (med, gain)
