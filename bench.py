@@ -263,9 +263,10 @@ def workloads():
     return [W.scattering_sphere(t, n_target=N_S, seed=0, instance=i) for i, t in enumerate(TAUS)]
 
 
-def cpu_baseline(wls, roots_per_instance: int):
-    """The oracle, as it stands, on the first `roots_per_instance` roots of
-    each instance (same inputs and seed as the first GPU step)."""
+def cpu_baseline(wls, steps: int):
+    """The oracle, as it stands, on `steps` whole bench steps: every root of
+    the three instances with all their descendants, seeds 0, 1, ... (the
+    GPU's timed steps use the same seeds)."""
     import oracle
     t_total, n_total = 0.0, 0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -276,17 +277,18 @@ def cpu_baseline(wls, roots_per_instance: int):
             o.make_superphotons(wl.emit)
             o.track_scatter(wl.track, 0, 0, n_threads=threads)
             o.read_spectrum(reset=True)
-        t0 = time.perf_counter()
-        o.make_superphotons(wl.emit)
-        o.track_scatter(wl.track, 0, roots_per_instance, n_threads=threads)
-        r = o.read_spectrum(reset=True)
-        t_total += time.perf_counter() - t0
-        n_total += int(r.stats[0] + r.stats[1])
+        for s in range(steps):
+            t0 = time.perf_counter()
+            o.make_superphotons(dict(wl.emit, seed=s))
+            o.track_scatter(wl.track, n_threads=threads)
+            r = o.read_spectrum(reset=True)
+            t_total += time.perf_counter() - t0
+            n_total += int(r.stats[0] + r.stats[1])
     o.close()
     return dict(value=n_total / t_total, unit="superphotons/s", cores=threads, kind="oracle",
-                sample="first %d roots of each of the 3 instances (tau_T=%s) with all their "
-                       "scattered descendants, seed 0; make + track; %.1f s, %d superphotons; "
-                       "host cores visible: %d" % (roots_per_instance, list(TAUS), t_total,
+                sample="%d whole bench steps (seeds 0-%d): every root of the 3 instances (tau_T=%s) "
+                       "with all their scattered descendants; make + track; %.1f s, %d superphotons; "
+                       "host cores visible: %d" % (steps, steps - 1, list(TAUS), t_total,
                                                    n_total, len(os.sched_getaffinity(0))))
 
 
@@ -296,8 +298,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-roots", type=int, default=400000,
-                    help="roots per instance in the CPU oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="whole bench steps timed on the CPU oracle")
     ap.add_argument("--track-waves", type=int, default=0,
                     help="waves/SIMD variant of the tracker (2-4); 0 = autotune")
     ap.add_argument("--refill-min", type=int, default=8)
@@ -529,7 +531,7 @@ def main():
     if ttx is not None:
         out["time_to_1pct"] = ttx
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_roots)
+        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_steps)
     ctx.close()
     print(json.dumps(out), flush=True)
 
