@@ -749,13 +749,15 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
         c->chunk_retries += 1;
         chunk = std::max<unsigned long long>(1, cnt / 4);
     }
+    // counters of every instance, one synchronisation
+    std::vector<unsigned long long> st((size_t)n_inst * S_N);
+    for (int k = 0; k < n_inst; ++k)
+        HIPCHK(hipMemcpyAsync(st.data() + (size_t)k * S_N, c->inst[ids[k]].stats.p, S_N * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     for (int k = 0; k < n_inst; ++k) {
-        Instance &I = c->inst[ids[k]];
-        std::vector<unsigned long long> st(S_N);
-        HIPCHK(hipMemcpyAsync(st.data(), I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        for (int i = 0; i < S_N; ++i) acc[i] += (long long)st[i];
-        I.pending = false;
+        for (int i = 0; i < S_N; ++i) acc[i] += (long long)st[(size_t)k * S_N + i];
+        c->inst[ids[k]].pending = false;
     }
     return GM_OK;
 }
