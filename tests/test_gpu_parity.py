@@ -223,11 +223,12 @@ def test_histories_do_not_depend_on_tuning(gm):
         np.testing.assert_allclose(led, ref[2], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["f64", "f32_emissivity"])
 @pytest.mark.parametrize("kind", ["flat", "kerr"])
-def test_batched_launch_equals_separate(gm, kind):
+def test_batched_launch_equals_separate(gm, kind, precision):
     """Several instances tracked in shared launches give, instance by
     instance, bitwise the same photon histories as tracking each alone, and
-    the same tallies up to summation order."""
+    the same tallies up to summation order (both precision forms)."""
     if kind == "flat":
         wls = [W.scattering_sphere(t, n_target=3000, seed=4, instance=i) for i, t in enumerate((1e-3, 1e-2, 1e-1))]
     else:
@@ -242,7 +243,7 @@ def test_batched_launch_equals_separate(gm, kind):
             c.set_instance_bias(i, wl.track)
             c.make_superphotons(wl.emit, i)
         c.set_trace(400000)
-        st = c.track_scatter(wls[0].track)
+        st = c.track_scatter(dict(wls[0].track, precision=precision))
         specs = [c.read_spectrum(i) for i in range(len(wls))]
         tr = np.sort(c.read_trace(), order=["s2", "s1", "s0"])
         c.close()
