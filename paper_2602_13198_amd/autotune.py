@@ -12,7 +12,8 @@ from __future__ import annotations
 import itertools
 import time
 
-DEFAULT_CANDIDATES = list(itertools.product((2, 3, 4), (8, 16, 32), (1, 64)))
+DEFAULT_CANDIDATES = (list(itertools.product((2, 3, 4), (8, 16, 32), (1, 64)))
+                      + [(2, 12, 64), (2, 24, 64)])
 
 
 def autotune(ctx, step, candidates=None, repeats: int = 1, log=None):
