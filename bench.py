@@ -38,7 +38,7 @@ FP64_PEAK_TFLOPS = 78.6
 # Algorithmic FP64 operations of the tracking kernel per event (counting
 # convention: + - * / sqrt and each elementary function = 1, fused
 # multiply-add = 2; comparisons, min/max, floor and integer work not
-# counted).  The breakdown of each figure is tabulated in the design doc.  Only
+# counted); the breakdown of each figure is in the comment beside it.  Only
 # the tracking kernel's own work is counted: birth and scattering kernels
 # are timed apart.
 FLOPS_PER = {
@@ -332,8 +332,8 @@ def main():
         summarize_trace(*args.summarize_trace, " && ".join(args.commands))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (--gpus %d requested); multi-GPU sharding is "
-              "described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus %d requested): sharding over several "
+              "GPUs is not built" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -10,7 +10,7 @@
  * Everything is IEEE double precision, written for readability rather than
  * speed.  Each function cites the passage of the paper it follows
  * (section / equation label).  Where the paper is silent or garbled the
- * reading taken is stated at the point of use and listed in the design doc.
+ * reading taken is stated at the point of use.
  *
  * Parity pins: every physics function here is checked in tests/ against
  * closed forms, scipy/mpmath, brute force or invariants (see the test files
