@@ -74,9 +74,8 @@ def track_variant(waves: int, batch: int) -> str:
 def measured_traffic(variant):
     """HBM bytes per tracking launch from the committed counter summary, if
     it was taken on the current kernel source and the same variant (else None)."""
-    p = os.path.join(ROOT, "profiles", "track_kernel_scattering_sphere_traffic.json")
     try:
-        d = json.load(open(p))
+        d = json.load(open(TRAFFIC_JSON))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != variant:
