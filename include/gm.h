@@ -38,7 +38,8 @@ typedef struct gm_ctx gm_ctx;
 typedef enum {
     GM_OK = 0,
     GM_EINVAL = -1,        /* bad argument; nothing changed                   */
-    GM_ENOMEM = -2,        /* device allocation failed or a queue overflowed  */
+    GM_ENOMEM = -2,        /* device allocation failed, or one root's
+                              scattering cascade alone overflows a queue    */
     GM_EDEVICE = -3,       /* a HIP call failed                               */
     GM_ESTATE = -4,        /* call out of order (e.g. track before make)      */
     GM_EUNSUPPORTED = -5   /* option not built into this library              */
