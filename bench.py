@@ -111,10 +111,12 @@ def register_bound(ctx, waves, target_ms=40.0):
     return out
 
 
-def kerr_torus_form(ctx, instance, runs=2):
+def kerr_torus_form(ctx, instance, waves, runs=2):
     """Superphotons/s on the synthetic Kerr torus (a = 0.9375, 256 x 128 MKS
     zones, N_s = 1e7, 200 x 6 bins) in FP64 and in the FP32-emissivity form:
-    one untimed round, then `runs` timed make + track + read rounds each."""
+    the refill threshold chosen by one timed round each (Kerr photons live
+    ~300 steps, so lanes are refilled earlier than in flat space), then one
+    untimed round and `runs` timed make + track + read rounds per form."""
     import torch
     from paper_2602_13198_amd import workloads as W
     wl = W.torus(n_target=1e7)
@@ -122,6 +124,20 @@ def kerr_torus_form(ctx, instance, runs=2):
     out = {"workload": "Kerr torus a=0.9375, 256x128 modified Kerr-Schild zones, Fishbone-Moncrief "
                        "torus with 5% log-normal perturbations, R-beta electrons (R_high=40), "
                        "b = 1e3 Theta_e^2, N_s=1e7, 200x6 bins"}
+    trial = {}
+    for refill in (4, 8, 16):
+        ctx.set_tuning(waves, refill)
+        ctx.make_superphotons(dict(wl.emit, seed=6999), instance=instance)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.track_scatter(wl.track)
+        torch.cuda.synchronize()
+        trial[refill] = time.perf_counter() - t0
+        ctx.read_spectrum(instance, reset=True)
+    best = min(trial, key=trial.get)
+    ctx.set_tuning(waves, best)
+    out["tuning"] = {"track_waves": waves, "refill_min": best,
+                     "trial_track_s": {str(k): round(v, 4) for k, v in trial.items()}}
     for prec, key in ((0, "f64"), (1, "f32_emissivity")):
         def one(seed):
             ctx.make_superphotons(dict(wl.emit, seed=seed), instance=instance)
@@ -525,7 +541,7 @@ def main():
             "avg_track_launch_ms": ms32 / l32 if l32 else None,
             "speedup_vs_f64": (n32 / el32) / value,
         },
-        "kerr_torus": kerr_torus_form(ctx, len(wls)),
+        "kerr_torus": kerr_torus_form(ctx, len(wls), tuning["track_waves"]),
     }
     if ttx is not None:
         out["time_to_1pct"] = ttx
