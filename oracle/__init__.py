@@ -87,6 +87,11 @@ TRACE_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("n_sc", "<
                         ("x", "<f8", 4), ("k", "<f8", 4)])
 assert TRACE_DTYPE.itemsize == 112
 
+EVENT_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("p0", "<u4"), ("p1", "<u4"),
+                        ("p2", "<u4"), ("zone", "<i4"), ("gen", "<i4"), ("eps", "<f8"),
+                        ("w", "<f8"), ("score", "<f8"), ("x", "<f8", 3)])
+assert EVENT_DTYPE.itemsize == 80
+
 _lib = None
 
 
@@ -125,6 +130,12 @@ def lib() -> C.CDLL:
                                       C.c_void_p, u64, C.POINTER(C.c_uint64)]),
             "gmo_read_spectrum": (i, [C.c_void_p, dp, dp, C.POINTER(C.c_int64), i]),
             "gmo_last_error": (C.c_char_p, []),
+            "gmo_set_bias_table": (i, [C.c_void_p, dp, i, d, d]),
+            "gmo_set_emission_table": (i, [C.c_void_p, dp, i, d, d]),
+            "gmo_set_event_log": (i, [C.c_void_p, C.c_void_p, u64, u64]),
+            "gmo_event_count": (i, [C.c_void_p, C.POINTER(C.c_uint64)]),
+            "gmo_set_score_weights": (i, [C.c_void_p, dp, i]),
+            "gmo_table_value": (d, [C.c_void_p, i, i, d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -350,6 +361,48 @@ class Oracle:
                                        int(n_threads), tr.ctypes.data if tr is not None else None,
                                        int(trace_cap), C.byref(tn)))
         return tr[:tn.value] if tr is not None else None
+
+    def set_bias_table(self, table, lo, hi):
+        """Per-zone table [nz][n] in ln eps for the TABLE and WINDOW bias
+        modes (None removes it)."""
+        if table is None:
+            _check(lib().gmo_set_bias_table(self._c, None, 0, 0.0, 0.0))
+            return
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        self._btab = t
+        _check(lib().gmo_set_bias_table(self._c, _dp(t), int(t.shape[1]), float(lo), float(hi)))
+
+    def set_emission_table(self, table, lo, hi):
+        """Per-zone modulation [nz][n] in ln nu of the emission weights
+        (None removes it); takes effect at the next make."""
+        if table is None:
+            _check(lib().gmo_set_emission_table(self._c, None, 0, 0.0, 0.0))
+            return
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        _check(lib().gmo_set_emission_table(self._c, _dp(t), int(t.shape[1]), float(lo), float(hi)))
+
+    def table_value(self, which, zone, v):
+        return lib().gmo_table_value(self._c, int(which), int(zone), float(v))
+
+    def set_event_log(self, capacity, root_stride=1):
+        if capacity <= 0:
+            self._ev = None
+            _check(lib().gmo_set_event_log(self._c, None, 0, 0))
+            return
+        self._ev = np.zeros(int(capacity), EVENT_DTYPE)
+        _check(lib().gmo_set_event_log(self._c, self._ev.ctypes.data, int(capacity), int(root_stride)))
+
+    def read_event_log(self):
+        n = C.c_uint64(0)
+        _check(lib().gmo_event_count(self._c, C.byref(n)))
+        return self._ev[:min(int(n.value), len(self._ev))].copy()
+
+    def set_score_weights(self, sw):
+        if sw is None:
+            _check(lib().gmo_set_score_weights(self._c, None, 0))
+            return
+        a = np.ascontiguousarray(sw, dtype=np.float64).reshape(-1)
+        _check(lib().gmo_set_score_weights(self._c, _dp(a), int(a.size)))
 
     def read_spectrum(self, reset=False) -> Result:
         spec = np.zeros((self.n_theta, self.n_nu, 3))

@@ -69,6 +69,9 @@ typedef struct {
 #define GMO_BIAS_CONST  0
 #define GMO_BIAS_THETA2 1
 #define GMO_BIAS_GEN2   2
+#define GMO_BIAS_TABLE  3   /* b = exp(T_zone(ln eps)), T from gmo_set_bias_table     */
+#define GMO_BIAS_WINDOW 4   /* b = w exp(T_zone(ln eps)), w the weight at the start
+                               of the step (weight-window splitting)                */
 
 typedef struct {
     int    scattering;      /* 0: no Compton opacity at all                 */
@@ -204,6 +207,50 @@ int      gmo_track_scatter(gmo_ctx *c, const gmo_track_params *p,
 int      gmo_read_spectrum(gmo_ctx *c, double *spec, double *ledger, int64_t *stats,
                            int reset);
 const char *gmo_last_error(void);
+
+/* ---- tables and records of the learned / adaptive forms --------------
+ * Not passages of the paper, which names bias tuning only as future work
+ * (Conclusions).  A per-zone table holds n_nodes values per zone on nodes
+ * uniform in a log variable over [lo, hi]; between nodes a value is linear
+ * in that variable, outside [lo, hi] it is the end node's value.
+ *
+ * Bias table (variable ln eps, eps the fluid-frame photon energy in
+ * m_e c^2): used by GMO_BIAS_TABLE and GMO_BIAS_WINDOW.  Any b >= 1 keeps
+ * the estimator unbiased (Scattering section: child w/b, parent w(1-1/b)).
+ *
+ * Emission table (variable ln nu): m_i(nu) lowers the weight of zone i's
+ * superphotons, ln w_i(nu) = ln w(nu) - m_i(nu), which raises its expected
+ * count by the same factor inside the integral of the Sampling procedure;
+ * the expected emitted luminosity does not change (eq:weight_calc).
+ * NULL removes the table.  Both are copied. */
+int gmo_set_bias_table(gmo_ctx *c, const double *tab, int n_nodes, double lo, double hi);
+int gmo_set_emission_table(gmo_ctx *c, const double *tab, int n_nodes, double lo, double hi);
+/* A table's value for zone z at log variable v (which: 0 bias, 1 emission). */
+double gmo_table_value(const gmo_ctx *c, int which, int zone, double v);
+
+/* Event records: one per scattering (the child it creates) and one per
+ * root whose id is a multiple of root_stride (its emission).  score sums,
+ * over the created photon and all its descendants that escape into a
+ * tally bin, w E s_bin with E the energy at infinity in erg and s_bin the
+ * score weight of the bin (1 when no weights are set). */
+typedef struct {
+    uint32_t s0, s1, s2;    /* stream of the photon the event created        */
+    uint32_t p0, p1, p2;    /* stream of the photon that scattered (0: emission) */
+    int32_t  zone;          /* zone whose plasma scattered or emitted        */
+    int32_t  gen;           /* generation of the created photon               */
+    double   eps;           /* fluid-frame energy of the incoming photon (scattering)
+                               or of the emitted photon, m_e c^2              */
+    double   w;             /* weight of the created photon                   */
+    double   score;
+    double   x[3];          /* event position, code coordinates               */
+} gmo_event_rec;
+
+/* buf = NULL disables the log.  Records beyond cap are counted, not kept. */
+int gmo_set_event_log(gmo_ctx *c, gmo_event_rec *buf, uint64_t cap, uint64_t root_stride);
+int gmo_event_count(const gmo_ctx *c, uint64_t *n);
+/* Score weights [n_theta][n_nu] of the next track calls (n must match
+ * their tally), NULL = 1. */
+int gmo_set_score_weights(gmo_ctx *c, const double *sw, int n);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,12 @@ struct gmo_ctx {
     double *spec;
     double ledger[GMO_L_N];
     int64_t stats[GMO_S_N];
+    /* per-zone tables of the learned / adaptive forms */
+    double *btab; int bt_n; double bt_lo, bt_hi;      /* bias, in ln eps       */
+    double *mtab; int mt_n; double mt_lo, mt_hi;      /* emission, in ln nu    */
+    /* event log and score weights */
+    gmo_event_rec *ev_out; uint64_t ev_cap, ev_n, root_stride;
+    double *sw; int sw_n;
 };
 
 gmo_ctx *gmo_create(void)
@@ -76,7 +82,7 @@ void gmo_destroy(gmo_ctx *c)
 {
     if (!c) return;
     free_zones(c);
-    free(c->sh); free(c->spec);
+    free(c->sh); free(c->spec); free(c->btab); free(c->mtab); free(c->sw);
     free(c);
 }
 
@@ -286,6 +292,89 @@ static double ln_weight(const gmo_ctx *c, double lnnu)
     return (1.0 - f) * c->ln_w[i] + f * c->ln_w[i + 1];
 }
 
+/* Value of a per-zone table at log variable v: linear between the nodes,
+ * the end node's value outside [lo, hi]. */
+static double table_at(const double *tab, int n, double lo, double hi, int z, double v)
+{
+    const double *t = tab + (size_t)z * n;
+    double pos = (v - lo) / (hi - lo) * (n - 1);
+    if (pos <= 0.0) return t[0];
+    if (pos >= n - 1) return t[n - 1];
+    int i = (int)floor(pos);
+    double f = pos - i;
+    return t[i] + f * (t[i + 1] - t[i]);
+}
+
+/* ln w_i(nu) of zone z: the weight table lowered by the zone's emission
+ * modulation, when one is set. */
+static double ln_weight_zone(const gmo_ctx *c, int z, double lnnu)
+{
+    double lw = ln_weight(c, lnnu);
+    if (c->mtab) lw -= table_at(c->mtab, c->mt_n, c->mt_lo, c->mt_hi, z, lnnu);
+    return lw;
+}
+
+static int set_table(double **dst, int *dn, double *dlo, double *dhi, const gmo_ctx *c,
+                     const double *tab, int n, double lo, double hi)
+{
+    if (!tab) { free(*dst); *dst = NULL; *dn = 0; return GMO_OK; }
+    if (!c->n_e) { gmo_set_error("load zones first"); return GMO_ESTATE; }
+    if (n < 2 || !(hi > lo)) { gmo_set_error("bad table shape"); return GMO_EINVAL; }
+    size_t m = (size_t)c->nz * n;
+    for (size_t i = 0; i < m; ++i)
+        if (!isfinite(tab[i])) { gmo_set_error("table entry not finite"); return GMO_EINVAL; }
+    free(*dst);
+    *dst = malloc(sizeof(double) * m);
+    memcpy(*dst, tab, sizeof(double) * m);
+    *dn = n; *dlo = lo; *dhi = hi;
+    return GMO_OK;
+}
+
+int gmo_set_bias_table(gmo_ctx *c, const double *tab, int n_nodes, double lo, double hi)
+{
+    return set_table(&c->btab, &c->bt_n, &c->bt_lo, &c->bt_hi, c, tab, n_nodes, lo, hi);
+}
+
+int gmo_set_emission_table(gmo_ctx *c, const double *tab, int n_nodes, double lo, double hi)
+{
+    return set_table(&c->mtab, &c->mt_n, &c->mt_lo, &c->mt_hi, c, tab, n_nodes, lo, hi);
+}
+
+double gmo_table_value(const gmo_ctx *c, int which, int zone, double v)
+{
+    if (which == 0) return c->btab ? table_at(c->btab, c->bt_n, c->bt_lo, c->bt_hi, zone, v) : NAN;
+    return c->mtab ? table_at(c->mtab, c->mt_n, c->mt_lo, c->mt_hi, zone, v) : NAN;
+}
+
+int gmo_set_event_log(gmo_ctx *c, gmo_event_rec *buf, uint64_t cap, uint64_t root_stride)
+{
+    if (buf && (cap == 0 || root_stride == 0)) { gmo_set_error("bad event log"); return GMO_EINVAL; }
+    c->ev_out = buf;
+    c->ev_cap = buf ? cap : 0;
+    c->ev_n = 0;
+    c->root_stride = root_stride;
+    return GMO_OK;
+}
+
+int gmo_event_count(const gmo_ctx *c, uint64_t *n)
+{
+    *n = c->ev_n;
+    return GMO_OK;
+}
+
+int gmo_set_score_weights(gmo_ctx *c, const double *sw, int n)
+{
+    free(c->sw);
+    c->sw = NULL;
+    c->sw_n = 0;
+    if (!sw) return GMO_OK;
+    if (n < 1) { gmo_set_error("bad score weights"); return GMO_EINVAL; }
+    c->sw = malloc(sizeof(double) * n);
+    memcpy(c->sw, sw, sizeof(double) * n);
+    c->sw_n = n;
+    return GMO_OK;
+}
+
 int gmo_make_superphotons(gmo_ctx *c, const gmo_emit_params *p, uint64_t *n_made)
 {
     if (!c || !c->n_e) { gmo_set_error("load zones first"); return GMO_ESTATE; }
@@ -343,13 +432,18 @@ int gmo_make_superphotons(gmo_ctx *c, const gmo_emit_params *p, uint64_t *n_made
         c->w_node[k] += p->w_floor_rel * wmax;
         c->ln_w[k] = log(c->w_node[k]);
     }
-    /* per zone: dN/dln nu = V J / (h w); Simpson over the nodes; bound F_max */
+    /* per zone: dN/dln nu = V J / (h w_i); Simpson over the nodes; bound
+     * F_max.  w_i = w e^{-m_i} under an emission table. */
     const double d = c->lnnu_span / (nw - 1);
     uint64_t total = 0;
     for (int i = 0; i < nz; ++i) {
         double s = 0.0, fm = 0.0;
         for (int k = 0; k < nw; ++k) {
-            double F = Jz[(size_t)i * nw + k] / c->w_node[k];
+            double wik = c->w_node[k];
+            if (c->mtab)
+                wik *= exp(-table_at(c->mtab, c->mt_n, c->mt_lo, c->mt_hi, i,
+                                     c->lnnu_min + c->lnnu_span * k / (nw - 1)));
+            double F = Jz[(size_t)i * nw + k] / wik;
             double wk = (k == 0 || k == nw - 1) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
             s += wk * F;
             if (F > fm) fm = F;
@@ -389,10 +483,15 @@ int gmo_read_emission(const gmo_ctx *c, uint32_t *counts, double *nbar, double *
 typedef struct {
     double x[4], k[4], a[4];
     double w, w_birth, x1;         /* x1: remaining biased optical depth    */
-    double nua, nus, b;            /* at the current point                  */
+    double nua, nus, b;            /* at the current point (window mode: the
+                                      importance factor instead of b)         */
     int n_sc;
     uint32_t steps;
     gmo_rng rng;
+    /* worker-local indices of the event records of the photon's ancestry
+     * (its creating event first): its escape adds to every one of them */
+    int n_anc;
+    int64_t anc[GMO_MAX_GEN + 1];
 } photon;
 
 typedef struct {
@@ -403,7 +502,26 @@ typedef struct {
     uint64_t trace_n, trace_cap;
     photon *stack;
     size_t stack_n, stack_cap;
+    gmo_event_rec *ev;
+    size_t ev_n, ev_cap;
 } worker;
+
+/* Append an event record to the worker's list; returns its index. */
+static int64_t add_event(worker *wk, const uint32_t s[3], const uint32_t par[3], int zone, int gen,
+                         double eps, double w, const double x[4])
+{
+    if (wk->ev_n == wk->ev_cap) {
+        wk->ev_cap = wk->ev_cap ? 2 * wk->ev_cap : 256;
+        wk->ev = realloc(wk->ev, sizeof(gmo_event_rec) * wk->ev_cap);
+    }
+    gmo_event_rec *r = &wk->ev[wk->ev_n];
+    memset(r, 0, sizeof(*r));
+    r->s0 = s[0]; r->s1 = s[1]; r->s2 = s[2];
+    if (par) { r->p0 = par[0]; r->p1 = par[1]; r->p2 = par[2]; }
+    r->zone = zone; r->gen = gen; r->eps = eps; r->w = w;
+    for (int m = 0; m < 3; ++m) r->x[m] = x[m + 1];
+    return (int64_t)wk->ev_n++;
+}
 
 typedef struct {
     double nua, nus, b;
@@ -446,10 +564,28 @@ static void coefficients(const gmo_ctx *c, const gmo_track_params *tp, const dou
     case GMO_BIAS_GEN2:
         b = (double)(n_sc + 1) * (n_sc + 1) / (c->n_e[z] * GMO_SIGT * tp->bias_value * c->grid.L_unit_cm);
         break;
+    case GMO_BIAS_TABLE:
+    case GMO_BIAS_WINDOW:
+        b = exp(table_at(c->btab, c->bt_n, c->bt_lo, c->bt_hi, z, log(ef)));
+        break;
     }
+    /* the window mode's factor is multiplied by the weight at each step */
+    if (tp->bias_mode == GMO_BIAS_WINDOW) { out->b = b; return; }
     if (b < 1.0) b = 1.0;
     if (b > tp->bias_max) b = tp->bias_max;
     out->b = b;
+}
+
+/* Bias of a step from the value carried by the photon or evaluated at the
+ * step's end: the value itself, or in the window mode w times the
+ * importance factor, clamped to [1, bias_max]. */
+static double step_bias(const gmo_track_params *tp, double w, double bf)
+{
+    if (tp->bias_mode != GMO_BIAS_WINDOW) return bf;
+    double b = w * bf;
+    if (b < 1.0) b = 1.0;
+    if (b > tp->bias_max) b = tp->bias_max;
+    return b;
 }
 
 static void accel_at(const gmo_grid *grid, const double x[4], const double k[4], double a[4])
@@ -514,11 +650,13 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
     double g[4][4];
     gmo_gcov(&c->grid, xs, g);
     double kchild[4];
+    double eps_in = 0.0;
     if (z >= 0 && c->n_e[z] > 0.0) {
         double u[4], bh[4], e[4][4], eps;
         int has_b;
         fluid_frame(c, z, g, u, bh, &has_b);
         scatter_tetrad(g, u, bh, has_b, ks, e, &eps);
+        eps_in = eps;
         double kf[4];
         gmo_scatter_in_frame(&ch.rng, c->theta[z], eps, NULL, NULL, kf,
                              &wk->stats[GMO_S_E_TRIALS], &wk->stats[GMO_S_ANG_TRIALS]);
@@ -529,6 +667,13 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
     for (int m = 0; m < 4; ++m) { ch.x[m] = xs[m]; ch.k[m] = kchild[m]; }
     ch.w = ch.w_birth = w_child;
     ch.n_sc = par->n_sc + 1;
+    /* event record: the child inherits the parent's ancestry plus this
+     * event; a child without a record starts an empty ancestry */
+    ch.n_anc = 0;
+    if (c->ev_out && z >= 0 && c->n_e[z] > 0.0) {
+        for (int j = 0; j < par->n_anc; ++j) ch.anc[ch.n_anc++] = par->anc[j];
+        ch.anc[ch.n_anc++] = add_event(wk, ch.rng.s, par->rng.s, z, ch.n_sc, eps_in, w_child, xs);
+    }
     wk->ledger[GMO_L_E_COMPTON] += w_child * (e_inf(g, kchild) - e_inf(g, ks)) * MEC2;
     wk->stats[GMO_S_SCATTER] += 1;
     (void)tp;
@@ -687,7 +832,8 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
 
         double tau_a = 0.5 * (ph->nua + c1.nua) * Cc * dl;
         double tau_s = tp->scattering ? 0.5 * (ph->nus + c1.nus) * Cc * dl : 0.0;
-        double b = c1.vacuum ? ph->b : c1.b;
+        double bf = c1.vacuum ? ph->b : c1.b;
+        double b = step_bias(tp, ph->w, bf);
         gmo_gcov(G, ph->x, g);
         double e_old = e_inf(g, ph->k);
 
@@ -734,7 +880,7 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
             wk->ledger[GMO_L_W_ABS] += wb - ph->w;
             wk->ledger[GMO_L_E_ABS] += (wb - ph->w) * e_old * MEC2;
             for (int m = 0; m < 4; ++m) { ph->x[m] = xn[m]; ph->k[m] = kn[m]; ph->a[m] = an[m]; }
-            ph->nua = c1.nua; ph->nus = c1.nus; ph->b = b;
+            ph->nua = c1.nua; ph->nus = c1.nus; ph->b = bf;
             gmo_gcov(G, ph->x, g);
             double e_new = e_inf(g, ph->k);
             wk->ledger[GMO_L_E_DRIFT] += ph->w * (e_new - e_old) * MEC2;
@@ -775,6 +921,9 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
                 int inu = (int)fi;
                 double *bin = &wk->spec[((size_t)ith * tp->n_nu + inu) * 3];
                 bin[0] += E; bin[1] += E * E; bin[2] += 1.0;
+                /* the escape scores for every event of the photon's ancestry */
+                double sc = E * (c->sw ? c->sw[(size_t)ith * tp->n_nu + inu] : 1.0);
+                for (int j = 0; j < ph->n_anc; ++j) wk->ev[ph->anc[j]].score += sc;
                 wk->ledger[GMO_L_W_ESC] += ph->w; wk->ledger[GMO_L_E_ESC] += E;
                 wk->stats[GMO_S_ESCAPED] += 1;
                 record_end(c, wk, ph, GMO_END_ESCAPE, inu, ith);
@@ -828,7 +977,7 @@ static void birth(const gmo_ctx *c, worker *wk, uint64_t p, int z, photon *ph)
         lnnu = c->lnnu_min + gmo_rng_next(&ph->rng) * c->lnnu_span;
         nu = exp(lnnu);
         double u2 = gmo_rng_next(&ph->rng);
-        double F = zone_J(c, z, nu) / exp(ln_weight(c, lnnu));
+        double F = zone_J(c, z, nu) / exp(ln_weight_zone(c, z, lnnu));
         wk->stats[GMO_S_NU_TRIALS] += 1;
         if (F > c->fmax[z]) wk->stats[GMO_S_OVERSHOOT] += 1;
         if (u2 < F / c->fmax[z] || it >= GMO_MAX_TRIALS) break;
@@ -852,9 +1001,12 @@ static void birth(const gmo_ctx *c, worker *wk, uint64_t p, int z, photon *ph)
     double sth = sqrt(1.0 - cth * cth);
     double kf[4] = {eps, eps * sth * cos(phi), eps * sth * sin(phi), eps * cth};
     from_frame(e, kf, ph->k);
-    ph->w = ph->w_birth = exp(ln_weight(c, lnnu));
+    ph->w = ph->w_birth = exp(ln_weight_zone(c, z, lnnu));
     ph->x1 = -log(1.0 - gmo_rng_next(&ph->rng));
     ph->n_sc = 0;
+    ph->n_anc = 0;
+    if (c->ev_out && p % c->root_stride == 0)
+        ph->anc[ph->n_anc++] = add_event(wk, ph->rng.s, NULL, z, 0, eps, ph->w, ph->x);
     wk->ledger[GMO_L_W_EMIT] += ph->w;
     wk->ledger[GMO_L_E_EMIT] += ph->w * e_inf(g, ph->k) * MEC2;
     wk->stats[GMO_S_ROOTS] += 1;
@@ -880,6 +1032,12 @@ int gmo_track_scatter(gmo_ctx *c, const gmo_track_params *tp, uint64_t root_begi
         tp->n_sc_max < 0 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0)) {
         gmo_set_error("bad track parameters"); return GMO_EINVAL;
     }
+    if ((tp->bias_mode == GMO_BIAS_TABLE || tp->bias_mode == GMO_BIAS_WINDOW) && !c->btab) {
+        gmo_set_error("bias table not set"); return GMO_ESTATE;
+    }
+    if (c->sw && c->sw_n != tp->n_nu * tp->n_theta) {
+        gmo_set_error("score weights do not match the tally"); return GMO_EINVAL;
+    }
     if (root_end > c->offset[c->nz]) root_end = c->offset[c->nz];
     if (c->spec && (c->n_nu != tp->n_nu || c->n_theta != tp->n_theta)) {
         gmo_set_error("tally shape changed without reset"); return GMO_EINVAL;
@@ -889,8 +1047,19 @@ int gmo_track_scatter(gmo_ctx *c, const gmo_track_params *tp, uint64_t root_begi
         c->spec = calloc((size_t)tp->n_nu * tp->n_theta * 3, sizeof(double));
     }
     if (tp->scattering && !c->sh) {
+        /* the table depends on nothing but its fixed nodes: built once per
+         * process and copied into each context */
+        static double *sh_cache = NULL;
         c->sh = malloc(sizeof(double) * GMO_SH_NT * GMO_SH_NE);
-        gmo_sigma_hot_table(c->sh);
+        #pragma omp critical(gmo_sh_cache)
+        {
+            if (!sh_cache) {
+                double *t = malloc(sizeof(double) * GMO_SH_NT * GMO_SH_NE);
+                gmo_sigma_hot_table(t);
+                sh_cache = t;
+            }
+        }
+        memcpy(c->sh, sh_cache, sizeof(double) * GMO_SH_NT * GMO_SH_NE);
     }
 #ifdef _OPENMP
     int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
@@ -932,7 +1101,9 @@ int gmo_track_scatter(gmo_ctx *c, const gmo_track_params *tp, uint64_t root_begi
         for (int i = 0; i < GMO_S_N; ++i) c->stats[i] += W[t].stats[i];
         if (trace)
             for (uint64_t r = 0; r < W[t].trace_n && tn < trace_cap; ++r) trace[tn++] = W[t].trace[r];
-        free(W[t].spec); free(W[t].trace); free(W[t].stack);
+        for (size_t r = 0; r < W[t].ev_n; ++r, ++c->ev_n)
+            if (c->ev_n < c->ev_cap) c->ev_out[c->ev_n] = W[t].ev[r];
+        free(W[t].spec); free(W[t].trace); free(W[t].stack); free(W[t].ev);
     }
     free(W);
     if (trace_n) *trace_n = tn;

@@ -36,7 +36,8 @@ M_E = 9.1093837015e-28
 METRIC_MINKOWSKI_CART = 0
 METRIC_KS_MKS = 1
 
-BIAS_CONST, BIAS_THETA2, BIAS_GEN2, BIAS_LEARNED = 0, 1, 2, 3
+BIAS_CONST, BIAS_THETA2, BIAS_GEN2, BIAS_TABLE, BIAS_WINDOW = 0, 1, 2, 3, 4
+BIAS_LEARNED = BIAS_TABLE
 
 
 @dataclass
