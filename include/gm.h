@@ -39,7 +39,8 @@ typedef enum {
     GM_OK = 0,
     GM_EINVAL = -1,        /* bad argument; nothing changed                   */
     GM_ENOMEM = -2,        /* device allocation failed, or one root's
-                              scattering cascade alone overflows a queue    */
+                              scattering cascade alone overflows a queue
+                              (gm_track_scatter: see there)                */
     GM_EDEVICE = -3,       /* a HIP call failed                               */
     GM_ESTATE = -4,        /* call out of order (e.g. track before make)      */
     GM_EUNSUPPORTED = -5   /* option not built into this library              */
@@ -66,9 +67,12 @@ typedef struct {
 
 /* Zone plasma in double precision, zone index z = (i1*n2 + i2)*n3 + i3.
  * ucon and bcon are [4][nzones] (component-major).  on_device = 1 means the
- * pointers are device pointers, else host pointers.  Zones with n_e > 0 need
- * theta_e > 0.  bcon gives only the field direction; its normalisation is
- * ignored. */
+ * pointers are device pointers, else host pointers.  Every zone needs finite
+ * n_e >= 0, B >= 0 and theta_e; zones with n_e > 0 need theta_e > 0 and
+ * u^t > 0, and in Kerr a timelike u at the zone centre.  These checks run on
+ * the host for host inputs and in a kernel for device inputs; a failure is
+ * GM_EINVAL with the first bad zone named.  bcon gives only the field
+ * direction; its normalisation is ignored. */
 typedef struct {
     int           on_device;
     const double *n_e;      /* electron density, cm^-3                            */
@@ -90,9 +94,16 @@ typedef struct {
 #define GM_BIAS_CONST  0    /* b = bias_value                                    */
 #define GM_BIAS_THETA2 1    /* b = bias_value * Theta_e^2                        */
 #define GM_BIAS_GEN2   2    /* b = (n_sc+1)^2 / (n_e sigma_T bias_value ell)     */
-#define GM_BIAS_LEARNED 3   /* b = exp of the instance's learned table ln b[zone]
-                               interpolated in ln eps (gm_set_bias_table);
-                               bias_value is ignored.  Any b >= 1 keeps the
+#define GM_BIAS_TABLE  3    /* b = exp T[zone](ln eps), the instance's table
+                               (gm_set_bias_table) interpolated in ln eps of
+                               the fluid-frame photon energy; bias_value is
+                               ignored                                          */
+#define GM_BIAS_LEARNED GM_BIAS_TABLE
+#define GM_BIAS_WINDOW 4    /* weight window: b = w exp T[zone](ln eps), w the
+                               photon's weight at the start of the step, so
+                               that heavy photons split more and the children's
+                               weights approach 1/importance.  Every mode is
+                               clamped to [1, bias_max]; any b >= 1 keeps the
                                estimator unbiased (child w/b, parent w(1-1/b)). */
 
 #define GM_PRECISION_F64 0  /* all transport arithmetic in double                 */
@@ -189,15 +200,26 @@ gm_status gm_make_superphotons(gm_ctx *ctx, int instance, const gm_emit_params *
 /* Track every root made and not yet tracked, and all its descendants, to
  * escape, capture or loss (geodesic, Absorption and Scattering sections),
  * adding to the tallies.  stats (may be NULL) receives GM_S_N counters of
- * this call and synchronises the stream.  GM_ENOMEM if a child queue would
- * overflow (the tallies of that call are then incomplete). */
+ * this call and synchronises the stream.  Instances of one metric share
+ * launches (gm_set_batch); their tallies are kept per block in LDS when
+ * they fit the 56 KiB budget, else added to in HBM (gm_set_tally_mode).
+ * GM_ENOMEM if the scattering cascade of a single root overflows the photon
+ * queue: the instances of the launch group that failed are left as before
+ * the call (tallies, ledgers, trace and event-log counts restored, roots
+ * still pending); groups tracked before it keep their results. */
 gm_status gm_track_scatter(gm_ctx *ctx, const gm_track_params *params, int64_t *stats);
 
-/* Copy the tally of one instance into `out` = [n_theta][n_nu][3] doubles
+/* The recorded spectrum (Recording of superphotons, the last of the paper's
+ * five kernels: each escaping superphoton adds its energy to its frequency
+ * bin; inclination bins as in the Tests section's spectra).  Copies the
+ * tally of one instance into `out` = [n_theta][n_nu][3] doubles
  * {sum of w E, sum of (w E)^2, number of superphotons}, E the energy at
- * infinity in erg (so sums are erg/s), out_on_device selecting a device or
- * host buffer; ledger_out (host, may be NULL) receives GM_L_N doubles.
- * reset = 1 clears the tally and ledger afterwards.  Synchronises. */
+ * infinity in erg (so sums are erg/s; nu L_nu of a bin is
+ * (4 pi / dOmega) sum(w E) / dln(nu)), out_on_device selecting a device or
+ * host buffer (caller-owned, n_theta*n_nu*3 doubles); ledger_out (host, may
+ * be NULL) receives GM_L_N doubles.  reset = 1 clears the tally and ledger
+ * afterwards.  GM_ESTATE if the instance has never been tracked.
+ * Synchronises. */
 gm_status gm_read_spectrum(gm_ctx *ctx, int instance, double *out, int out_on_device,
                            double *ledger_out, int reset);
 
@@ -232,8 +254,8 @@ gm_status gm_set_tuning(gm_ctx *ctx, int track_waves, int refill_min);
 /* Instances per launch (1..GM_MAX_INSTANCES, default all): gm_track_scatter
  * tracks the pending instances of one metric together -- one birth launch
  * and per generation one tracking and one scattering launch over all their
- * photons -- in groups of at most this many whose per-block tallies fit
- * the 56 KiB LDS tally budget.  Results do not depend on it. */
+ * photons -- in groups of at most this many (GPU implementation section:
+ * batches).  Results do not depend on it. */
 gm_status gm_set_batch(gm_ctx *ctx, int max_instances);
 
 /* Photon queues (scheduling; results do not depend on it beyond the order
@@ -298,10 +320,17 @@ gm_status gm_mlp_get_params(gm_ctx *ctx, float *host_params);
 /* Outputs for n rows: X [n][8] and Y [n][2] are device buffers; stream-
  * ordered, no synchronisation. */
 gm_status gm_mlp_forward(gm_ctx *ctx, const float *X, int64_t n, float *Y);
-/* Gradient of L = sum_rows sum_o C[r][o] (y[r][o] - T[r][o])^2 with respect
- * to the parameters, into host vectors grad [GM_MLP_PARAMS] and loss [1]
- * (either may be NULL).  X [n][8], T [n][2], C [n][2] are device buffers;
- * the caller normalises C.  Synchronises. */
+/* Loss of gm_mlp_grad and gm_mlp_train_step: GM_MLP_SQUARED (default)
+ * L = sum_rows sum_o C[r][o] (y[r][o] - T[r][o])^2, or GM_MLP_POISSON, the
+ * log-link Poisson deviance L = sum C[r][o] (e^{y[r][o]} - T[r][o] y[r][o]),
+ * whose minimiser is y = ln E[T] (targets >= 0, mostly zero allowed). */
+#define GM_MLP_SQUARED 0
+#define GM_MLP_POISSON 1
+gm_status gm_mlp_set_loss(gm_ctx *ctx, int kind);
+/* Gradient of the loss with respect to the parameters, into host vectors
+ * grad [GM_MLP_PARAMS] and loss [1] (either may be NULL).  X [n][8],
+ * T [n][2], C [n][2] are device buffers; the caller normalises C.  The
+ * result does not depend on scheduling (bitwise).  Synchronises. */
 gm_status gm_mlp_grad(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
                       float *grad, float *loss);
 /* One Adam step (beta 0.9, 0.999, eps 1e-8) on the same loss with learning
@@ -310,26 +339,68 @@ gm_status gm_mlp_grad(gm_ctx *ctx, const float *X, const float *T, const float *
 gm_status gm_mlp_train_step(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
                             float lr, float *loss);
 
-/* Learned bias table of an instance: ln b for every zone on n_eps nodes
- * uniform in ln eps over [ln_eps_lo, ln_eps_hi] (eps the fluid-frame photon
- * energy in m_e c^2), host array [nzones][n_eps], copied.  Used by
- * GM_BIAS_LEARNED. */
-gm_status gm_set_bias_table(gm_ctx *ctx, int instance, const double *ln_b, int n_eps,
+/* ---- tables and records of the learned and adaptive forms -------------
+ * Not passages of the paper, which names tuning the bias "on the fly" as
+ * future work (Conclusions); they only change where superphotons are
+ * spent, never the expected spectrum.
+ *
+ * A per-zone table holds n values per zone on nodes uniform in a log
+ * variable over [lo, hi]; between nodes a value is linear in that
+ * variable, outside [lo, hi] it is the end node's value.  Tables are host
+ * arrays [nzones][n], copied (synchronises); GM_ESTATE before gm_load_zones.
+ *
+ * Bias table T (variable ln eps, eps the fluid-frame photon energy in
+ * m_e c^2), used by GM_BIAS_TABLE and GM_BIAS_WINDOW. */
+gm_status gm_set_bias_table(gm_ctx *ctx, int instance, const double *table, int n_eps,
                             double ln_eps_lo, double ln_eps_hi);
 
-/* Scattering-event log (training records of the learned form): one
- * gm_event_rec per scattering event into a device buffer of `capacity`
- * records (NULL disables); gm_event_count returns the count (synchronises). */
+/* Emission table m (variable ln nu, Hz): zone i's superphotons get the
+ * weight w_i(nu) = w(nu) e^{-m_i(ln nu)} (eq:weight_calc), so its expected
+ * count at nu rises by e^{m_i} (Sampling procedure) while the expected
+ * emitted luminosity is unchanged.  table = NULL removes it.  Takes effect
+ * at the next gm_make_superphotons, which then recomputes the expected
+ * counts and rejection bounds. */
+gm_status gm_set_emission_table(gm_ctx *ctx, int instance, const double *table, int n_nu_nodes,
+                                double ln_nu_lo, double ln_nu_hi);
+
+/* Event log: one record per scattering (the child it creates, when the
+ * scattering point holds plasma) and one per root whose photon id is a
+ * multiple of root_stride (its emission; root_stride = 0: none), written by
+ * gm_track_scatter into a caller-owned device buffer of `capacity` records
+ * (NULL disables; capacity <= 2^32 - 2).  Records past the capacity are
+ * counted, not kept, and start no ancestry.  At the end of gm_track_scatter
+ * every record's score holds the sum of w E s_bin over the photon it
+ * created and all its descendants that escape into a tally bin (E the
+ * energy at infinity in erg, s_bin the instance's score weight of the bin,
+ * 1 by default); summation order varies (FP64 atomics).  gm_event_count
+ * returns the count (synchronises). */
 typedef struct {
-    uint32_t s0, s1, s2;    /* the child's stream id (its trace record's key)     */
-    int32_t  zone;          /* zone whose plasma scattered                        */
-    double   eps;           /* incoming photon's fluid-frame energy, m_e c^2      */
-    double   w_child;       /* the child's weight                                 */
-    double   x[3];          /* event position (code coordinates)                  */
-    double   pad;
+    uint32_t s0, s1, s2;    /* stream of the photon the event created (its trace key) */
+    uint32_t p0, p1, p2;    /* stream of the photon that scattered (0: emission)   */
+    int32_t  zone;          /* zone whose plasma scattered or emitted              */
+    int32_t  gen;           /* generation of the created photon                    */
+    uint32_t parent;        /* record of the photon that scattered (0xffffffff: none) */
+    uint32_t pad;
+    double   eps;           /* fluid-frame energy of the incoming or emitted photon,
+                               m_e c^2                                              */
+    double   w;             /* weight of the created photon                        */
+    double   score;
+    double   x[3];          /* event position (code coordinates)                   */
 } gm_event_rec;
-gm_status gm_set_event_log(gm_ctx *ctx, void *device_buffer, uint64_t capacity);
+gm_status gm_set_event_log(gm_ctx *ctx, void *device_buffer, uint64_t capacity, uint64_t root_stride);
 gm_status gm_event_count(gm_ctx *ctx, uint64_t *n);
+
+/* Score weights of an instance's event records: host array [n_theta][n_nu]
+ * (n must match the tally of the next gm_track_scatter), copied; NULL
+ * restores the weight 1. */
+gm_status gm_set_score_weights(gm_ctx *ctx, int instance, const double *sw, int n);
+
+/* Where the tallies of a shared launch accumulate (scheduling; results
+ * change only through the order of FP64 sums): 0 automatic (per-block LDS
+ * tallies when those of the launch group fit 56 KiB, else direct FP64
+ * atomics on the instances' tallies in HBM), 1 LDS (GM_EUNSUPPORTED at
+ * track time if one instance's tally does not fit), 2 HBM. */
+gm_status gm_set_tally_mode(gm_ctx *ctx, int mode);
 
 #ifdef __cplusplus
 }

@@ -400,7 +400,7 @@ int gmo_make_superphotons(gmo_ctx *c, const gmo_emit_params *p, uint64_t *n_made
     {
         double *Gk = malloc(sizeof(double) * nw);
         double last_nuc = -1.0;
-        #pragma omp for schedule(static)
+        #pragma omp for schedule(dynamic, 64)
         for (int i = 0; i < nz; ++i) {
             if (!c->emits[i]) {
                 for (int k = 0; k < nw; ++k) Jz[(size_t)i * nw + k] = 0.0;

@@ -3,11 +3,16 @@ only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline may use
 it; it shares nothing with the HIP path).
 
 Network 6 -> 64 -> 64 -> 2: h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2),
-y = h2 W3 + b3.  Loss L = sum_r sum_o C[r,o] (y[r,o] - T[r,o])^2.
+y = h2 W3 + b3.  Losses: squared error L = sum_r sum_o C[r,o] (y - T)^2, or
+the log-link Poisson deviance L = sum C[r,o] (e^y - T y), whose minimiser
+over y is ln E[T] (unbiased for targets with many zeros).
 Parameter vector order: W1[6][64], b1[64], W2[64][64], b2[64], W3[64][2],
 b3[2].  The gradient is written out by the chain rule; it is pinned against
-central finite differences in tests/test_oracle_mlp.py.  This network is not
-from the paper, which names bias tuning as future work (Conclusions)."""
+central finite differences in tests/test_oracle_mlp.py.  The same code with
+every matrix-product operand rounded to bfloat16 (nearest even) is the
+reference of matrix-core kernels that take BF16 operands and accumulate in
+FP32.  This network is not from the paper, which names bias tuning as
+future work (Conclusions)."""
 import numpy as np
 
 N_IN, N_H, N_OUT = 6, 64, 2
@@ -42,30 +47,53 @@ def init(seed=0):
     return pack(d)
 
 
-def forward(p, X):
+SQUARED, POISSON = 0, 1
+
+
+def _same(a):
+    return a
+
+
+def forward(p, X, rnd=_same):
+    """Outputs and activations; rnd is applied to every operand of a
+    matrix product (identity: exact FP64)."""
     W = unpack(p)
     x = np.asarray(X, dtype=np.float64)[:, :N_IN]
-    h1 = np.tanh(x @ W["W1"] + W["b1"])
-    h2 = np.tanh(h1 @ W["W2"] + W["b2"])
-    y = h2 @ W["W3"] + W["b3"]
+    h1 = np.tanh(rnd(x) @ rnd(W["W1"]) + W["b1"])
+    h2 = np.tanh(rnd(h1) @ rnd(W["W2"]) + W["b2"])
+    y = rnd(h2) @ rnd(W["W3"]) + W["b3"]
     return y, (x, h1, h2)
 
 
-def loss(p, X, T, C):
+def _loss_terms(y, T, C, kind):
+    if kind == POISSON:
+        return C * (np.exp(y) - T * y), C * (np.exp(y) - T)
+    return C * (y - T) ** 2, 2.0 * C * (y - T)
+
+
+def loss(p, X, T, C, kind=SQUARED):
     y, _ = forward(p, X)
-    return float(np.sum(C * (y - T) ** 2))
+    return float(np.sum(_loss_terms(y, T, C, kind)[0]))
 
 
-def grad(p, X, T, C):
+def grad(p, X, T, C, kind=SQUARED, rnd=_same):
+    """Gradient and loss; with rnd = bf16 every product operand (inputs,
+    weights, activations, back-propagated errors) is rounded as the
+    matrix cores see it."""
     W = unpack(p)
-    y, (x, h1, h2) = forward(p, X)
-    dy = 2.0 * C * (y - T)                      # dL/dy
-    g = {"W3": h2.T @ dy, "b3": dy.sum(0)}
-    dz2 = (dy @ W["W3"].T) * (1.0 - h2 ** 2)    # through tanh
-    g["W2"], g["b2"] = h1.T @ dz2, dz2.sum(0)
-    dz1 = (dz2 @ W["W2"].T) * (1.0 - h1 ** 2)
-    g["W1"], g["b1"] = x.T @ dz1, dz1.sum(0)
-    return pack(g), float(np.sum(C * (y - T) ** 2))
+    y, (x, h1, h2) = forward(p, X, rnd)
+    lt, dy = _loss_terms(y, T, C, kind)                 # dL/dy
+    g = {"W3": rnd(h2).T @ rnd(dy), "b3": dy.sum(0)}
+    dz2 = (rnd(dy) @ rnd(W["W3"]).T) * (1.0 - h2 ** 2)  # through tanh
+    g["W2"], g["b2"] = rnd(h1).T @ rnd(dz2), dz2.sum(0)
+    dz1 = (rnd(dz2) @ rnd(W["W2"]).T) * (1.0 - h1 ** 2)
+    g["W1"], g["b1"] = rnd(x).T @ rnd(dz1), dz1.sum(0)
+    return pack(g), float(np.sum(lt))
+
+
+def grad_bf16(p, X, T, C, kind=SQUARED):
+    """The gradient with BF16 product operands (see grad)."""
+    return grad(p, X, T, C, kind, rnd=bf16)
 
 
 def adam_step(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -91,10 +91,19 @@ struct Instance {
     // per-instance bias overriding the track call's (bias_mode < 0: none)
     int bias_mode = -1;
     double bias_value = 0.0, bias_max = 0.0;
-    // learned bias table ln b [nz][lnb_n]
+    // bias table [nz][lnb_n] (ln b, or ln of the weight-window factor)
     DevBuf<double> lnb;
     int lnb_n = 0;
     double lnb_lo = 0.0, lnb_hi = 0.0;
+    // emission table [nz][mt_n] (NULL: none); a new table invalidates the
+    // stored expected counts
+    DevBuf<double> mtab;
+    int mt_n = 0;
+    double mt_lo = 0.0, mt_hi = 0.0;
+    bool mt_on = false;
+    // score weights [n_theta][n_nu] of the event records (none: 1)
+    DevBuf<double> sw;
+    int sw_n = 0;
 };
 
 }  // namespace
@@ -116,11 +125,11 @@ struct gm_ctx {
     unsigned long long queue_cap = 0;           // entries in use (<= child_cap)
     unsigned long long queue_cap_set = 0;       // fixed by gm_set_queue_capacity, 0 = automatic
     // accumulators of the instances of a root chunk, kept to redo the chunk
-    DevBuf<double> bak_d;
-    DevBuf<unsigned long long> bak_u;
+    DevBuf<double> bak_d, call_bak_d;
+    DevBuf<unsigned long long> bak_u, call_bak_u;
     unsigned long long chunk_retries = 0;
     DevBuf<double> qd[2][13];
-    DevBuf<uint32_t> qu[2][4];
+    DevBuf<uint32_t> qu[2][5];
     DevBuf<int32_t> qi[2][3];
     DevBuf<unsigned long long> ctr;             // [gen][2]: count, cursor
     DevBuf<int> flags;                          // [0] overflow, [1] status
@@ -142,13 +151,16 @@ struct gm_ctx {
     unsigned long long trace_cap = 0;
     DevBuf<unsigned long long> trace_n;
     EventRec *evlog = nullptr;
-    unsigned long long evlog_cap = 0;
+    unsigned long long evlog_cap = 0, root_stride = 0;
     DevBuf<unsigned long long> evlog_n;
+    // tallies of a shared launch: 0 automatic (LDS when they fit), 1 LDS, 2 HBM
+    int tally_mode = 0;
     // learned form: network parameters (FP32 master, BF16 copies), Adam state
     DevBuf<float> mlp_p, mlp_m, mlp_v, mlp_g, mlp_gpart;
     DevBuf<short> mlp_pb;
     bool mlp_ready = false;
     long long mlp_t = 0;
+    int mlp_loss = 0;
 };
 
 static gm_status set_device(gm_ctx *c)
@@ -247,9 +259,10 @@ gm_status gm_destroy(gm_ctx *c)
         I.w_node.release(); I.ln_w.release(); I.nbar.release(); I.fmax.release();
         I.partial.release(); I.count.release(); I.zone_of_root.release(); I.offset.release();
         I.tile.release(); I.roots.release(); I.spec.release(); I.ledger.release(); I.stats.release();
-        I.lnb.release();
+        I.lnb.release(); I.mtab.release(); I.sw.release();
     }
     c->inst_args.release(); c->root_off.release(); c->inst_ctr.release();
+    c->bak_d.release(); c->bak_u.release(); c->call_bak_d.release(); c->call_bak_u.release();
     c->mlp_p.release(); c->mlp_m.release(); c->mlp_v.release(); c->mlp_g.release();
     c->mlp_gpart.release(); c->mlp_pb.release(); c->evlog_n.release();
     c->gcheb.release(); c->sh_table.release(); c->sh_table32.release(); c->gl_x.release(); c->gl_w.release();
@@ -317,6 +330,23 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
             }
         }
     }
+    if (z->on_device) {
+        // validate on the device before anything changes
+        CheckArgs V;
+        V.n_e = z->n_e; V.theta = z->theta_e; V.B = z->B; V.ucon = z->ucon; V.nz = nz;
+        for (int j = 0; j < 3; ++j) { V.n[j] = g->n[j]; V.xs[j] = g->x_start[j]; V.dx[j] = g->dx[j]; }
+        V.kerr = kerr ? 1 : 0;
+        V.a_spin = g->a_spin;
+        V.h_slope = g->h_slope;
+        V.first_bad = c->flags.p + 2;
+        int first = INT_MAX;
+        HIPCHK(hipMemcpyAsync(V.first_bad, &first, sizeof(int), hipMemcpyHostToDevice, c->stream));
+        zone_check_kernel<<<(nz + 255) / 256, 256, 0, c->stream>>>(V);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&first, V.first_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (first != INT_MAX) return fail(GM_EINVAL, "zone %d: bad n_e/B/theta/u (device input)", first);
+    }
     Instance &I = c->inst[instance];
     DevBuf<double> stage[5];
     const double *dsrc[5];
@@ -378,7 +408,7 @@ static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint
     // zones and on everything in the parameters but the seed: reuse them
     const bool reuse = I.made && I.ep.n_target == p->n_target && I.ep.nu_min == p->nu_min &&
                        I.ep.nu_max == p->nu_max && I.ep.n_wnodes == p->n_wnodes &&
-                       I.ep.w_floor_rel == p->w_floor_rel;
+                       I.ep.w_floor_rel == p->w_floor_rel;   // (a new emission table clears made)
     if (!reuse) {
         std::vector<double> nus(nw);
         for (int k = 0; k < nw; ++k) nus[k] = std::exp(lnmin + span * k / (nw - 1));
@@ -391,6 +421,11 @@ static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint
     E.w_floor_rel = p->w_floor_rel; E.nbar = I.nbar.p; E.fmax = I.fmax.p; E.count = I.count.p;
     E.key0 = (uint32_t)p->seed; E.key1 = (uint32_t)(p->seed >> 32); E.inst = instance;
     E.status = c->flags.p + 1;
+    E.mtab = I.mt_on ? I.mtab.p : nullptr;
+    E.mt_n = I.mt_n;
+    E.mt_lo = I.mt_lo;
+    E.mt_hi = I.mt_hi;
+    E.lnnu_min = lnmin;
     if (reuse) {
         recount_kernel<<<nblk, 256, 0, c->stream>>>(E);
     } else {
@@ -474,6 +509,7 @@ static PhotonQ queue(gm_ctx *c, int b)
     q.w = c->qd[b][7].p; q.wb = c->qd[b][8].p; q.x1 = c->qd[b][9].p;
     q.nua = c->qd[b][10].p; q.nus = c->qd[b][11].p; q.b = c->qd[b][12].p;
     q.s0 = c->qu[b][0].p; q.s1 = c->qu[b][1].p; q.s2 = c->qu[b][2].p; q.blk = c->qu[b][3].p;
+    q.ev = c->qu[b][4].p;
     q.n_sc = c->qi[b][0].p; q.zone = c->qi[b][1].p; q.inst = c->qi[b][2].p;
     return q;
 }
@@ -590,10 +626,16 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
     A.evlog = c->evlog;
     A.evlog_n = c->evlog_n.p;
     A.evlog_cap = c->evlog_cap;
+    A.root_stride = c->root_stride;
+    A.sw = I.sw_n == tp->n_nu * tp->n_theta ? I.sw.p : nullptr;
     A.lnb = I.lnb.p;
     A.lnb_n = I.lnb_n;
     A.lnb_lo = I.lnb_lo;
-    A.lnb_inv_d = I.lnb_n > 1 ? (I.lnb_n - 1) / (I.lnb_hi - I.lnb_lo) : 0.0;
+    A.lnb_hi = I.lnb_hi;
+    A.mtab = I.mt_on ? I.mtab.p : nullptr;
+    A.mt_n = I.mt_n;
+    A.mt_lo = I.mt_lo;
+    A.mt_hi = I.mt_hi;
     A.overflow = c->flags.p;
     A.cap = c->queue_cap;
     A.refill_min = c->refill_min;
@@ -615,11 +657,14 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
 // launch over the photons of all of them (each photon carries its
 // instance), root ranges chunked by queue capacity.
 static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_track_params *tp,
-                             std::vector<long long> &acc)
+                             bool hbm_tally, std::vector<long long> &acc)
 {
     const int n_inst = (int)ids.size();
     const size_t nspec = (size_t)tp->n_theta * tp->n_nu * 3;
-    const size_t lds_track = (size_t)n_inst * (L_N + S_N + nspec) * 8 + kEvBytesPerBlock;
+    // per instance in LDS: ledger and counters, and the tally unless it is
+    // added to in HBM directly
+    const size_t lds_stride = L_N + S_N + (hbm_tally ? 0 : nspec);
+    const size_t lds_track = (size_t)n_inst * lds_stride * 8 + kEvBytesPerBlock;
     const size_t lds_small = (size_t)n_inst * (L_N + S_N) * 8;
     const bool kerr = c->inst[ids[0]].grid.metric == GM_METRIC_KS_MKS;
     const bool f32 = tp->precision == GM_PRECISION_F32_EMISSIVITY;
@@ -665,7 +710,7 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     L.insts = c->inst_args.p;
     L.n_inst = n_inst;
     L.root_off = c->root_off.p;
-    L.lds_stride = (int)(L_N + S_N + nspec);
+    L.lds_stride = (int)lds_stride;
     L.inst_count = c->inst_ctr.p;
     L.inst_cursor = c->inst_ctr.p + GM_MAX_INSTANCES;
 
@@ -679,19 +724,48 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     unsigned long long chunk = std::max<unsigned long long>(1, c->queue_cap / 2);
     const size_t nacc_d = nspec + L_N, nacc_u = S_N;
     if (c->bak_d.ensure((size_t)n_inst * nacc_d) != hipSuccess ||
-        c->bak_u.ensure((size_t)n_inst * nacc_u + 2) != hipSuccess)
+        c->bak_u.ensure((size_t)n_inst * nacc_u + 2) != hipSuccess ||
+        c->call_bak_d.ensure((size_t)n_inst * nacc_d) != hipSuccess ||
+        c->call_bak_u.ensure((size_t)n_inst * nacc_u + 2) != hipSuccess)
         return fail(GM_ENOMEM, "chunk backup");
-    for (unsigned long long start = 0; start < total;) {
-        const unsigned long long cnt = std::min(chunk, total - start);
+    // accumulators before the chunk (b = bak) or the call (b = call_bak)
+    auto save = [&](DevBuf<double> &bd, DevBuf<unsigned long long> &bu) -> gm_status {
         for (int k = 0; k < n_inst; ++k) {
             Instance &I = c->inst[ids[k]];
-            HIPCHK(hipMemcpyAsync(c->bak_d.p + k * nacc_d, I.spec.p, nspec * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(hipMemcpyAsync(c->bak_d.p + k * nacc_d + nspec, I.ledger.p, L_N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(hipMemcpyAsync(c->bak_u.p + k * nacc_u, I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(bd.p + k * nacc_d, I.spec.p, nspec * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(bd.p + k * nacc_d + nspec, I.ledger.p, L_N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(bu.p + k * nacc_u, I.stats.p, S_N * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
         }
-        unsigned long long *bak_n = c->bak_u.p + (size_t)n_inst * nacc_u;
-        HIPCHK(hipMemcpyAsync(bak_n, c->trace_n.p, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(bak_n + 1, c->evlog_n.p, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        unsigned long long *bn = bu.p + (size_t)n_inst * nacc_u;
+        HIPCHK(hipMemcpyAsync(bn, c->trace_n.p, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(bn + 1, c->evlog_n.p, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        return GM_OK;
+    };
+    auto restore = [&](DevBuf<double> &bd, DevBuf<unsigned long long> &bu) -> gm_status {
+        for (int k = 0; k < n_inst; ++k) {
+            Instance &I = c->inst[ids[k]];
+            HIPCHK(hipMemcpyAsync(I.spec.p, bd.p + k * nacc_d, nspec * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(I.ledger.p, bd.p + k * nacc_d + nspec, L_N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(I.stats.p, bu.p + k * nacc_u, S_N * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        }
+        unsigned long long *bn = bu.p + (size_t)n_inst * nacc_u;
+        HIPCHK(hipMemcpyAsync(c->trace_n.p, bn, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->evlog_n.p, bn + 1, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        return GM_OK;
+    };
+    gm_status bs = save(c->call_bak_d, c->call_bak_u);
+    if (bs != GM_OK) return bs;
+    // event records of this call: their scores are passed up the ancestry
+    // once every chunk is done
+    unsigned long long ev_lo = 0;
+    if (c->evlog) {
+        HIPCHK(hipMemcpyAsync(&ev_lo, c->evlog_n.p, sizeof(ev_lo), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    for (unsigned long long start = 0; start < total;) {
+        const unsigned long long cnt = std::min(chunk, total - start);
+        bs = save(c->bak_d, c->bak_u);
+        if (bs != GM_OK) return bs;
         reset_counters_kernel<<<1, 64, 0, c->stream>>>(c->ctr.p, 64, c->flags.p);
         L.root_begin = start;
         L.root_count = cnt;
@@ -736,18 +810,32 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
             start += cnt;
             continue;
         }
-        if (cnt == 1)
-            return fail(GM_ENOMEM, "the scattering cascade of one root overflows the photon queue of %llu", c->queue_cap);
-        for (int k = 0; k < n_inst; ++k) {
-            Instance &I = c->inst[ids[k]];
-            HIPCHK(hipMemcpyAsync(I.spec.p, c->bak_d.p + k * nacc_d, nspec * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(hipMemcpyAsync(I.ledger.p, c->bak_d.p + k * nacc_d + nspec, L_N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(hipMemcpyAsync(I.stats.p, c->bak_u.p + k * nacc_u, S_N * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        // a single root's cascade overflows: the call is undone for these
+        // instances (accumulators and counts as before it; roots still pending)
+        if (cnt == 1) {
+            bs = restore(c->call_bak_d, c->call_bak_u);
+            if (bs != GM_OK) return bs;
+            HIPCHK(hipStreamSynchronize(c->stream));
+            return fail(GM_ENOMEM, "the scattering cascade of root %llu alone overflows the photon queue of %llu",
+                        start, c->queue_cap);
         }
-        HIPCHK(hipMemcpyAsync(c->trace_n.p, bak_n, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(c->evlog_n.p, bak_n + 1, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        // undo the chunk: tallies, ledgers, counters, trace and event-log counts
+        bs = restore(c->bak_d, c->bak_u);
+        if (bs != GM_OK) return bs;
         c->chunk_retries += 1;
         chunk = std::max<unsigned long long>(1, cnt / 4);
+    }
+    if (c->evlog) {
+        unsigned long long ev_hi = 0;
+        HIPCHK(hipMemcpyAsync(&ev_hi, c->evlog_n.p, sizeof(ev_hi), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        ev_hi = std::min(ev_hi, c->evlog_cap);
+        if (ev_hi > ev_lo) {
+            const unsigned nb = (unsigned)std::min<unsigned long long>((ev_hi - ev_lo + 255) / 256, 4096);
+            for (int g = tp->n_sc_max; g >= 1; --g)
+                score_propagate_kernel<<<nb, 256, 0, c->stream>>>(c->evlog, ev_lo, ev_hi, g);
+            HIPCHK(hipGetLastError());
+        }
     }
     // counters of every instance, one synchronisation
     std::vector<unsigned long long> st((size_t)n_inst * S_N);
@@ -768,7 +856,7 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     if (tp->n_nu < 1 || tp->n_theta < 1 || !(tp->nu_lo > 0.0) || !(tp->nu_hi > tp->nu_lo) ||
         !(tp->bias_max >= 1.0) || !(tp->step_h > 0.0) || tp->verlet_max_it < 1 || tp->n_sc_max < 0 ||
         tp->n_sc_max > 15 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0) || tp->max_steps < 1 ||
-        tp->bias_mode < 0 || tp->bias_mode > 3 || (tp->bias_mode < 3 && !(tp->bias_value > 0.0)))
+        tp->bias_mode < 0 || tp->bias_mode > 4 || (tp->bias_mode < 3 && !(tp->bias_value > 0.0)))
         return fail(GM_EINVAL, "bad track parameters");
     if (tp->precision != GM_PRECISION_F64 && tp->precision != GM_PRECISION_F32_EMISSIVITY)
         return fail(GM_EINVAL, "precision %d", tp->precision);
@@ -780,8 +868,11 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     for (int i = 0; i < GM_MAX_INSTANCES; ++i) {
         const Instance &I = c->inst[i];
         const int mode = I.bias_mode >= 0 ? I.bias_mode : tp->bias_mode;
-        if (I.pending && mode == GM_BIAS_LEARNED && (!I.lnb.p || I.lnb_n < 2))
-            return fail(GM_ESTATE, "instance %d has no learned bias table", i);
+        if (I.pending && (mode == GM_BIAS_TABLE || mode == GM_BIAS_WINDOW) && (!I.lnb.p || I.lnb_n < 2))
+            return fail(GM_ESTATE, "instance %d has no bias table", i);
+        if (I.pending && I.sw_n && I.sw_n != tp->n_nu * tp->n_theta)
+            return fail(GM_EINVAL, "instance %d: score weights of %d bins, tally of %d", i, I.sw_n,
+                        tp->n_nu * tp->n_theta);
     }
     if (tp->scattering) {
         s = ensure_sigma_hot(c);
@@ -797,24 +888,29 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     if (c->queue_cap_set) need = c->queue_cap_set;
     s = ensure_children(c, need);
     if (s != GM_OK) return s;
-    // instances of one metric share launches, as many as their LDS tallies
-    // allow (and at most max_batch): 56 KiB of tallies and the event staging
-    // per block keep two blocks on a CU
-    const size_t per_inst = (size_t)(L_N + S_N + (size_t)tp->n_theta * tp->n_nu * 3) * 8;
-    const size_t tally_budget = 56 * 1024;
-    if (per_inst > tally_budget) return fail(GM_EUNSUPPORTED, "tally of %d bins exceeds the LDS tally", tp->n_theta * tp->n_nu);
-    const int fit = (int)std::min<size_t>(tally_budget / per_inst, (size_t)c->max_batch);
+    // instances of one metric share launches (at most max_batch).  56 KiB
+    // of per-block accumulators and the event staging keep two blocks on a
+    // CU: the tallies stay in LDS when those of the group fit, else every
+    // escape adds to the instance's tally in HBM directly
+    const size_t per_small = (size_t)(L_N + S_N) * 8;
+    const size_t per_inst = per_small + (size_t)tp->n_theta * tp->n_nu * 3 * 8;
+    const size_t acc_budget = 56 * 1024;
     std::vector<long long> acc(S_N, 0);
     for (int metric = 0; metric < 2; ++metric) {
-        std::vector<int> ids;
-        for (int i = 0; i <= GM_MAX_INSTANCES; ++i) {
-            const bool take = i < GM_MAX_INSTANCES && c->inst[i].pending && c->inst[i].grid.metric == metric;
-            if (take) ids.push_back(i);
-            if (!ids.empty() && ((int)ids.size() == fit || i == GM_MAX_INSTANCES)) {
-                s = track_batch(c, ids, tp, acc);
-                if (s != GM_OK) return s;
-                ids.clear();
-            }
+        std::vector<int> pend;
+        for (int i = 0; i < GM_MAX_INSTANCES; ++i)
+            if (c->inst[i].pending && c->inst[i].grid.metric == metric) pend.push_back(i);
+        if (pend.empty()) continue;
+        const int want = std::min((int)pend.size(), c->max_batch);
+        const int lds_fit = (int)(acc_budget / per_inst);
+        bool hbm = c->tally_mode == 2 || (c->tally_mode == 0 && lds_fit < want);
+        if (c->tally_mode == 1 && lds_fit < 1)
+            return fail(GM_EUNSUPPORTED, "tally of %d bins exceeds the LDS budget", tp->n_theta * tp->n_nu);
+        const int group = hbm ? std::min(want, (int)(acc_budget / per_small)) : std::min(want, lds_fit);
+        for (size_t g0 = 0; g0 < pend.size(); g0 += group) {
+            std::vector<int> ids(pend.begin() + g0, pend.begin() + std::min(pend.size(), g0 + group));
+            s = track_batch(c, ids, tp, hbm, acc);
+            if (s != GM_OK) return s;
         }
     }
     if (stats)
@@ -912,7 +1008,7 @@ gm_status gm_set_instance_bias(gm_ctx *c, int instance, int bias_mode, double bi
 {
     if (!c) return fail(GM_EINVAL, "NULL context");
     if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
-    if (bias_mode > 3 || (bias_mode >= 0 && !(bias_max >= 1.0)) ||
+    if (bias_mode > 4 || (bias_mode >= 0 && !(bias_max >= 1.0)) ||
         (bias_mode >= 0 && bias_mode < 3 && !(bias_value > 0.0)))
         return fail(GM_EINVAL, "bad bias");
     Instance &I = c->inst[instance];
@@ -1047,14 +1143,15 @@ gm_status gm_eval_G(gm_ctx *c, const double *hx, double *hy, int n)
     return GM_OK;
 }
 
-gm_status gm_set_event_log(gm_ctx *c, void *buf, uint64_t capacity)
+gm_status gm_set_event_log(gm_ctx *c, void *buf, uint64_t capacity, uint64_t root_stride)
 {
     if (!c) return fail(GM_EINVAL, "NULL context");
-    if (buf && capacity == 0) return fail(GM_EINVAL, "zero capacity");
+    if (buf && (capacity == 0 || capacity > 0xfffffffeull)) return fail(GM_EINVAL, "capacity not in [1, 2^32 - 2]");
     gm_status s = set_device(c);
     if (s != GM_OK) return s;
     c->evlog = (EventRec *)buf;
     c->evlog_cap = buf ? capacity : 0;
+    c->root_stride = buf ? root_stride : 0;
     HIPCHK(hipMemsetAsync(c->evlog_n.p, 0, sizeof(unsigned long long), c->stream));
     return GM_OK;
 }
@@ -1093,6 +1190,61 @@ gm_status gm_set_bias_table(gm_ctx *c, int instance, const double *ln_b, int n_e
     return GM_OK;
 }
 
+gm_status gm_set_emission_table(gm_ctx *c, int instance, const double *m, int n_nodes, double ln_nu_lo,
+                                double ln_nu_hi)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    Instance &I = c->inst[instance];
+    if (!I.loaded) return fail(GM_ESTATE, "instance %d has no zones", instance);
+    if (!m) {
+        I.mt_on = false;
+        I.made = false;          // the expected counts change with the table
+        return GM_OK;
+    }
+    if (n_nodes < 2 || n_nodes > 4096 || !(ln_nu_hi > ln_nu_lo)) return fail(GM_EINVAL, "bad emission table shape");
+    const size_t n = (size_t)I.nz * n_nodes;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(m[i])) return fail(GM_EINVAL, "emission table entry %zu not finite", i);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    if (I.mtab.ensure(n) != hipSuccess) return fail(GM_ENOMEM, "emission table");
+    HIPCHK(hipMemcpyAsync(I.mtab.p, m, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    I.mt_n = n_nodes;
+    I.mt_lo = ln_nu_lo;
+    I.mt_hi = ln_nu_hi;
+    I.mt_on = true;
+    I.made = false;
+    return GM_OK;
+}
+
+gm_status gm_set_score_weights(gm_ctx *c, int instance, const double *sw, int n)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    Instance &I = c->inst[instance];
+    if (!sw) { I.sw_n = 0; return GM_OK; }
+    if (n < 1) return fail(GM_EINVAL, "bad score weights");
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(sw[i])) return fail(GM_EINVAL, "score weight %d not finite", i);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    if (I.sw.ensure(n) != hipSuccess) return fail(GM_ENOMEM, "score weights");
+    HIPCHK(hipMemcpyAsync(I.sw.p, sw, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    I.sw_n = n;
+    return GM_OK;
+}
+
+gm_status gm_set_tally_mode(gm_ctx *c, int mode)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (mode < 0 || mode > 2) return fail(GM_EINVAL, "tally mode %d not in 0..2", mode);
+    c->tally_mode = mode;
+    return GM_OK;
+}
+
 static gm_status mlp_buffers(gm_ctx *c)
 {
     if (c->mlp_p.ensure(kMlpParams) != hipSuccess || c->mlp_m.ensure(kMlpParams) != hipSuccess ||
@@ -1118,6 +1270,14 @@ gm_status gm_mlp_set_params(gm_ctx *c, const float *params)
     HIPCHK(hipStreamSynchronize(c->stream));
     c->mlp_t = 0;
     c->mlp_ready = true;
+    return GM_OK;
+}
+
+gm_status gm_mlp_set_loss(gm_ctx *c, int kind)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (kind != GM_MLP_SQUARED && kind != GM_MLP_POISSON) return fail(GM_EINVAL, "loss kind %d", kind);
+    c->mlp_loss = kind;
     return GM_OK;
 }
 
@@ -1154,7 +1314,7 @@ static gm_status mlp_gradient(gm_ctx *c, const float *X, const float *T, const f
     if (c->mlp_gpart.ensure((size_t)nb * (kMlpParams + 1)) != hipSuccess) return fail(GM_ENOMEM, "gradient partials");
     MlpArgs M{};
     M.X = X; M.T = T; M.C = C; M.n = n; M.P = c->mlp_p.p; M.Pb = c->mlp_pb.p;
-    M.gpart = c->mlp_gpart.p; M.loss_scale = 1.0f;
+    M.gpart = c->mlp_gpart.p; M.loss_scale = 1.0f; M.loss_kind = c->mlp_loss;
     mlp_grad_kernel<<<(unsigned)nb, 64 * kMlpGradWaves, 0, c->stream>>>(M);
     HIPCHK(hipGetLastError());
     mlp_reduce_kernel<<<(kMlpParams + 1 + 255) / 256, 256, 0, c->stream>>>(c->mlp_gpart.p, (int)nb, c->mlp_g.p);

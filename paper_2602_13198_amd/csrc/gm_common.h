@@ -87,6 +87,22 @@ GM_HD Rng child_rng(const Rng &p, uint32_t block_at, uint32_t k0, uint32_t k1)
     return Rng{o.x, o.y, o.z | 0x80000000u, 0u};
 }
 
+// Value of a per-zone table at log variable v: n nodes per zone uniform in
+// v over [lo, hi], linear between nodes, the end node's value outside.
+GM_HD double zone_table(const double *tab, int n, double lo, double hi, int z, double v)
+{
+    const double *t = tab + (size_t)z * n;
+    double pos = (v - lo) / (hi - lo) * (double)(n - 1);
+    if (pos <= 0.0) return t[0];
+    if (pos >= (double)(n - 1)) return t[n - 1];
+    int i = (int)floor(pos);
+    double f = pos - (double)i;
+    return t[i] + f * (t[i + 1] - t[i]);
+}
+
+// No event record (event-log index of a photon without one).
+constexpr uint32_t kNoEvent = 0xffffffffu;
+
 // Keep a wave-uniform value in a vector register: the compiler otherwise
 // re-reads kernel arguments from memory inside long loops when scalar
 // registers run short, and waits for every re-read.

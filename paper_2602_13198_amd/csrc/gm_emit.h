@@ -85,6 +85,47 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
     f[F_NE] = (float)ne;
 }
 
+// Validation of zone inputs that live in device memory (the host path runs
+// the same tests on the host): finite n_e >= 0, B >= 0 and Theta_e; where
+// n_e > 0, Theta_e > 0 and u^t > 0, and in Kerr a timelike u at the zone
+// centre.  The smallest bad zone index is left in *first_bad.
+struct CheckArgs {
+    const double *n_e, *theta, *B, *ucon;
+    int nz;
+    int n[3];
+    double xs[3], dx[3];
+    int kerr;
+    double a_spin, h_slope;
+    int *first_bad;
+};
+
+__global__ __launch_bounds__(256) void zone_check_kernel(CheckArgs C)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.nz) return;
+    double ne = C.n_e[i], th = C.theta[i], B = C.B[i];
+    bool bad = !(ne >= 0.0) || !isfinite(ne) || !(B >= 0.0) || !isfinite(B) || !isfinite(th);
+    if (!bad && ne > 0.0) {
+        bad = !(th > 0.0) || !(C.ucon[i] > 0.0);
+        if (!bad && C.kerr) {
+            int i2 = (i / C.n[2]) % C.n[1], i1 = i / (C.n[2] * C.n[1]);
+            KMetric K;
+            kerr_metric<false>(C.a_spin, C.h_slope, C.xs[0] + (i1 + 0.5) * C.dx[0], C.xs[1] + (i2 + 0.5) * C.dx[1], K);
+            double g[4][4], u[4];
+            kerr_full(K, g);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) u[m] = C.ucon[(size_t)m * C.nz + i];
+            double uu = 0.0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) uu += g[m][n] * u[m] * u[n];
+            bad = !(uu < 0.0);
+        }
+    }
+    if (bad) atomicMin(C.first_bad, i);
+}
+
 // ---------------------------------------------------------------------------
 // Weight table (Creation of superphotons section, eq:weight_calc):
 //   w(nu_k) = Delta t Delta(ln nu) / (h N_s) sum_i V_i J_i(nu_k) + floor,
@@ -107,6 +148,11 @@ struct EmitArgs {
     uint32_t key0, key1;
     int inst;
     int *status;
+    // emission table (NULL: none): zone i emits with w_i(nu) = w(nu) e^{-m_i(ln nu)},
+    // nodes uniform over [mt_lo, mt_hi]; ln nu of weight node k = lnnu_min + span k/(nw-1)
+    const double *mtab;
+    int mt_n;
+    double mt_lo, mt_hi, lnnu_min;
 };
 
 GM_D double zone_J(const double *zr, double nu, const GCheb &G)
@@ -163,6 +209,8 @@ __global__ __launch_bounds__(256) void weight_table_kernel(EmitArgs E)
 // nodes, its composite-Simpson integral n-bar, the rejection bound
 // F_max = 1.02 max_k J/w, and the count floor(n-bar) + [u < frac(n-bar)]
 // with u the first draw of the zone's stream (z, 0, instance<<8 | 2).
+// Under an emission table the zone's weights are w e^{-m_i}: more, lighter
+// superphotons where m_i > 0, with the same expected luminosity.
 __global__ __launch_bounds__(256) void count_kernel(EmitArgs E)
 {
     int z = blockIdx.x * 256 + threadIdx.x;
@@ -171,7 +219,11 @@ __global__ __launch_bounds__(256) void count_kernel(EmitArgs E)
     if (E.emits[z]) {
         const double *zr = E.zrec + (size_t)z * Z_STRIDE;
         for (int k = 0; k < E.nw; ++k) {
-            double F = zone_J(zr, E.nu_nodes[k], E.G) / E.w_node[k];
+            double wk_ = E.w_node[k];
+            if (E.mtab)
+                wk_ *= exp(-zone_table(E.mtab, E.mt_n, E.mt_lo, E.mt_hi, z,
+                                       E.lnnu_min + E.span * k / (E.nw - 1)));
+            double F = zone_J(zr, E.nu_nodes[k], E.G) / wk_;
             double wk = (k == 0 || k == E.nw - 1) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
             s += wk * F;
             fm = fmax(fm, F);

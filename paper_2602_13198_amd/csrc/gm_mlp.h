@@ -6,9 +6,12 @@
 // MFMAs (v_mfma_f32_16x16x16_bf16); between layers the activations go
 // through LDS to turn the accumulator layout into the operand layout.  The
 // backward pass forms the weight gradients H^T dZ with the 16 rows of the
-// tile as the MFMA reduction dimension; blocks write partial gradients that
-// a second kernel sums in block order (deterministic), and an Adam kernel
-// updates the FP32 weights and refreshes their BF16 copies.
+// tile as the MFMA reduction dimension.  Within a block each gradient entry
+// receives exactly one addition per wave (two waves) onto zero, and IEEE
+// addition is commutative, so the block's partial does not depend on the
+// order of the waves' LDS atomics; blocks write their partials, which a
+// second kernel sums in block order, so the gradient is deterministic.  An
+// Adam kernel updates the FP32 weights and refreshes their BF16 copies.
 //
 // Operand layouts of the 16x16x16 BF16 MFMA (lane l, element j = 0..3):
 //   A (16 x K16):  row l % 16, k = 4 (l / 16) + j
@@ -66,6 +69,7 @@ struct MlpArgs {
     const short *Pb;       // BF16 padded weights
     float *gpart;          // [n_blocks][kMlpParams + 1] partial gradients (+ loss)
     float loss_scale;      // 1 / sum of the loss weights
+    int loss_kind;         // 0: C (y - T)^2; 1: log-link Poisson deviance C (e^y - T y)
 };
 
 // Per-wave LDS scratch: a 16 x 64 tile (+1 pad column) of floats.
@@ -191,10 +195,11 @@ __global__ __launch_bounds__(64 * kMlpWaves) void mlp_forward_kernel(MlpArgs M)
     }
 }
 
-// Forward + backward of a weighted squared loss
-//   L = loss_scale * sum_rows sum_o C[r][o] (y[r][o] - T[r][o])^2
-// over the rows of this block; writes the block's partial gradient and
-// loss to gpart[block].
+// Forward + backward of a weighted loss over the rows of this block,
+//   L = loss_scale * sum_rows sum_o C[r][o] l(y[r][o], T[r][o]),
+// l = (y - T)^2 or the Poisson deviance e^y - T y (minimised by
+// y = ln E[T], also for targets that are mostly zero); writes the block's
+// partial gradient and loss to gpart[block].
 __global__ __launch_bounds__(64 * kMlpGradWaves) void mlp_grad_kernel(MlpArgs M)
 {
     __shared__ float lds[kMlpGradWaves][4][16 * kTileLd];    // h1, h2, dz2, dz1 per wave
@@ -216,9 +221,16 @@ __global__ __launch_bounds__(64 * kMlpGradWaves) void mlp_grad_kernel(MlpArgs M)
             for (int j = 0; j < 4; ++j) {
                 long long r = r0 + 4 * (l >> 4) + j;
                 if (r < M.n) {
-                    float c = M.C[r * kMlpOut + n], e = y[j] - M.T[r * kMlpOut + n];
-                    dy[j] = 2.0f * M.loss_scale * c * e;
-                    lsum += M.loss_scale * c * e * e;
+                    const float c = M.C[r * kMlpOut + n], t = M.T[r * kMlpOut + n];
+                    if (M.loss_kind == 1) {
+                        const float ey = expf(y[j]);
+                        dy[j] = M.loss_scale * c * (ey - t);
+                        lsum += M.loss_scale * c * (ey - t * y[j]);
+                    } else {
+                        const float e = y[j] - t;
+                        dy[j] = 2.0f * M.loss_scale * c * e;
+                        lsum += M.loss_scale * c * e * e;
+                    }
                 }
             }
         }

@@ -29,18 +29,27 @@ struct PhotonQ {
     double *x[3], *k[4];
     double *w, *wb, *x1, *nua, *nus, *b;
     uint32_t *s0, *s1, *s2, *blk;
+    uint32_t *ev;                  // event-log record that created the photon (kNoEvent: none);
+                                   // in an event queue: the scattering photon's record
     int32_t *n_sc, *zone, *inst;
 };
 
-// One scattering event of the event log (training records of the learned
-// form): the child's stream, the zone and the incoming photon's fluid-frame
-// energy at the event, the child's weight and the event position.  64 bytes.
+// One event of the event log (records of the learned and adaptive forms):
+// the emission of a root or a scattering, keyed by the stream of the photon
+// it created.  score sums w E s_bin over that photon and all its
+// descendants that escape into a tally bin (E the energy at infinity in
+// erg, s_bin the bin's score weight); parent is the record of the photon
+// that scattered, so scores propagate up the ancestry.  88 bytes.
 struct EventRec {
-    uint32_t s0, s1, s2;
-    int32_t zone;
-    double eps, w_child;
-    double x[3];
-    double pad;
+    uint32_t s0, s1, s2;           // stream of the photon the event created
+    uint32_t p0, p1, p2;           // stream of the photon that scattered (0: emission)
+    int32_t zone, gen;             // plasma zone; generation of the created photon
+    uint32_t parent, pad;          // record of the scattering photon (kNoEvent: none)
+    double eps;                    // fluid-frame energy of the incoming (scattering) or
+                                   // emitted photon, m_e c^2
+    double w;                      // weight of the created photon
+    double score;
+    double x[3];                   // event position, code coordinates
 };
 
 struct TraceRec {
@@ -113,10 +122,17 @@ struct TArgs {
     EventRec *evlog;
     unsigned long long *evlog_n;
     unsigned long long evlog_cap;
-    // learned bias: ln b per zone on ln(eps) nodes (bias mode 3)
+    unsigned long long root_stride;   // roots with id % root_stride == 0 log their emission
+    const double *sw;                 // score weights [n_theta][n_nu] (NULL: 1)
+    // bias table: ln of the bias (mode 3) or of the importance factor
+    // (mode 4) per zone on ln(eps) nodes over [lnb_lo, lnb_hi]
     const double *lnb;
     int lnb_n;
-    double lnb_lo, lnb_inv_d;
+    double lnb_lo, lnb_hi;
+    // emission table: ln w_i(nu) = ln w(nu) - m_i(ln nu), nodes over [mt_lo, mt_hi]
+    const double *mtab;
+    int mt_n;
+    double mt_lo, mt_hi;
 };
 
 struct Coef {
@@ -141,7 +157,7 @@ struct StepArgs {
     float ln_c2_2h;
     const double *lnb;
     int lnb_n;
-    double lnb_lo, lnb_inv_d;
+    double lnb_lo, lnb_hi;
 };
 
 GM_D StepArgs step_args(const TArgs &T)
@@ -155,7 +171,7 @@ GM_D StepArgs step_args(const TArgs &T)
     S.key0 = T.key0; S.key1 = T.key1;
     S.bias_value = T.bias_value; S.bias_max = T.bias_max; S.L_unit_cm = T.L_unit_cm;
     S.sh = T.sh; S.sh32 = T.sh32; S.ln_c2_2h = T.ln_c2_2h;
-    S.lnb = T.lnb; S.lnb_n = T.lnb_n; S.lnb_lo = T.lnb_lo; S.lnb_inv_d = T.lnb_inv_d;
+    S.lnb = T.lnb; S.lnb_n = T.lnb_n; S.lnb_lo = T.lnb_lo; S.lnb_hi = T.lnb_hi;
     return S;
 }
 
@@ -176,13 +192,15 @@ GM_D void lds_zero(double *lds, int n_inst, int stride)
     __syncthreads();
 }
 
+// The tally is in LDS when the stride leaves room for it, else the
+// instance's tally in HBM is added to directly (spec = NULL here).
 GM_D BlockAcc lds_acc(double *lds, int stride, int inst)
 {
     BlockAcc B;
     double *base = lds + (size_t)inst * stride;
     B.ledger = base;
     B.stats = reinterpret_cast<unsigned long long *>(base + L_N);
-    B.spec = base + L_N + S_N;
+    B.spec = stride > L_N + S_N ? base + L_N + S_N : nullptr;
     return B;
 }
 
@@ -220,7 +238,8 @@ constexpr size_t kEvBytesPerBlock = (size_t)(256 / 64) * kEvDoubles * 8;
 
 struct EvStage {
     double *d;    // [8][kEvCap]: x1, x2, x3, k0..k3, w
-    int *i;       // [7][kEvCap]: instance, parent stream s0 s1 s2 and block, generation, zone
+    int *i;       // [7][kEvCap]: instance | generation << 8, parent stream s0 s1 s2 and
+                  // block, parent's event record, zone
     int n;
 };
 
@@ -250,12 +269,13 @@ GM_D void ev_flush(const TArgs &L, EvStage &S)
 #pragma unroll
             for (int m = 0; m < 4; ++m) Q.k[m][q] = S.d[(3 + m) * kEvCap + l];
             Q.w[q] = S.d[7 * kEvCap + l];
-            Q.inst[q] = S.i[l];
+            Q.inst[q] = S.i[l] & 0xff;
+            Q.n_sc[q] = S.i[l] >> 8;
             Q.s0[q] = (uint32_t)S.i[kEvCap + l];
             Q.s1[q] = (uint32_t)S.i[2 * kEvCap + l];
             Q.s2[q] = (uint32_t)S.i[3 * kEvCap + l];
             Q.blk[q] = (uint32_t)S.i[4 * kEvCap + l];
-            Q.n_sc[q] = S.i[5 * kEvCap + l];
+            Q.ev[q] = (uint32_t)S.i[5 * kEvCap + l];
             Q.zone[q] = S.i[6 * kEvCap + l];
         } else {
             atomicOr(L.overflow, 1);
@@ -267,9 +287,10 @@ GM_D void ev_flush(const TArgs &L, EvStage &S)
 // Stage the events of the lanes in `smask` (whole wave; `scat` is this
 // lane's bit): scattering point x, incoming wavevector k, child weight, the
 // parent's stream and counter block at the event (the scattering kernel
-// derives the child's stream from them), child generation and plasma zone.
+// derives the child's stream from them), child generation, the parent's
+// event record and the plasma zone.
 GM_D void ev_push(const TArgs &L, EvStage &S, uint64_t smask, bool scat, int inst, const double *x,
-                  const double *k, double w, const Rng &r, int n_sc, int zone)
+                  const double *k, double w, const Rng &r, int n_sc, uint32_t pev, int zone)
 {
     const int nn = __popcll(smask);
     if (S.n + nn > kEvCap) ev_flush(L, S);
@@ -280,15 +301,46 @@ GM_D void ev_push(const TArgs &L, EvStage &S, uint64_t smask, bool scat, int ins
 #pragma unroll
         for (int m = 0; m < 4; ++m) S.d[(3 + m) * kEvCap + j] = k[m];
         S.d[7 * kEvCap + j] = w;
-        S.i[j] = inst;
+        S.i[j] = inst | (n_sc << 8);
         S.i[kEvCap + j] = (int)r.s0;
         S.i[2 * kEvCap + j] = (int)r.s1;
         S.i[3 * kEvCap + j] = (int)r.s2;
         S.i[4 * kEvCap + j] = (int)r.block;
-        S.i[5 * kEvCap + j] = n_sc;
+        S.i[5 * kEvCap + j] = (int)pev;
         S.i[6 * kEvCap + j] = zone;
     }
     S.n += nn;
+}
+
+// Append an event to the log (emission: parent stream NULL); returns its
+// index, or kNoEvent when the log is full (the event is still counted).
+GM_D uint32_t log_event(const TArgs &A, const Rng &made, const Rng *par, int z, int gen, double eps, double w,
+                        const double *x, uint32_t parent)
+{
+    unsigned long long i = atomicAdd(A.evlog_n, 1ull);
+    if (i >= A.evlog_cap) return kNoEvent;
+    EventRec &e = A.evlog[i];
+    e.s0 = made.s0; e.s1 = made.s1; e.s2 = made.s2;
+    e.p0 = par ? par->s0 : 0u; e.p1 = par ? par->s1 : 0u; e.p2 = par ? par->s2 : 0u;
+    e.zone = z;
+    e.gen = gen;
+    e.parent = parent;
+    e.pad = 0u;
+    e.eps = eps;
+    e.w = w;
+    e.score = 0.0;
+    e.x[0] = x[0]; e.x[1] = x[1]; e.x[2] = x[2];
+    return (uint32_t)i;
+}
+
+// An escape into tally bin (ith, inu) with energy E adds to the score of the
+// photon's own record; scores reach the ancestors' records afterwards
+// (score_propagate_kernel).
+GM_D void score_escape(const TArgs &A, uint32_t ev, int ith, int inu, double E)
+{
+    if (!A.evlog || ev == kNoEvent) return;
+    double s = A.sw ? E * A.sw[(size_t)ith * A.n_nu + inu] : E;
+    atomicAdd(&A.evlog[ev].score, s);
 }
 
 // Instance of a root in the launch's combined root range (binary search of
@@ -337,10 +389,12 @@ GM_D int zone_ks(const TArgs &A, double x1, double x2, double x3)
 }
 
 // Bias of a point (Scattering section): constant, Theta_e^2-scaled,
-// growing with the generation and falling with the density, or learned
-// (ln b of the zone interpolated linearly in ln eps on its node table);
-// clamped to [1, bias_max].  Any b >= 1 keeps the estimator unbiased: the
-// child carries w/b, the parent keeps w(1 - 1/b).
+// growing with the generation and falling with the density, or from the
+// zone's table (exp of its entry interpolated in ln eps), clamped to
+// [1, bias_max].  In the weight-window mode (4) the table gives an
+// importance factor, returned unclamped: the bias of a step is the
+// photon's weight times it (step_bias).  Any b >= 1 keeps the estimator
+// unbiased: the child carries w/b, the parent keeps w(1 - 1/b).
 template <class Args>
 GM_D double bias_at(const Args &A, int z, double theta, double ne, int n_sc, double eps)
 {
@@ -349,14 +403,20 @@ GM_D double bias_at(const Args &A, int z, double theta, double ne, int n_sc, dou
     else if (A.bias_mode == 1) b = A.bias_value * theta * theta;
     else if (A.bias_mode == 2) b = (double)((n_sc + 1) * (n_sc + 1)) / (ne * kSigT * A.bias_value * A.L_unit_cm);
     else {
-        double a = (log(eps) - A.lnb_lo) * A.lnb_inv_d;
-        a = fmin(fmax(a, 0.0), (double)(A.lnb_n - 1));
-        int i = min((int)a, A.lnb_n - 2);
-        double f = a - (double)i;
-        const double *t = A.lnb + (size_t)z * A.lnb_n + i;
-        b = exp((1.0 - f) * t[0] + f * t[1]);
+        b = exp(zone_table(A.lnb, A.lnb_n, A.lnb_lo, A.lnb_hi, z, log(eps)));
+        if (A.bias_mode == 4) return b;
     }
     return fmin(fmax(b, 1.0), A.bias_max);
+}
+
+// Bias of a step from the value carried by the photon or evaluated at the
+// step's end: the value itself, or in the weight-window mode the weight at
+// the step's start times the importance factor, clamped to [1, bias_max].
+template <class Args>
+GM_D double step_bias(const Args &A, double w, double bf)
+{
+    if (A.bias_mode != 4) return bf;
+    return fmin(fmax(w * bf, 1.0), A.bias_max);
 }
 
 // Invariant absorption and scattering coefficients (nu alpha) at a point
@@ -504,6 +564,7 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
             i = max(0, min(i, A.n_wnodes - 2));
             double f = a - i;
             lnw = (1.0 - f) * A.ln_w[i] + f * A.ln_w[i + 1];
+            if (A.mtab) lnw -= zone_table(A.mtab, A.mt_n, A.mt_lo, A.mt_hi, (int)z, lnnu);
             double F = 4.0 * kPi * Az * G_of_Xc(A.G, nu / nuc) / exp(lnw);
             ++trials;
             over += (F > fm) ? 1u : 0u;
@@ -559,6 +620,8 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
         Q.nua[q] = c.nua; Q.nus[q] = c.nus; Q.b[q] = c.b;
         Q.s0[q] = rng.s0; Q.s1[q] = rng.s1; Q.s2[q] = rng.s2; Q.blk[q] = rng.block;
         Q.n_sc[q] = 0;
+        Q.ev[q] = (A.evlog && p % A.root_stride == 0)
+                      ? log_event(A, rng, nullptr, (int)z, 0, eps, w, x + 1, kNoEvent) : kNoEvent;
         lds_add(&B.ledger[L_W_EMIT], w);
         lds_add(&B.ledger[L_E_EMIT], w * e_inf(g, k) * kMeC2);
         lds_inc(&B.stats[S_ROOTS], 1);
@@ -581,6 +644,7 @@ struct Photon {
     double acc_wabs, acc_wcap;     // weight lost to absorption / the generation cap
     Rng rng;
     int n_sc, inst;
+    uint32_t ev;                   // event-log record that created the photon
     uint32_t steps, nsub;          // steps; partial steps to scattering points
     // opacities and bias of the last zone evaluated: in flat spacetime they
     // depend only on the zone, k (fixed for a photon) and n_sc, so a step
@@ -601,6 +665,7 @@ GM_D void load_photon(const PhotonQ &Q, unsigned long long i, Photon &ph)
     ph.rng = Rng{Q.s0[i], Q.s1[i], Q.s2[i], Q.blk[i]};
     ph.n_sc = Q.n_sc[i];
     ph.inst = Q.inst[i];
+    ph.ev = Q.ev[i];
     ph.steps = 0;
     ph.nsub = 0;
     ph.cz = INT_MIN;
@@ -641,10 +706,11 @@ GM_D void finish(const TArgs &A, BlockAcc &B, const Photon &ph, int kind)
             ith = max(0, min((int)floor(th * A.n_theta / kPi), A.n_theta - 1));
             inu = (int)fi;
             double E = ph.w * e;
-            double *bin = B.spec + ((size_t)ith * A.n_nu + inu) * 3;
+            double *bin = (B.spec ? B.spec : A.spec) + ((size_t)ith * A.n_nu + inu) * 3;
             lds_add(&bin[0], E);
             lds_add(&bin[1], E * E);
             lds_add(&bin[2], 1.0);
+            score_escape(A, ph.ev, ith, inu, E);
         }
     }
     if (ph.acc_wabs != 0.0) { lds_add(&B.ledger[L_W_ABS], ph.acc_wabs); lds_add(&B.ledger[L_E_ABS], ph.acc_wabs * e); }
@@ -787,7 +853,8 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
                 // ---- optical depths by the trapezoid rule ----
                 double tau_a = 0.5 * (ph.nua + c1.nua) * A.C * dl;
                 double tau_s = A.scattering ? 0.5 * (ph.nus + c1.nus) * A.C * dl : 0.0;
-                double b = c1.vacuum ? ph.b : c1.b;
+                const double bf = c1.vacuum ? ph.b : c1.b;
+                const double b = step_bias(A, ph.w, bf);
                 if (A.scattering && ph.n_sc < A.n_sc_max && b * tau_s > ph.x1) {
                     // ---- scattering point: the step's start advanced over
                     // the fraction f of the step (a straight line here) ----
@@ -840,7 +907,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
                     ph.acc_wabs += wba - ph.w;
 #pragma unroll
                     for (int m = 0; m < 3; ++m) ph.x[m] = xn[m];
-                    ph.nua = c1.nua; ph.nus = c1.nus; ph.b = b;
+                    ph.nua = c1.nua; ph.nus = c1.nus; ph.b = bf;
                     bool esc = false;
 #pragma unroll
                     for (int j = 0; j < 3; ++j) esc |= (ph.x[j] < A.xs[j]) || (ph.x[j] >= A.xe[j]);
@@ -884,7 +951,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
         // point and the incoming wavevector (the parent's own, unchanged in
         // flat spacetime) ----
         uint64_t smask = __ballot(scat);
-        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, ev_rng, ph.n_sc + 1, zs);
+        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, ev_rng, ph.n_sc + 1, ph.ev, zs);
     }
     ev_flush(L, ev);
     if constexpr (BATCHED) {
@@ -951,20 +1018,6 @@ GM_D void for_events_grouped(const TArgs &L, unsigned long long n, Ev ev)
     }
 }
 
-// Append a scattering event to the log (when one is set and has room).
-GM_D void log_event(const TArgs &A, const Rng &child, int z, double eps, double w_child, const double *x)
-{
-    unsigned long long i = atomicAdd(A.evlog_n, 1ull);
-    if (i >= A.evlog_cap) return;
-    EventRec &e = A.evlog[i];
-    e.s0 = child.s0; e.s1 = child.s1; e.s2 = child.s2;
-    e.zone = z;
-    e.eps = eps;
-    e.w_child = w_child;
-    e.x[0] = x[0]; e.x[1] = x[1]; e.x[2] = x[2];
-    e.pad = 0.0;
-}
-
 // ---------------------------------------------------------------------------
 // Scattering events -> child photons (Scattering section), one thread per
 // event of the generation just tracked.  Draws come from the child's stream
@@ -990,8 +1043,11 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_flat(TArgs L)
         int z = Q.zone[i];
         int n_sc = Q.n_sc[i];
         double wchild = Q.w[i];
-        Rng r = child_rng(Rng{Q.s0[i], Q.s1[i], Q.s2[i], 0u}, Q.blk[i], A.key0, A.key1);
+        const Rng r_par{Q.s0[i], Q.s1[i], Q.s2[i], 0u};
+        const uint32_t pev = Q.ev[i];
+        Rng r = child_rng(r_par, Q.blk[i], A.key0, A.key1);
         const Rng r_child = r;
+        uint32_t cev = kNoEvent;
         double g[4][4];
         Minkowski::gcov(x, g);
         double kc[4];
@@ -1011,7 +1067,9 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_flat(TArgs L)
 #pragma unroll
             for (int m = 0; m < 4; ++m) kc[m] = ks[m];
         }
-        if (A.evlog && z >= 0) log_event(A, r, z, -dot4(g, ks, A.zrec + (size_t)z * Z_STRIDE + Z_U0), wchild, x + 1);
+        if (A.evlog && z >= 0)
+            cev = log_event(A, r_child, &r_par, z, n_sc, -dot4(g, ks, A.zrec + (size_t)z * Z_STRIDE + Z_U0), wchild,
+                            x + 1, pev);
         lds_add(&B.ledger[L_E_COMPTON], wchild * (e_inf(g, kc) - e_inf(g, ks)) * kMeC2);
         lds_inc(&B.stats[S_SCATTER], 1);
         lds_inc(&B.stats[S_CHILDREN], 1);
@@ -1033,6 +1091,7 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_flat(TArgs L)
         O.x1[o] = x1;
         O.nua[o] = c.nua; O.nus[o] = c.nus; O.b[o] = c.b;
         O.blk[o] = r.block;
+        O.ev[o] = cev;
     };
     if constexpr (BATCHED) {
         for_events_grouped(L, n, event);
@@ -1042,6 +1101,19 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_flat(TArgs L)
             event(i, i);
     }
     lds_flush_all(L, lds, stride);
+}
+
+// Scores of one generation's records reach their parents' records
+// (records [lo, hi) of one track call; launched from the highest generation
+// down, so a record's score is complete when it is passed on).
+__global__ __launch_bounds__(256) void score_propagate_kernel(EventRec *ev, unsigned long long lo,
+                                                              unsigned long long hi, int gen)
+{
+    for (unsigned long long i = lo + (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        const EventRec &e = ev[i];
+        if (e.gen == gen && e.parent != kNoEvent && e.score != 0.0) atomicAdd(&ev[e.parent].score, e.score);
+    }
 }
 
 }  // namespace gm

@@ -35,6 +35,7 @@ struct PhotonK {
     double acc_edrift;             // sum of w * (change of e_inf) along steps
     Rng rng;
     int n_sc, inst;
+    uint32_t ev;                   // event-log record that created the photon
     int zone_end;                  // zone of the end of the step that found a scattering
     uint32_t steps, vit;
     int ncoef;                     // opacity evaluations (one per iteration)
@@ -52,6 +53,7 @@ GM_D void load_photon_ks(const PhotonQ &Q, unsigned long long i, PhotonK &ph)
     ph.rng = Rng{Q.s0[i], Q.s1[i], Q.s2[i], Q.blk[i]};
     ph.n_sc = Q.n_sc[i];
     ph.inst = Q.inst[i];
+    ph.ev = Q.ev[i];
     ph.steps = 0;
     ph.vit = 0;
     ph.ncoef = 0;
@@ -90,10 +92,11 @@ GM_D void finish_ks(const TArgs &A, BlockAcc &B, const PhotonK &ph, int kind)
             ith = max(0, min((int)floor(th * A.n_theta / kPi), A.n_theta - 1));
             inu = (int)fi;
             double E = ph.w * e;
-            double *bin = B.spec + ((size_t)ith * A.n_nu + inu) * 3;
+            double *bin = (B.spec ? B.spec : A.spec) + ((size_t)ith * A.n_nu + inu) * 3;
             lds_add(&bin[0], E);
             lds_add(&bin[1], E * E);
             lds_add(&bin[2], 1.0);
+            score_escape(A, ph.ev, ith, inu, E);
         }
     }
     if (ph.acc_wabs != 0.0) { lds_add(&B.ledger[L_W_ABS], ph.acc_wabs); lds_add(&B.ledger[L_E_ABS], ph.acc_eabs * kMeC2); }
@@ -299,7 +302,8 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                 // ---- optical depths by the trapezoid rule ----
                 double tau_a = 0.5 * (ph.nua + c1.nua) * A.C * dl;
                 double tau_s = A.scattering ? 0.5 * (ph.nus + c1.nus) * A.C * dl : 0.0;
-                double b = c1.vacuum ? ph.b : c1.b;
+                const double bf = c1.vacuum ? ph.b : c1.b;
+                const double b = step_bias(A, ph.w, bf);
                 const double e_old = ph.e;
                 if (A.scattering && ph.n_sc < A.n_sc_max && b * tau_s > ph.x1) {
                     // ---- scattering inside the step, at the fraction f: absorb
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                     for (int m = 0; m < 3; ++m) ph.x[m] = P[m];
 #pragma unroll
                     for (int m = 0; m < 4; ++m) { ph.k[m] = kn[m]; ph.a[m] = an[m]; }
-                    ph.nua = c1.nua; ph.nus = c1.nus; ph.b = b;
+                    ph.nua = c1.nua; ph.nus = c1.nus; ph.b = bf;
                     ph.r = K.r;
                     ph.e = e_here;
                     ph.acc_edrift += ph.w * (e_here - e_old);
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
         // ---- scattering events (the parent now sits at the scattering
         // point with the wavevector it scattered) ----
         uint64_t smask = __ballot(scat);
-        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, ev_rng, ph.n_sc + 1, zs);
+        if (smask) ev_push(L, ev, smask, scat, ph.inst, ph.x, ph.k, wchild, ev_rng, ph.n_sc + 1, ph.ev, zs);
     }
     ev_flush(L, ev);
     if constexpr (BATCHED) {
@@ -428,8 +432,11 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_ks(TArgs L)
         int z = Q.zone[i];
         int n_sc = Q.n_sc[i];
         double wchild = Q.w[i];
-        Rng r = child_rng(Rng{Q.s0[i], Q.s1[i], Q.s2[i], 0u}, Q.blk[i], A.key0, A.key1);
+        const Rng r_par{Q.s0[i], Q.s1[i], Q.s2[i], 0u};
+        const uint32_t pev = Q.ev[i];
+        Rng r = child_rng(r_par, Q.blk[i], A.key0, A.key1);
         const Rng r_child = r;
+        uint32_t cev = kNoEvent;
         KMetric K;
         kerr_metric<false>(A.a_spin, A.h_slope, Q.x[0][i], Q.x[1][i], K);
         double g[4][4];
@@ -442,7 +449,7 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_ks(TArgs L)
             double eps = scatter_tetrad(g, u, bh, has_b, ks, e);
             if (A.evlog) {
                 double xe[3] = {Q.x[0][i], Q.x[1][i], Q.x[2][i]};
-                log_event(A, r, z, eps, wchild, xe);
+                cev = log_event(A, r_child, &r_par, z, n_sc, eps, wchild, xe, pev);
             }
             double kf[4];
             ScatterCount cnt{0, 0};
@@ -474,6 +481,7 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_ks(TArgs L)
         O.wb[o] = wchild;
         O.x1[o] = x1;
         O.blk[o] = r.block;
+        O.ev[o] = cev;
     };
     if constexpr (BATCHED) {
         for_events_grouped(L, n, event);

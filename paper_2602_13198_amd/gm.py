@@ -35,11 +35,15 @@ TRACE_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("n_sc", "<
                         ("x", "<f8", 4), ("k", "<f8", 4)])
 TRACE_BYTES = 112
 
-EVENT_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("zone", "<i4"),
-                        ("eps", "<f8"), ("w_child", "<f8"), ("x", "<f8", 3), ("pad", "<f8")])
-EVENT_BYTES = 64
+EVENT_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("p0", "<u4"), ("p1", "<u4"),
+                        ("p2", "<u4"), ("zone", "<i4"), ("gen", "<i4"), ("parent", "<u4"), ("pad", "<u4"),
+                        ("eps", "<f8"), ("w", "<f8"), ("score", "<f8"), ("x", "<f8", 3)])
+EVENT_BYTES = 88
+assert EVENT_DTYPE.itemsize == EVENT_BYTES
+NO_EVENT = 0xFFFFFFFF
 MLP_PARAMS = 4738
-BIAS_LEARNED = 3
+BIAS_CONST, BIAS_THETA2, BIAS_GEN2, BIAS_TABLE, BIAS_WINDOW = 0, 1, 2, 3, 4
+BIAS_LEARNED = BIAS_TABLE
 PRECISION_F64, PRECISION_F32_EMISSIVITY = 0, 1
 
 # Every function the header declares (checked by the CPU symbol test).
@@ -50,7 +54,8 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_set_bias_table",
            "gm_set_event_log", "gm_event_count", "gm_set_batch",
            "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
-           "gm_queue_stats"]
+           "gm_queue_stats", "gm_set_emission_table", "gm_set_score_weights", "gm_set_tally_mode",
+           "gm_mlp_set_loss"]
 
 
 class GmGrid(C.Structure):
@@ -113,7 +118,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_mlp_grad": (i, [vp, vp, vp, vp, C.c_int64, vp, vp]),
         "gm_mlp_train_step": (i, [vp, vp, vp, vp, C.c_int64, C.c_float, vp]),
         "gm_set_bias_table": (i, [vp, i, dp, i, C.c_double, C.c_double]),
-        "gm_set_event_log": (i, [vp, vp, u64]),
+        "gm_set_event_log": (i, [vp, vp, u64, u64]),
+        "gm_set_emission_table": (i, [vp, i, dp, i, C.c_double, C.c_double]),
+        "gm_set_score_weights": (i, [vp, i, dp, i]),
+        "gm_set_tally_mode": (i, [vp, i]),
+        "gm_mlp_set_loss": (i, [vp, i]),
         "gm_event_count": (i, [vp, C.POINTER(C.c_uint64)]),
         "gm_set_batch": (i, [vp, i]),
         "gm_set_instance_bias": (i, [vp, i, i, C.c_double, C.c_double]),
@@ -219,6 +228,18 @@ class Context:
         _check(load_library().gm_load_zones(self._h, int(instance), C.byref(G), C.byref(Z)))
         self.shapes[instance] = int(np.prod(wl.grid["n"]))
 
+    def load_zones_device(self, grid: dict, n_e, theta_e, B, ucon, bcon, instance: int = 0):
+        """gm_load_zones with the zone arrays in device memory (copied to
+        float64 cuda tensors first when given as host arrays)."""
+        dev = "cuda:%d" % self.device
+        ts = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(dev) if not torch.is_tensor(a)
+              else a.to(device=dev, dtype=torch.float64).contiguous()
+              for a in (n_e, theta_e, B, ucon, bcon)]
+        Z = GmZones(1, *[t.data_ptr() for t in ts])
+        G = grid_struct(grid)
+        _check(load_library().gm_load_zones(self._h, int(instance), C.byref(G), C.byref(Z)))
+        self.shapes[instance] = int(np.prod(grid["n"]))
+
     def make_superphotons(self, emit: dict, instance: int = 0, sync: bool = True) -> int | None:
         P = emit_struct(emit)
         self.n_wnodes = P.n_wnodes
@@ -269,6 +290,24 @@ class Context:
                                   device="cuda:%d" % self.device)
         _check(load_library().gm_set_trace(self._h, C.c_void_p(self._trace.data_ptr()), int(capacity)))
 
+    def trace_count(self) -> int:
+        """Finished photons counted by the trace (also those past its capacity)."""
+        n = C.c_uint64(0)
+        _check(load_library().gm_trace_count(self._h, C.byref(n)))
+        return int(n.value)
+
+    def read_trace_subset(self, keys) -> np.ndarray:
+        """Trace records whose stream (s0 | s1 << 32) is in `keys`, selected
+        on the device (for traces too large to copy whole)."""
+        cap = self._trace.numel() // TRACE_BYTES
+        m = min(self.trace_count(), cap)
+        rec = self._trace[: m * TRACE_BYTES].view(m, TRACE_BYTES)
+        w = rec.view(torch.int32)[:, :2].to(torch.int64)
+        k = (w[:, 0] & 0xFFFFFFFF) | (w[:, 1] << 32)
+        want = torch.as_tensor(np.asarray(keys, dtype=np.uint64).view(np.int64), device=rec.device)
+        sel = rec[torch.isin(k, want)]
+        return sel.cpu().numpy().reshape(-1).view(TRACE_DTYPE).copy()
+
     def read_trace(self) -> np.ndarray:
         n = C.c_uint64(0)
         _check(load_library().gm_trace_count(self._h, C.byref(n)))
@@ -277,14 +316,17 @@ class Context:
         raw = self._trace[: m * TRACE_BYTES].cpu().numpy()
         return raw.view(TRACE_DTYPE).copy()
 
-    def set_event_log(self, capacity: int):
+    def set_event_log(self, capacity: int, root_stride: int = 0):
+        """Event records of scatterings, and of the emission of every
+        root_stride-th root (0: none), into a device buffer of `capacity`."""
         if capacity <= 0:
             self._evlog = None
-            _check(load_library().gm_set_event_log(self._h, None, 0))
+            _check(load_library().gm_set_event_log(self._h, None, 0, 0))
             return
         self._evlog = torch.empty(capacity * EVENT_BYTES, dtype=torch.uint8,
                                   device="cuda:%d" % self.device)
-        _check(load_library().gm_set_event_log(self._h, C.c_void_p(self._evlog.data_ptr()), int(capacity)))
+        _check(load_library().gm_set_event_log(self._h, C.c_void_p(self._evlog.data_ptr()), int(capacity),
+                                               int(root_stride)))
 
     def read_event_log(self) -> np.ndarray:
         n = C.c_uint64(0)
@@ -299,6 +341,10 @@ class Context:
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.size == MLP_PARAMS
         _check(load_library().gm_mlp_set_params(self._h, C.c_void_p(p.ctypes.data)))
+
+    def mlp_set_loss(self, kind: int):
+        """0: weighted squared error; 1: log-link Poisson deviance."""
+        _check(load_library().gm_mlp_set_loss(self._h, int(kind)))
 
     def mlp_get_params(self) -> np.ndarray:
         p = np.zeros(MLP_PARAMS, np.float32)
@@ -342,6 +388,27 @@ class Context:
         t = np.ascontiguousarray(ln_b, dtype=np.float64)
         _check(load_library().gm_set_bias_table(self._h, int(instance), _dp(t), int(t.shape[1]),
                                                 float(ln_eps_lo), float(ln_eps_hi)))
+
+    def set_emission_table(self, instance: int, table, ln_nu_lo: float = 0.0, ln_nu_hi: float = 1.0):
+        """Per-zone emission modulation [nz][n] in ln nu (None removes it)."""
+        if table is None:
+            _check(load_library().gm_set_emission_table(self._h, int(instance), None, 0, 0.0, 0.0))
+            return
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        _check(load_library().gm_set_emission_table(self._h, int(instance), _dp(t), int(t.shape[1]),
+                                                    float(ln_nu_lo), float(ln_nu_hi)))
+
+    def set_score_weights(self, instance: int, sw):
+        """Score weights [n_theta][n_nu] of the event records (None: 1)."""
+        if sw is None:
+            _check(load_library().gm_set_score_weights(self._h, int(instance), None, 0))
+            return
+        a = np.ascontiguousarray(sw, dtype=np.float64).reshape(-1)
+        _check(load_library().gm_set_score_weights(self._h, int(instance), _dp(a), int(a.size)))
+
+    def set_tally_mode(self, mode: int):
+        """0 automatic, 1 per-block LDS tallies, 2 direct HBM tallies."""
+        _check(load_library().gm_set_tally_mode(self._h, int(mode)))
 
     def sigma_hot_table(self) -> np.ndarray:
         t = np.zeros((64, 256))

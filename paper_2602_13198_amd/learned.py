@@ -100,7 +100,7 @@ def collect_records(ctx, wl, instance, rounds, seed0, track=None, bin_weight=Non
         ctx.set_trace(0)
         ctx.set_event_log(0)
         # children of fully absorbed parents carry weight 0: no information
-        ev = ev[ev["w_child"] > 0.0]
+        ev = ev[ev["w"] > 0.0]
         if len(ev) == 0:
             continue
         key_t = (tr["s0"].astype(np.uint64) << np.uint64(32)) | tr["s1"].astype(np.uint64)
@@ -118,11 +118,11 @@ def collect_records(ctx, wl, instance, rounds, seed0, track=None, bin_weight=Non
         e_esc = nu_esc / M_E_C2_OVER_H
         with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
             if bin_weight is None:
-                val = np.where(esc, rec["w_end"] * e_esc / (ev["w_child"] * ev["eps"]), 0.0)
+                val = np.where(esc, rec["w_end"] * e_esc / (ev["w"] * ev["eps"]), 0.0)
                 floor = 1e-3
             else:
                 bw = np.where(esc, bin_weight[np.clip(rec["i_theta"], 0, None), np.clip(rec["i_nu"], 0, None)], 0.0)
-                val = np.where(esc, rec["w_end"] / ev["w_child"] * e_esc * bw, 0.0)
+                val = np.where(esc, rec["w_end"] / ev["w"] * e_esc * bw, 0.0)
                 nzv = val[(val > 0) & np.isfinite(val)]
                 floor = 1e-3 * (np.median(nzv) if len(nzv) else 1.0)
             T = np.stack([np.log(val + floor), esc.astype(float)], axis=1)

@@ -18,6 +18,11 @@ Workloads
   GRMHD test section (that snapshot is not available): log-normal density and
   internal-energy perturbations, a poloidal single-loop field at a fixed
   gas-to-magnetic pressure ratio, and R-beta electron temperatures.
+* ``corona_torus`` -- the torus on a 3-D grid under a hot, field-free
+  scattering corona (n_e falling as 1/r, radial Thomson depth 0.1).
+* ``survey`` -- many 3-D tori differing in spin, electron-temperature ratio,
+  density scale and superphoton count (batched runs of the paper's
+  implementation section).
 """
 from __future__ import annotations
 
@@ -283,4 +288,98 @@ def torus(n1=256, n2=128, n3=1, a=0.9375, h_slope=0.3, r_in=6.0, r_max=12.0, gam
     tk.update(track_kw)
     return Workload(name, grid, n_e.reshape(-1), theta_e.reshape(-1), B.reshape(-1), ucon, bcon,
                     emit, default_track(**tk),
-                    meta=dict(l=l, rho_unit=rho_unit, M_unit=M_unit, r_h=rh))
+                    meta=dict(l=l, rho_unit=rho_unit, M_unit=M_unit, r_h=rh, R_high=R_high))
+
+
+def normal_observer(grid: dict):
+    """Direction of the normal observer's 4-velocity in every zone of a
+    modified Kerr-Schild grid: u^mu proportional to -g^{mu t} =
+    (1 + 2r/Sigma, -2/Sigma, 0, 0) in (t, ln r, x2, phi), Sigma = r^2 +
+    a^2 cos^2 theta -- timelike everywhere, inside the ergosphere too
+    (consumers normalise it with their own metric)."""
+    n1, n2, n3 = grid["n"]
+    a, hs = grid["a_spin"], grid["h_slope"]
+    x1 = grid["x_start"][0] + (np.arange(n1) + 0.5) * grid["dx"][0]
+    x2 = grid["x_start"][1] + (np.arange(n2) + 0.5) * grid["dx"][1]
+    r = np.exp(x1)[:, None]
+    th = (np.pi * x2 + 0.5 * (1 - hs) * np.sin(2 * np.pi * x2))[None, :]
+    sig = r * r + a * a * np.cos(th) ** 2
+    u0 = np.repeat((1.0 + 2.0 * r / sig)[:, :, None], n3, axis=2).reshape(-1)
+    u1 = np.repeat((-2.0 / sig)[:, :, None], n3, axis=2).reshape(-1)
+    return u0, u1
+
+
+def corona_torus(n1=192, n2=96, n3=96, a=0.9375, R_high=40.0, tau_corona=0.1, theta_corona=1.0,
+                 r_corona=40.0, n_target=1e8, seed=5, bias_value=10.0, name="corona_torus", **kw) -> Workload:
+    """The 3-D torus (3-D log-normal perturbations) under a scattering
+    corona: every zone the torus leaves empty with r_h < r < r_corona holds
+    electrons at n_e = n_0 r_g / r, Theta_e = theta_corona, no field (a pure
+    scatterer, no emission), moving with the normal observer; n_0 sets the
+    radial Thomson depth, n_0 sigma_T r_g ln(r_corona / r_h) = tau_corona.
+    The torus emits synchrotron photons that the corona Compton-scatters
+    into bands the torus does not reach.  Transport: constant bias b =
+    bias_value (1 / tau_corona), four scattering generations."""
+    kw.setdefault("step_h", 0.5)
+    wl = torus(n1=n1, n2=n2, n3=n3, a=a, R_high=R_high, n_target=n_target, seed=seed, name=name,
+               bias_mode=BIAS_CONST, bias_value=bias_value, **kw)
+    g = wl.grid
+    rh = wl.meta["r_h"]
+    L = g["L_unit_cm"]
+    x1 = g["x_start"][0] + (np.arange(n1) + 0.5) * g["dx"][0]
+    r = np.repeat(np.exp(x1), n2 * n3)
+    n0 = tau_corona / (SIGMA_T * L * math.log(r_corona / rh))
+    cor = (wl.n_e <= 0.0) & (r > rh) & (r < r_corona)
+    n_e = np.where(cor, n0 / r, wl.n_e)
+    theta_e = np.where(cor, float(theta_corona), wl.theta_e)
+    B = np.where(cor, 0.0, wl.B)
+    u0, u1 = normal_observer(g)
+    ucon = wl.ucon.copy()
+    ucon[0] = np.where(cor, u0, ucon[0])
+    ucon[1] = np.where(cor, u1, ucon[1])
+    ucon[3] = np.where(cor, 0.0, ucon[3])
+    meta = dict(wl.meta, n0=n0, r_corona=r_corona, tau_corona=tau_corona, theta_corona=theta_corona,
+                corona=cor)
+    return Workload(name, g, n_e, theta_e, B, ucon, wl.bcon, wl.emit, wl.track, meta)
+
+
+SURVEY_SPINS = (-0.5, 0.0, 0.5, 0.9375)
+SURVEY_R_HIGH = (1.0, 10.0, 40.0, 160.0)
+# torus radii (r_in, r_max) per spin: with r_in = 6 a retrograde a = -0.5
+# torus is empty (its ISCO lies at 7.6)
+SURVEY_RADII = {-0.5: (10.0, 20.0), 0.0: (8.0, 16.0), 0.5: (7.0, 14.0), 0.9375: (6.0, 12.0)}
+
+
+def survey(n1=192, n2=96, n3=96, n_draw=4, M_c=1e27, ns_lo=1e5, ns_hi=1e7, seed=4, step_h=0.5,
+           **track_kw):
+    """Batched survey: for every spin in SURVEY_SPINS and R_high in
+    SURVEY_R_HIGH, n_draw density scales M_unit log-uniform on
+    [M_c / 10, 10 M_c] (4 x 4 x 4 = 64 instances by default), each with its
+    own N_s log-uniform on [ns_lo, ns_hi] and its own emission seed.  One
+    torus structure per spin (shared perturbations); R_high and M_unit only
+    rescale it (Theta_e through R-beta, n_e by M_unit, B by sqrt(M_unit)),
+    so the instances are built without recomputing the torus.  Returns the
+    list of workloads, instance i at emit["instance"] = i."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    out = []
+    i = 0
+    for a in SURVEY_SPINS:
+        rin, rmax = SURVEY_RADII[a]
+        base = torus(n1=n1, n2=n2, n3=n3, a=a, r_in=rin, r_max=rmax, R_high=1.0, M_unit=1.0,
+                     step_h=step_h, **track_kw)
+        beta = 100.0
+        for rh_ in SURVEY_R_HIGH:
+            Rf = (rh_ * beta ** 2 + 1.0) / (1 + beta ** 2)
+            R1 = (1.0 * beta ** 2 + 1.0) / (1 + beta ** 2)
+            # Theta_e scales as 1/(1 + R) before the floor; the floor is re-applied
+            th_raw = np.where(base.n_e > 0, base.theta_e * (1 + R1) / (1 + Rf), 0.0)
+            theta_e = np.where(base.n_e > 0, np.maximum(th_raw, 1e-2), 0.0)
+            for _ in range(n_draw):
+                Mu = M_c * 10.0 ** rng.uniform(-1.0, 1.0)
+                ns = 10.0 ** rng.uniform(math.log10(ns_lo), math.log10(ns_hi))
+                emit = dict(base.emit, n_target=float(ns), seed=int(1000 + i), instance=i)
+                wl = Workload("survey_%d" % i, base.grid, base.n_e * Mu, theta_e, base.B * math.sqrt(Mu),
+                              base.ucon, base.bcon, emit, dict(base.track),
+                              meta=dict(a=a, R_high=rh_, M_unit=Mu, N_s=ns, r_h=base.meta["r_h"]))
+                out.append(wl)
+                i += 1
+    return out

@@ -1,18 +1,21 @@
 """The FP32 precision form (emissivity, Kirchhoff absorption and the hot
 cross section in single precision; geodesics, step control, optical-depth
-sums, weights, sampling and tallies in double) against the FP64 path on the
-same seeded inputs.
+sums, weights, sampling and tallies in double) against the FP64 oracle and
+against the library's own FP64 path on the same seeded inputs.
 
 Same seed, so the photon histories coincide except where a threshold test
-(scattering, roulette) lands within the FP32 rounding of the opacities;
-per-bin spectra are compared in bins holding >= 1e3 superphotons: the
-relative difference must stay within 3 statistical standard deviations of
-the bin plus 1e-3, and its maximum is printed (and recorded with the
-workload in the design notes)."""
+(scattering, roulette) lands within the FP32 rounding of the opacities.
+Against the oracle: per-bin relative error in bins holding >= 1e3
+superphotons within 1e-3 for the same seed (the target of the precision
+form is 1 %), and chi^2/dof <= 1.2 (the statistical parity measure, with
+the bins' own variances) for a different seed; on the full Kerr torus the
+oracle recomputes sampled root families, whose histories must agree with
+the FP32 ones to the FP32 rounding of the optical depths.  The measured
+figures are printed."""
 import numpy as np
 import pytest
 
-from _parity import compare_traces, ledger_residuals
+from _parity import compare_traces, describe, ledger_residuals
 from paper_2602_13198_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -81,3 +84,71 @@ def test_f32_histories_mostly_identical(gm):
     n, bad = compare_traces(t32, t64, rtol=1e-4, atol_x=1e-12)
     assert n > 10000
     assert len(bad) <= 1e-3 * n
+
+
+def chi2_dof(a, b, min_n=1000):
+    """Statistical parity: sum (S1_a - S1_b)^2 / (S2_a + S2_b) over bins with
+    at least min_n superphotons on both sides, per bin."""
+    use = (a[..., 2] >= min_n) & (b[..., 2] >= min_n)
+    d = a[..., 0][use] - b[..., 0][use]
+    v = a[..., 1][use] + b[..., 1][use]
+    return float((d * d / v).sum() / max(1, use.sum())), int(use.sum())
+
+
+@pytest.mark.parametrize("wl", [
+    W.thin_sphere(n_target=1e5, seed=0),
+    W.scattering_sphere(0.1, n_target=1e6, seed=0),
+], ids=["thin_1e5", "scat_0.1_1e6"])
+def test_f32_spectrum_against_oracle(gm, oracle_lib, wl):
+    s32, l32, st32, _ = run(gm, wl, 1)
+    ores, _ = oracle_lib.run(wl)
+    so = ores.spectrum
+    use = so[..., 2] >= 1000
+    assert use.sum() >= 10
+    rel = np.abs(s32[..., 0][use] - so[..., 0][use]) / so[..., 0][use]
+    c2, nb = chi2_dof(s32, so)
+    print("%s FP32 vs oracle, same seed: %d bins >= 1e3, per-bin relative error max %.3e median %.3e, "
+          "chi2/dof %.3e" % (wl.name, use.sum(), rel.max(), np.median(rel), c2))
+    assert rel.max() <= 1e-3
+    assert c2 <= 1.2
+    # another seed: statistical agreement only
+    s32b, _, _, _ = run(gm, wl.with_emit(seed=wl.emit["seed"] + 1000), 1)
+    c2b, nbb = chi2_dof(s32b, so)
+    print("%s FP32 (seed +1000) vs oracle: chi2/dof %.3f over %d bins" % (wl.name, c2b, nbb))
+    assert nbb >= 10 and c2b <= 1.2
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["f64", "f32_emissivity"])
+def test_full_torus_sampled_families(gm, oracle_lib, precision):
+    """The Kerr torus at full size (256 x 128 zones, N_s = 1e7): every photon
+    traced on the GPU, the oracle recomputing sampled root families with
+    all their descendants.  FP64 histories agree within 1e-10; FP32 ones
+    within 1e-4 (the FP32 rounding of the optical depths)."""
+    wl = W.torus(n_target=1e7, seed=3)
+    c = gm.Context(0)
+    c.load_zones(wl)
+    n = c.make_superphotons(wl.emit)
+    c.set_trace(12_000_000)
+    st = c.track_scatter(dict(wl.track, precision=precision))
+    tr = c.read_trace()
+    _, led = c.read_spectrum()
+    c.close()
+    assert len(tr) == st[0] + st[1]
+    o = oracle_lib.Oracle()
+    o.load_zones(wl)
+    assert o.make_superphotons(wl.emit) == n
+    rng = np.random.default_rng(5)
+    starts = np.sort(rng.choice(n - 20, 10, replace=False))
+    ora = np.concatenate([o.track_scatter(wl.track, int(s), int(s) + 20, trace_cap=100000) for s in starts])
+    o.close()
+
+    def key(a):
+        return (a["s0"].astype(np.uint64) << np.uint64(32)) | a["s1"].astype(np.uint64)
+    sub = tr[np.isin(key(tr), key(ora))]
+    rtol = 1e-10 if precision == 0 else 1e-4
+    m, bad = compare_traces(sub, ora, rtol=rtol, atol_x=rtol, subset=True)
+    print("torus 256x128 %s: %d sampled photons, %d differ" % (("f64", "f32")[precision], m, len(bad)))
+    assert m == len(ora) and m >= 200
+    assert len(bad) <= max(1, (1e-3 if precision == 0 else 1e-2) * m), describe(sub, ora, bad)
+    wr, er = ledger_residuals(led)
+    assert abs(wr) < 1e-12 and abs(er) < 1e-12

@@ -22,6 +22,53 @@ def test_gradient_matches_finite_differences():
         assert abs(fd - g[i]) <= 1e-7 + 1e-6 * abs(g[i]), (i, fd, g[i])
 
 
+def test_poisson_gradient_matches_finite_differences():
+    """The log-link Poisson deviance e^y - T y, targets with many zeros."""
+    rng = np.random.default_rng(2)
+    p = M.init(5) + 0.01 * rng.standard_normal(M.N_PARAMS)
+    X = rng.standard_normal((29, 8))
+    T = np.where(rng.uniform(size=(29, 2)) < 0.6, 0.0, rng.exponential(2.0, (29, 2)))
+    C = rng.uniform(0.1, 1.0, (29, 2)) / 29
+    g, L = M.grad(p, X, T, C, kind=M.POISSON)
+    assert abs(L - M.loss(p, X, T, C, kind=M.POISSON)) < 1e-14 * max(1.0, abs(L))
+    h = 1e-6
+    for i in rng.choice(M.N_PARAMS, 60, replace=False):
+        e = np.zeros(M.N_PARAMS)
+        e[i] = h
+        fd = (M.loss(p + e, X, T, C, M.POISSON) - M.loss(p - e, X, T, C, M.POISSON)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 + 1e-6 * abs(g[i]), (i, fd, g[i])
+
+
+def test_poisson_minimiser_is_log_mean():
+    """A bias-only output trained on zero-inflated targets goes to ln E[T]
+    (the squared error on ln(T + floor) would not)."""
+    rng = np.random.default_rng(3)
+    T = np.where(rng.uniform(size=(4000, 1)) < 0.9, 0.0, rng.exponential(5.0, (4000, 1)))
+    y = 0.0
+    for _ in range(2000):
+        y -= 0.5 * np.mean(np.exp(y) - T)
+    assert abs(y - np.log(T.mean())) < 1e-9
+
+
+def test_bf16_gradient_reduces_to_exact():
+    """The BF16-operand gradient is the exact one when every operand is
+    representable in BF16 (rounding is then the identity), and within the
+    BF16 rounding (2^-8 relative per operand) of it otherwise."""
+    rng = np.random.default_rng(4)
+    p = M.bf16(M.init(6))
+    X = np.zeros((1, 8))
+    X[0, :6] = M.bf16(rng.standard_normal(6))
+    T = rng.standard_normal((1, 2))
+    C = np.ones((1, 2))
+    g, L = M.grad(p, X, T, C)
+    gb, Lb = M.grad_bf16(p, X, T, C)
+    rel = np.linalg.norm(gb - g) / np.linalg.norm(g)
+    assert 0 < rel < 2e-2
+    # identity rounding: bitwise the exact code path
+    g1, _ = M.grad(p, X, T, C, rnd=lambda a: a)
+    np.testing.assert_array_equal(g1, g)
+
+
 def test_parameter_layout():
     p = np.arange(M.N_PARAMS, dtype=float)
     d = M.unpack(p)
