@@ -188,6 +188,11 @@ const char *gm_last_error(void);
  * instance held; its tallies are kept. */
 gm_status gm_load_zones(gm_ctx *ctx, int instance, const gm_grid *grid, const gm_zones *zones);
 
+/* Free everything an instance holds (zones, emission tables, tallies,
+ * bias and emission tables, score weights); the instance can be loaded
+ * again.  Synchronises. */
+gm_status gm_unload_zones(gm_ctx *ctx, int instance);
+
 /* Superphoton generation (Creation of superphotons and Sampling procedure
  * sections): builds the weight table w(nu) (eq:weight_calc), draws each
  * zone's superphoton count by stochastic rounding of its expectation, and

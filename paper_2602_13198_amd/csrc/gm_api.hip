@@ -391,6 +391,23 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
     return GM_OK;
 }
 
+gm_status gm_unload_zones(gm_ctx *c, int instance)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    Instance &I = c->inst[instance];
+    I.zrec.release(); I.zrec32.release(); I.vol.release(); I.emits.release(); I.nu_nodes.release();
+    I.w_node.release(); I.ln_w.release(); I.nbar.release(); I.fmax.release();
+    I.partial.release(); I.count.release(); I.zone_of_root.release(); I.offset.release();
+    I.tile.release(); I.roots.release(); I.spec.release(); I.ledger.release(); I.stats.release();
+    I.lnb.release(); I.mtab.release(); I.sw.release();
+    I = Instance();
+    return GM_OK;
+}
+
 static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint64_t *n_made)
 {
     Instance &I = c->inst[instance];

@@ -247,9 +247,13 @@ __global__ __launch_bounds__(64 * kMlpGradWaves) void mlp_grad_kernel(MlpArgs M)
                 for (int j = 0; j < 4; ++j) atomicAdd(&gacc[kW3 + (16 * mt + 4 * (l >> 4) + j) * kMlpOut + n], g[j]);
             }
         }
-        if (n < kMlpOut) {
+        {
+            // db3: the wave's four row groups summed by shuffles in a fixed
+            // order, then one addition per wave
             float s = dy[0] + dy[1] + dy[2] + dy[3];
-            atomicAdd(&gacc[kB3 + n], s);
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            if (l < kMlpOut) atomicAdd(&gacc[kB3 + l], s);
         }
         // dH2 [16 x 64] = dY [16 x 16] W3^T [16 x 64]; dZ2 = dH2 (1 - h2^2)
         bf16x4 ady = tile_load_A(dz1, 0);

@@ -45,6 +45,7 @@ MLP_PARAMS = 4738
 BIAS_CONST, BIAS_THETA2, BIAS_GEN2, BIAS_TABLE, BIAS_WINDOW = 0, 1, 2, 3, 4
 BIAS_LEARNED = BIAS_TABLE
 PRECISION_F64, PRECISION_F32_EMISSIVITY = 0, 1
+MLP_SQUARED, MLP_POISSON = 0, 1
 
 # Every function the header declares (checked by the CPU symbol test).
 EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make_superphotons",
@@ -55,7 +56,7 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_set_event_log", "gm_event_count", "gm_set_batch",
            "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
            "gm_queue_stats", "gm_set_emission_table", "gm_set_score_weights", "gm_set_tally_mode",
-           "gm_mlp_set_loss"]
+           "gm_mlp_set_loss", "gm_unload_zones"]
 
 
 class GmGrid(C.Structure):
@@ -123,6 +124,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_set_score_weights": (i, [vp, i, dp, i]),
         "gm_set_tally_mode": (i, [vp, i]),
         "gm_mlp_set_loss": (i, [vp, i]),
+        "gm_unload_zones": (i, [vp, i]),
         "gm_event_count": (i, [vp, C.POINTER(C.c_uint64)]),
         "gm_set_batch": (i, [vp, i]),
         "gm_set_instance_bias": (i, [vp, i, i, C.c_double, C.c_double]),
@@ -239,6 +241,11 @@ class Context:
         G = grid_struct(grid)
         _check(load_library().gm_load_zones(self._h, int(instance), C.byref(G), C.byref(Z)))
         self.shapes[instance] = int(np.prod(grid["n"]))
+
+    def unload(self, instance: int = 0):
+        """Free an instance's device memory."""
+        _check(load_library().gm_unload_zones(self._h, int(instance)))
+        self.shapes.pop(instance, None)
 
     def make_superphotons(self, emit: dict, instance: int = 0, sync: bool = True) -> int | None:
         P = emit_struct(emit)

@@ -27,11 +27,12 @@ def gm():
 
 
 def _key(a):
-    return (a["s0"].astype(np.uint64) << np.uint64(32)) | a["s1"].astype(np.uint64)
+    """Stream key s0 | s1 << 32 (as read_trace_subset selects)."""
+    return a["s0"].astype(np.uint64) | (a["s1"].astype(np.uint64) << np.uint64(32))
 
 
 def test_corona_same_seed(gm, oracle_lib):
-    wl = W.corona_torus(n1=48, n2=24, n3=24, n_target=3000, seed=61)
+    wl = W.corona_torus(n1=48, n2=24, n3=24, n_target=8000, seed=61)
     c = gm.Context(0)
     c.load_zones(wl)
     n = c.make_superphotons(wl.emit)

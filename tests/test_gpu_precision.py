@@ -96,9 +96,9 @@ def chi2_dof(a, b, min_n=1000):
 
 
 @pytest.mark.parametrize("wl", [
-    W.thin_sphere(n_target=1e5, seed=0),
+    W.thin_sphere(n_target=1e6, seed=0),
     W.scattering_sphere(0.1, n_target=1e6, seed=0),
-], ids=["thin_1e5", "scat_0.1_1e6"])
+], ids=["thin_1e6", "scat_0.1_1e6"])
 def test_f32_spectrum_against_oracle(gm, oracle_lib, wl):
     s32, l32, st32, _ = run(gm, wl, 1)
     ores, _ = oracle_lib.run(wl)
