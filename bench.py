@@ -367,6 +367,7 @@ def cpu_baseline(wl, n_roots=2000, target_s=20.0):
     t0 = time.perf_counter()
     n_all = o.make_superphotons(dict(wl.emit, seed=0))
     t_make = time.perf_counter() - t0
+    print("cpu baseline: oracle make %.1f s" % t_make, file=sys.stderr, flush=True)
     # the cross-section table: built once per process, outside the timing
     o.track_scatter(wl.track, 0, 0, n_threads=threads)
     o.read_spectrum(reset=True)
@@ -379,6 +380,7 @@ def cpu_baseline(wl, n_roots=2000, target_s=20.0):
         n_sp += int(r.stats[0] + r.stats[1])
         n_r += n_roots
         start += n_roots
+        print("cpu baseline: %d roots tracked, %.1f s" % (n_r, t_track), file=sys.stderr, flush=True)
     o.close()
     t_prorated = t_track + t_make * n_r / n_all
     return dict(value=n_sp / t_prorated, unit="superphotons/s", cores=threads, kind="oracle",
@@ -545,6 +547,7 @@ def main():
         from paper_2602_13198_amd import importance as IM
         out["time_to_1pct"] = IM.compare_forms(ctx, wl, 0, seeds=args.ttx_seeds, ref_rounds=args.ttx_ref_rounds,
                                                round_div=args.ttx_round_div, log=log)
+        print(json.dumps({"partial": True, "time_to_1pct": out["time_to_1pct"]}), file=sys.stderr, flush=True)
     if not args.no_forms:
         out["forms"]["flat_scattering_sphere"] = flat_sphere_form(ctx, 1)
         log("flat sphere done")

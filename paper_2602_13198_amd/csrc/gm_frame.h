@@ -33,6 +33,21 @@ GM_D double dot4(const double g[4][4], const double *a, const double *b)
     return s;
 }
 
+// Inner products with the metric at a point, without forming a 4x4 matrix
+// whose zeros would still be multiplied: flat (Cartesian Minkowski), and a
+// general matrix for the paths that hold one.
+struct GFlat {
+    GM_D double dot(const double *a, const double *b) const
+    {
+        return -a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+    }
+};
+
+struct GMat {
+    const double (*g)[4];
+    GM_D double dot(const double *a, const double *b) const { return dot4(g, a, b); }
+};
+
 GM_D double e_inf(const double g[4][4], const double *k)
 {
     return -(g[0][0] * k[0] + g[0][1] * k[1] + g[0][2] * k[2] + g[0][3] * k[3]);
@@ -50,15 +65,16 @@ enum { Z_U0 = 0, Z_B0 = 4, Z_A = 8, Z_NUC = 9, Z_TH = 10, Z_NE = 11, Z_LNTH = 12
 // in u) is normalised with the local metric, the field direction (in bh)
 // projected normal to u and normalised (absent when the zone has no field
 // or it is degenerate here).
-GM_D bool fluid_frame_vec(bool zone_has_b, const double g[4][4], double u[4], double bh[4])
+template <class G>
+GM_D bool fluid_frame_vec(bool zone_has_b, const G &gm, double u[4], double bh[4])
 {
-    double un = sqrt(-dot4(g, u, u));
+    double un = sqrt(-gm.dot(u, u));
 #pragma unroll
     for (int m = 0; m < 4; ++m) u[m] /= un;
-    double bu = dot4(g, bh, u);
+    double bu = gm.dot(bh, u);
 #pragma unroll
     for (int m = 0; m < 4; ++m) bh[m] += bu * u[m];
-    double bb = dot4(g, bh, bh);
+    double bb = gm.dot(bh, bh);
     bool has_b = (bb > 0.0) && zone_has_b;
     double inv = has_b ? 1.0 / sqrt(bb) : 0.0;
 #pragma unroll
@@ -67,11 +83,17 @@ GM_D bool fluid_frame_vec(bool zone_has_b, const double g[4][4], double u[4], do
 }
 
 // Same from a packed FP64 zone record.
-GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], double bh[4])
+template <class G>
+GM_D bool fluid_frame_m(const double *zr, const G &gm, double u[4], double bh[4])
 {
 #pragma unroll
     for (int m = 0; m < 4; ++m) { u[m] = zr[Z_U0 + m]; bh[m] = zr[Z_B0 + m]; }
-    return fluid_frame_vec(zr[Z_HASB] != 0.0, g, u, bh);
+    return fluid_frame_vec(zr[Z_HASB] != 0.0, gm, u, bh);
+}
+
+GM_D bool fluid_frame(const double *zr, const double g[4][4], double u[4], double bh[4])
+{
+    return fluid_frame_m(zr, GMat{g}, u, bh);
 }
 
 // Flat spacetime: the normalised vectors were stored by the zone preparation.

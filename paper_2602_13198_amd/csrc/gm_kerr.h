@@ -101,6 +101,17 @@ GM_HD void kerr_metric(double a, double hs, double x1, double x2, KMetric &K)
     K.u33 = 1.0 / (Sv * S2.v);
 }
 
+// g(a, b) from the seven non-zero components.
+struct GKerr {
+    const KMetric &K;
+    GM_HD double dot(const double *a, const double *b) const
+    {
+        return K.g00 * (a[0] * b[0]) + K.g01 * (a[0] * b[1] + a[1] * b[0]) + K.g03 * (a[0] * b[3] + a[3] * b[0])
+             + K.g11 * (a[1] * b[1]) + K.g13 * (a[1] * b[3] + a[3] * b[1]) + K.g22 * (a[2] * b[2])
+             + K.g33 * (a[3] * b[3]);
+    }
+};
+
 GM_HD void kerr_full(const KMetric &K, double g[4][4])
 {
     g[0][0] = K.g00; g[0][1] = K.g01; g[0][2] = 0.0; g[0][3] = K.g03;

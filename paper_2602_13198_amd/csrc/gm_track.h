@@ -421,10 +421,11 @@ GM_D double step_bias(const Args &A, double w, double bf)
 
 // Invariant absorption and scattering coefficients (nu alpha) at a point
 // (Absorption and Scattering sections): alpha = j / B_nu (Kirchhoff),
-// alpha_sc = n_e sigma_h; and the bias at that point.  g is the metric at
-// the point; FLAT zones carry their unit u and field direction already.
-template <bool FLAT, class Args>
-GM_D Coef coefficients_at64(const Args &A, int z, const double g[4][4], const double *k, int n_sc)
+// alpha_sc = n_e sigma_h; and the bias at that point.  gm gives inner
+// products with the metric at the point; FLAT zones carry their unit u and
+// field direction already.
+template <bool FLAT, class Args, class G>
+GM_D Coef coefficients_at64(const Args &A, int z, const G &gm, const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
@@ -444,13 +445,13 @@ GM_D Coef coefficients_at64(const Args &A, int z, const double g[4][4], const do
     if (!(ne > 0.0)) return c;
     c.vacuum = false;
     double u[4], bh[4];
-    bool has_b = FLAT ? fluid_frame_flat(zr, u, bh) : fluid_frame(zr, g, u, bh);
-    double ef = -dot4(g, k, u);
+    bool has_b = FLAT ? fluid_frame_flat(zr, u, bh) : fluid_frame_m(zr, gm, u, bh);
+    double ef = -gm.dot(k, u);
     double inv_ef = 1.0 / ef;
     double nuf = ef * (kMeC2 / kH);
     double Az = zr[Z_A];
     if (has_b && Az > 0.0) {
-        double cth = dot4(g, k, bh) * inv_ef;
+        double cth = gm.dot(k, bh) * inv_ef;
         cth = fmin(fmax(cth, -1.0), 1.0);
         double s2 = 1.0 - cth * cth;
         if (s2 > 0.0) {
@@ -471,8 +472,8 @@ GM_D Coef coefficients_at64(const Args &A, int z, const double g[4][4], const do
 
 // The same in the FP32 form: frame products in double, then emissivity,
 // absorption and the hot cross section as FP32 logarithms and one exp each.
-template <bool FLAT, class Args>
-GM_D Coef coefficients_at32(const Args &A, int z, const double g[4][4], const double *k, int n_sc)
+template <bool FLAT, class Args, class G>
+GM_D Coef coefficients_at32(const Args &A, int z, const G &gm, const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
@@ -484,12 +485,12 @@ GM_D Coef coefficients_at32(const Args &A, int z, const double g[4][4], const do
 #pragma unroll
     for (int m = 0; m < 4; ++m) { u[m] = (double)zf[F_U0 + m]; bh[m] = (double)zf[F_B0 + m]; }
     bool has_b = zf[F_HASB] != 0.0f;
-    if (!FLAT) has_b = fluid_frame_vec(has_b, g, u, bh);
-    double ef = -dot4(g, k, u);
+    if (!FLAT) has_b = fluid_frame_vec(has_b, gm, u, bh);
+    double ef = -gm.dot(k, u);
     float lnnu = __logf((float)(ef * (kMeC2 / kH)));
     float lnA = zf[F_LNA];
     if (has_b && lnA > -1e30f) {
-        double cth = fmin(fmax(dot4(g, k, bh) / ef, -1.0), 1.0);
+        double cth = fmin(fmax(gm.dot(k, bh) / ef, -1.0), 1.0);
         float s2 = (float)(1.0 - cth * cth);
         if (s2 > 0.0f) {
             float lns = 0.5f * __logf(s2);
@@ -505,19 +506,20 @@ GM_D Coef coefficients_at32(const Args &A, int z, const double g[4][4], const do
     return c;
 }
 
-template <bool FLAT, bool F32 = false, class Args>
-GM_D Coef coefficients_at(const Args &A, int z, const double g[4][4], const double *k, int n_sc)
+template <bool FLAT, bool F32 = false, class Args, class G>
+GM_D Coef coefficients_at(const Args &A, int z, const G &gm, const double *k, int n_sc)
 {
-    if constexpr (F32) return coefficients_at32<FLAT>(A, z, g, k, n_sc);
-    else return coefficients_at64<FLAT>(A, z, g, k, n_sc);
+    if constexpr (F32) return coefficients_at32<FLAT>(A, z, gm, k, n_sc);
+    else return coefficients_at64<FLAT>(A, z, gm, k, n_sc);
 }
 
+// Flat spacetime (Cartesian Minkowski metric).
 template <class M, bool F32 = false, class Args>
 GM_D Coef coefficients(const Args &A, int z, const double *x, const double *k, int n_sc)
 {
-    double g[4][4];
-    M::gcov(x, g);
-    return coefficients_at<true, F32>(A, z, g, k, n_sc);
+    static_assert(!M::kCurved, "the flat form");
+    (void)x;
+    return coefficients_at<true, F32>(A, z, GFlat{}, k, n_sc);
 }
 
 // ---------------------------------------------------------------------------

@@ -279,10 +279,8 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 #pragma unroll
                 for (int m = 0; m < 4; ++m) ph.k[m] = kn[m];
             }
-            double g[4][4];
-            kerr_full(K, g);
             const int zn = zone_ks(A, P[0], P[1], P[2]);
-            Coef c1 = coefficients_at<false, F32>(A, zn, g, kn, ph.n_sc);
+            Coef c1 = coefficients_at<false, F32>(A, zn, GKerr{K}, kn, ph.n_sc);
             ph.ncoef += 1;
             if (mode != MODE_STEP) {
                 // restart at the scattering point, or first evaluation of a

@@ -41,7 +41,7 @@ def test_traffic_is_scaled_by_the_copy(tmp_path, monkeypatch):
     assert d["copy_calibration"]["write_factor"] == pytest.approx(1.0)
     assert d["bytes_per_launch"] == pytest.approx(1024 * (200.0 * 2.0 + 100.0 * 1.0))
     assert bench.measured_traffic(bench.TRACK_KERNEL) == pytest.approx(d["bytes_per_launch"])
-    assert bench.measured_traffic(bench.track_variant(2, 1)) is None        # another variant
+    assert bench.measured_traffic(bench.track_variant(2, 64)) is None       # another variant
     d["kernel_source_hash"] = "0" * 16
     json.dump(d, open(bench.TRAFFIC_JSON, "w"))
     assert bench.measured_traffic(bench.TRACK_KERNEL) is None               # other sources
@@ -64,5 +64,15 @@ def test_issued_fp64_convention(tmp_path, monkeypatch):
 
 
 def test_variant_names_match_the_compiled_kernels():
-    assert bench.track_variant(2, 1) == "track_kernel_flat<2, false, false>"
-    assert bench.track_variant(3, 64) == "track_kernel_flat<3, false, true>"
+    assert bench.track_variant(2, 1) == "track_kernel_ks<2, false, false>"
+    assert bench.track_variant(3, 64, kerr=False) == "track_kernel_flat<3, false, true>"
+
+
+def test_kerr_flop_count_from_counters():
+    """The tracker's algorithmic work from the event counters: every point
+    (step or sub-step), corrector pass, split and load counted once."""
+    st = [0] * 33
+    st[bench.S["STEPS"]], st[bench.S["SCATTER"]], st[bench.S["VERLET_IT"]] = 1000, 10, 2500
+    st[bench.S["ROOTS"]], st[bench.S["CHILDREN"]] = 7, 3
+    P = bench.KS_FLOPS_PER
+    assert bench.ks_flops(st) == P["point"] * 1010 + P["corrector"] * 2500 + P["split"] * 10 + P["load"] * 10
