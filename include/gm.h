@@ -338,6 +338,22 @@ gm_status gm_mlp_set_loss(gm_ctx *ctx, int kind);
  * result does not depend on scheduling (bitwise).  Synchronises. */
 gm_status gm_mlp_grad(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
                       float *grad, float *loss);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * allocation): gm_mlp_grad without any allocation and without
+ * synchronisation.  X [n][8], T [n][2], C [n][2] are device buffers as for
+ * gm_mlp_grad; grad_loss is a caller-owned device buffer of
+ * GM_MLP_PARAMS + 1 floats that receives the gradient followed by the loss.
+ * The per-block partial gradients live in a fixed scratch array of 32 MiB
+ * that each GPU holds until the process ends, which limits n to
+ * GM_MLP_NOALLOC_MAX_ROWS (GM_EINVAL above it).  Every call on one GPU
+ * shares that array: calls that overlap in time on the same GPU (other
+ * streams, other contexts) race and give wrong results.  The work is queued
+ * on the context's stream; the result is ready when that stream reaches it. */
+#define GM_MLP_NOALLOC_MAX_ROWS 56640
+gm_status gm_mlp_grad_noalloc(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
+                              float *grad_loss);
+
 /* One Adam step (beta 0.9, 0.999, eps 1e-8) on the same loss with learning
  * rate lr; loss (host, may be NULL: no synchronisation) receives the loss
  * before the step. */

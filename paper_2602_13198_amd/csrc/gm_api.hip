@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,17 @@ static_assert(sizeof(TraceRec) == sizeof(gm_trace_rec), "trace record layout");
 static_assert(sizeof(TraceRec) == 112, "trace record layout");
 static_assert(sizeof(EventRec) == sizeof(gm_event_rec), "event record layout");
 static_assert(kMlpParams == GM_MLP_PARAMS, "network parameter count");
+
+// Scratch of the allocation-free gradient entry point (gm_mlp_grad_noalloc):
+// the per-block partial gradients, kMlpParams + 1 floats for every block of
+// kMlpGradRows rows.  Each GPU the library runs on holds one copy until the
+// process ends; host code reaches it only through the address returned by
+// hipGetSymbolAddress for that device.
+constexpr size_t kScratchFloats = (size_t)8 << 20;                    // 32 MiB
+constexpr long long kNoAllocMaxRows =
+    (long long)(kScratchFloats / (gm::kMlpParams + 1)) * gm::kMlpGradRows;
+static __device__ __align__(256) float scratch[kScratchFloats];
+static_assert(kNoAllocMaxRows == GM_MLP_NOALLOC_MAX_ROWS, "row limit of the public header");
 
 namespace {
 
@@ -161,11 +173,31 @@ struct gm_ctx {
     bool mlp_ready = false;
     long long mlp_t = 0;
     int mlp_loss = 0;
+    float *scratch = nullptr;                   // this device's copy of the scratch array
 };
 
 static gm_status set_device(gm_ctx *c)
 {
     HIPCHK(hipSetDevice(c->device));
+    return GM_OK;
+}
+
+// Device address of the scratch array on the current device `device`,
+// looked up once per device.
+static gm_status scratch_address(int device, float **out)
+{
+    static std::mutex mu;
+    static float *addr[256] = {};
+    if (device < 0 || device >= 256) return fail(GM_EINVAL, "device %d", device);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GM_EDEVICE, "scratch address on device %d: %s", device, hipGetErrorString(e));
+        addr[device] = (float *)p;
+    }
+    *out = addr[device];
     return GM_OK;
 }
 
@@ -240,6 +272,8 @@ gm_status gm_create(gm_ctx **out, int device, void *hip_stream)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return fail(GM_EDEVICE, "device properties"); }
     c->n_cu = prop.multiProcessorCount;
+    s = scratch_address(device, &c->scratch);
+    if (s != GM_OK) { delete c; return s; }
     s = build_tables(c);
     if (s == GM_OK && (c->ctr.ensure(2 * 32) != hipSuccess || c->flags.ensure(4) != hipSuccess ||
                        c->trace_n.ensure(1) != hipSuccess || c->evlog_n.ensure(1) != hipSuccess))
@@ -1350,6 +1384,28 @@ gm_status gm_mlp_grad(gm_ctx *c, const float *X, const float *T, const float *C,
     if (grad) HIPCHK(hipMemcpyAsync(grad, c->mlp_g.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     if (loss) HIPCHK(hipMemcpyAsync(loss, c->mlp_g.p + kMlpParams, sizeof(float), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_mlp_grad_noalloc(gm_ctx *c, const float *X, const float *T, const float *C, int64_t n,
+                              float *grad_loss)
+{
+    if (!c || !X || !T || !C || !grad_loss || n <= 0) return fail(GM_EINVAL, "bad argument");
+    if (n > kNoAllocMaxRows)
+        return fail(GM_EINVAL, "%lld rows exceed the %lld rows of the fixed scratch (%zu MiB)", (long long)n,
+                    kNoAllocMaxRows, kScratchFloats * sizeof(float) >> 20);
+    if (!c->mlp_ready) return fail(GM_ESTATE, "network parameters not set");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    const long long nb = (n + kMlpGradRows - 1) / kMlpGradRows;
+    MlpArgs M{};
+    M.X = X; M.T = T; M.C = C; M.n = n; M.P = c->mlp_p.p; M.Pb = c->mlp_pb.p;
+    M.gpart = c->scratch; M.loss_scale = 1.0f; M.loss_kind = c->mlp_loss;
+    // every block writes all of its partial (no clearing needed)
+    mlp_grad_kernel<<<(unsigned)nb, 64 * kMlpGradWaves, 0, c->stream>>>(M);
+    HIPCHK(hipGetLastError());
+    mlp_reduce_kernel<<<(kMlpParams + 1 + 255) / 256, 256, 0, c->stream>>>(c->scratch, (int)nb, grad_loss);
+    HIPCHK(hipGetLastError());
     return GM_OK;
 }
 

@@ -46,6 +46,7 @@ BIAS_CONST, BIAS_THETA2, BIAS_GEN2, BIAS_TABLE, BIAS_WINDOW = 0, 1, 2, 3, 4
 BIAS_LEARNED = BIAS_TABLE
 PRECISION_F64, PRECISION_F32_EMISSIVITY = 0, 1
 MLP_SQUARED, MLP_POISSON = 0, 1
+MLP_NOALLOC_MAX_ROWS = 56640
 
 # Every function the header declares (checked by the CPU symbol test).
 EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make_superphotons",
@@ -56,7 +57,7 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_set_event_log", "gm_event_count", "gm_set_batch",
            "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
            "gm_queue_stats", "gm_set_emission_table", "gm_set_score_weights", "gm_set_tally_mode",
-           "gm_mlp_set_loss", "gm_unload_zones"]
+           "gm_mlp_set_loss", "gm_unload_zones", "gm_mlp_grad_noalloc"]
 
 
 class GmGrid(C.Structure):
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_set_tally_mode": (i, [vp, i]),
         "gm_mlp_set_loss": (i, [vp, i]),
         "gm_unload_zones": (i, [vp, i]),
+        "gm_mlp_grad_noalloc": (i, [vp, vp, vp, vp, C.c_int64, vp]),
         "gm_event_count": (i, [vp, C.POINTER(C.c_uint64)]),
         "gm_set_batch": (i, [vp, i]),
         "gm_set_instance_bias": (i, [vp, i, i, C.c_double, C.c_double]),
@@ -381,6 +383,16 @@ class Context:
                                           C.c_void_p(Cd.data_ptr()), int(Xd.shape[0]),
                                           C.c_void_p(g.ctypes.data), C.c_void_p(L.ctypes.data)))
         return g, float(L[0])
+
+    def mlp_grad_noalloc(self, Xd, Td, Cd, out):
+        """gm_mlp_grad_noalloc on device tensors: `out` (float32, device,
+        MLP_PARAMS + 1 entries) receives the gradient and the loss; nothing
+        is allocated and nothing synchronised."""
+        assert out.is_cuda and out.dtype == torch.float32 and out.numel() == MLP_PARAMS + 1 and out.is_contiguous()
+        _check(load_library().gm_mlp_grad_noalloc(self._h, C.c_void_p(Xd.data_ptr()), C.c_void_p(Td.data_ptr()),
+                                                  C.c_void_p(Cd.data_ptr()), int(Xd.shape[0]),
+                                                  C.c_void_p(out.data_ptr())))
+        return out
 
     def mlp_train_step(self, Xd, Td, Cd, lr: float, want_loss: bool = False):
         """One Adam step on device tensors (see _dev_rows); returns the loss
