@@ -145,13 +145,48 @@ def register_bound(ctx, waves, target_ms=40.0):
     return out
 
 
+def _db(d):
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*results.db"), recursive=True))
+    return f[0] if f else None
+
+
 def _counter_rows(d):
+    """Counter rows (Kernel_Name, Counter_Name, Counter_Value) of a rocprofv3
+    --pmc run: its counter_collection.csv, or the counters view of its
+    database output."""
     import csv
     import glob
     f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
-    if not f:
-        raise SystemExit("no counter_collection.csv under %s" % d)
-    return list(csv.DictReader(open(f[0])))
+    if f:
+        return list(csv.DictReader(open(f[0])))
+    db = _db(d)
+    if not db:
+        raise SystemExit("no counter output under %s" % d)
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+    return [{"Kernel_Name": k, "Counter_Name": c, "Counter_Value": v} for k, c, v in rows]
+
+
+def _trace_rows(d):
+    """(per-kernel stats rows, per-launch rows) of a rocprofv3 --kernel-trace
+    --stats run, from its CSV files or its database output."""
+    import csv
+    import glob
+    st = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
+    tr = sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True))
+    if st and tr:
+        return list(csv.DictReader(open(st[0]))), list(csv.DictReader(open(tr[0])))
+    import sqlite3
+    con = sqlite3.connect(_db(d))
+    stats = [{"Name": n, "Calls": c, "TotalDurationNs": t, "AverageNs": a, "Percentage": p}
+             for n, c, t, a, p in con.execute(
+                 "select name, total_calls, total_duration, average, percentage from top_kernels "
+                 "order by total_duration desc").fetchall()]
+    launches = [{"Kernel_Name": n, "Start_Timestamp": s_, "End_Timestamp": e, "Grid_Size_X": g}
+                for n, s_, e, g in con.execute("select name, start, end, grid_x from kernels").fetchall()]
+    return stats, launches
 
 
 def summarize_traffic(fetch_dir, write_dir, commands, copy_mib):
@@ -212,13 +247,9 @@ def summarize_trace(trace_dir, bench_log, command):
     """Writes the kernel-trace summary: rocprofv3 --stats table, the last
     launches, and the tracker's average launch time as bench.py measured it
     with HIP events in the same run."""
-    import csv
-    import glob
-    stats = sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True))[0]
-    trace = sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True))[0]
+    rows, tr = _trace_rows(trace_dir)
     line = [l for l in open(bench_log) if l.startswith("{")][-1]
     b = json.loads(line)
-    rows = list(csv.DictReader(open(stats)))
     mine = [r for r in rows if TRACK_KERNEL in r["Name"]]
     lines = ["# rocprofv3 kernel trace: " + WORKLOAD_TEXT,
              "# command: " + command,
@@ -231,7 +262,6 @@ def summarize_trace(trace_dir, bench_log, command):
     lines.append(",".join(rows[0].keys()))
     for r in rows[:16]:
         lines.append(",".join(str(v) for v in r.values()))
-    tr = list(csv.DictReader(open(trace)))
     tr.sort(key=lambda r: int(r["Start_Timestamp"]))
     lines += ["", "## the last 40 launches of the run: kernel | duration | grid (work-items)"]
     for r in tr[-40:]:

@@ -37,7 +37,8 @@ def reference(ctx, wl, instance: int, rounds: int, seed0: int, precision: int = 
     of one round's bin estimate, total superphotons).  The bin estimate of a
     round is a sum over photons, so its variance is estimated by the summed
     (wE)^2 of the round."""
-    ctx.read_spectrum(instance, reset=True)
+    if getattr(ctx, "n_theta", None):              # clear what earlier calls left
+        ctx.read_spectrum(instance, reset=True)
     n = 0
     for r in range(rounds):
         ctx.make_superphotons(dict(wl.emit, seed=seed0 + r), instance=instance)

@@ -23,6 +23,17 @@ GM_HD double g_shape(double X)
     return t * t * exp(-y);
 }
 
+// e^x - 1 for the Kirchhoff factor (x = h nu / k T >= 0): the series to
+// x^5 below 1e-3 (truncation below x^6 / 720 < 2e-21 relative), else
+// exp(x) - 1 (relative error below 2e-13 there).  Shares exp's code with
+// the other exponentials of the opacity evaluation instead of bringing a
+// second set of polynomial constants into the tracker's registers.
+GM_HD double expm1_kirchhoff(double x)
+{
+    if (x < 1e-3) return x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0)))));
+    return exp(x) - 1.0;
+}
+
 GM_HD double nu_crit(double theta_e, double B)
 {
     return (2.0 / 9.0) * (kE * B / (2.0 * kPi * kMe * kC)) * theta_e * theta_e;

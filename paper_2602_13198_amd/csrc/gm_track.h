@@ -461,7 +461,7 @@ GM_D Coef coefficients_at64(const Args &A, int z, const G &gm, const double *k, 
             if (j > 0.0) {
                 // nu alpha = j (e^{h nu / kT} - 1) c^2 / (2 h nu^2), Kirchhoff
                 double inv_nu = inv_ef * (kH / kMeC2);
-                c.nua = j * expm1(ef * zr[Z_INVTH]) * (kC * kC / (2.0 * kH)) * inv_nu * inv_nu;
+                c.nua = j * expm1_kirchhoff(ef * zr[Z_INVTH]) * (kC * kC / (2.0 * kH)) * inv_nu * inv_nu;
             }
         }
     }

@@ -260,31 +260,32 @@ def window_table(ln_I_sc_zone, sc, sc_lnI, b_plain, b_max):
     return ln_I_sc_zone + 0.5 * (lo + hi)
 
 
-def emission_modulation(ctx, wl, inst, ln_I_em_zone, n_nodes, n_s, clip=math.log(1e3)):
-    """m_i(nu) = ln w(nu) + ln I_em(zone, nu) + const on n_nodes log-nu nodes,
-    the spread of ln I_em limited to `clip` below its maximum per zone (no
-    region is starved), const fixing the expected roots to the plain run's.
-    The expected count scales exactly with e^const, so const is found from
-    one make at a const low enough that the make allocates almost nothing."""
+def emission_modulation(ctx, wl, inst, ln_I_em_zone, ln_I_mean, n_nodes, n_s, alpha=0.5):
+    """Defensive emission proposal: zone i's superphotons at nu get the
+    weight w(nu) / [(1 - alpha) + alpha I_em(zone, nu) / I_mean] (times the
+    constant that keeps the expected roots at the plain run's), I_mean the
+    plain run's mean importance per unit weight.  Where the importance is
+    high the proposal emits up to alpha I/I_mean times more roots; nowhere
+    does it emit fewer than 1 - alpha of the plain number, which bounds the
+    weights by w / (1 - alpha) however wrong the estimate.  The expected
+    count scales exactly with the constant, so it is found from one make at
+    a constant low enough that the make allocates almost nothing."""
     e = wl.emit
     lo, hi = math.log(e["nu_min"]), math.log(e["nu_max"])
-    em = ctx.read_emission(inst)
-    nw = len(em["ln_w"])
-    nb0 = float(em["nbar"].sum())
-    x = np.linspace(lo, hi, n_nodes)
-    lnw = np.interp(x, np.linspace(lo, hi, nw), em["ln_w"])
-    I = np.maximum(ln_I_em_zone, ln_I_em_zone.max(axis=1, keepdims=True) - clip)
-    m = lnw[None, :] + I
-    m = m - (m.max() + 20.0)
-    ctx.set_emission_table(inst, m, lo, hi)
+    nb0 = float(ctx.read_emission(inst)["nbar"].sum())
+    ratio = np.exp(np.clip(ln_I_em_zone - ln_I_mean, -50.0, 50.0))
+    m = np.log((1.0 - alpha) + alpha * ratio)
+    shift = m.max() + 20.0
+    ctx.set_emission_table(inst, m - shift, lo, hi)
     ctx.make_superphotons(dict(e, n_target=float(n_s), seed=1), instance=inst)
     nb1 = float(ctx.read_emission(inst)["nbar"].sum())
-    m = m + math.log(nb0 / max(nb1, 1e-300))
+    m = m - shift + math.log(nb0 / max(nb1, 1e-300))
     ctx.set_emission_table(inst, m, lo, hi)
     return m, lo, hi
 
 
-def build_tables(ctx, wl, inst, ev, root_stride, b_plain, b_max, n_s, mode, net_seed=1, log=None):
+def build_tables(ctx, wl, inst, ev, root_stride, b_plain, b_max, n_s, mode, net_seed=1, log=None,
+                 use_bias=True, use_emission=True, alpha=0.5):
     """Tables of the adaptive ("cells") or learned ("network") form from the
     pilot records; sets the instance's bias (window) and emission tables."""
     sc, em = split_records(ev, root_stride)
@@ -339,18 +340,28 @@ def build_tables(ctx, wl, inst, ev, root_stride, b_plain, b_max, n_s, mode, net_
         ye = net.predict(ctx, Xe)
         lnI_em = np.full((nz, nodes), math.log(n_em_mean))
         lnI_em[emits] = ye[:, 1].reshape(len(emits), nodes) + math.log(n_em_mean)
-    wt = window_table(lnI_sc, sc, sc_lnI, b_plain, b_max)
-    ctx.set_bias_table(inst, wt, LN_EPS[0], LN_EPS[1])
-    emission_modulation(ctx, wl, inst, lnI_em, nodes, n_s)
-    info["bias_table_range"] = [float(np.min(wt)), float(np.max(wt))]
+    if use_bias:
+        wt = window_table(lnI_sc, sc, sc_lnI, b_plain, b_max)
+        ctx.set_bias_table(inst, wt, LN_EPS[0], LN_EPS[1])
+        info["bias_table_range"] = [float(np.min(wt)), float(np.max(wt))]
+    if use_emission:
+        m, _, _ = emission_modulation(ctx, wl, inst, lnI_em, math.log(n_em_mean), nodes, n_s, alpha)
+        info["emission_table_range"] = [float(np.min(m)), float(np.max(m))]
     return info
 
 
 # ---------------------------------------------------------------------------
 # the comparison
 # ---------------------------------------------------------------------------
+FORMS = {
+    # name: (table source, weight-window bias, emission proposal)
+    "adaptive": ("cells", True, True),
+    "learned": ("network", True, True),
+}
+
+
 def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rounds=4, b_max=100.0,
-                  forms=("cells", "network"), log=None):
+                  forms=("adaptive", "learned"), log=None, alpha=0.5, variants=None):
     """Time to 1 % spectral error of the plain uniform bias and of the
     adaptive and learned forms on one workload (median over seeds), against
     one plain reference of ref_rounds rounds of N_s."""
@@ -383,7 +394,9 @@ def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rou
     if log:
         log("plain: %s" % secs)
     root_stride = 4
-    for form in forms:
+    variants = dict(FORMS, **(variants or {}))
+    for name in forms:
+        form, use_bias, use_em = variants[name]
         res = []
         infos = []
         for k in range(seeds):
@@ -392,12 +405,14 @@ def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rou
             try:
                 ev, sw, _ = pilot(ctx, wl, inst, pilot_rounds, 300000 + 1000 * k, n_round, root_stride)
                 info = build_tables(ctx, wl, inst, ev, root_stride, b_plain, b_max, n_round, form,
-                                    net_seed=1 + k, log=log)
+                                    net_seed=1 + k, log=log, use_bias=use_bias, use_emission=use_em,
+                                    alpha=alpha)
                 del ev
                 torch.cuda.synchronize()
                 t_prep = time.perf_counter() - ta
+                over = dict(bias_mode=GM.BIAS_WINDOW, bias_max=b_max) if use_bias else None
                 r = CV.time_to_error(ctx, wl, inst, L_ref, mask, 400000 + 1000 * k, n_round, max_rounds=512,
-                                     track_overrides=dict(bias_mode=GM.BIAS_WINDOW, bias_max=b_max))
+                                     track_overrides=over)
             except GM.GmError as exc:          # reported, not hidden: the form has no time then
                 ctx.set_emission_table(inst, None)
                 ctx.set_event_log(0)
@@ -413,16 +428,20 @@ def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rou
             infos.append(dict(info, superphotons=r["superphotons"], final_eps=r["final_eps"],
                               transport_s=r["seconds"]))
             if log:
-                log("%s seed %d: prep %.2f s, transport %s s, final eps %.4f" % (form, k, t_prep, r["seconds"],
-                                                                                  r["final_eps"]))
+                log("%s seed %d: prep %.2f s, transport %s s, final eps %.4f, %.3g superphotons"
+                    % (name, k, t_prep, r["seconds"], r["final_eps"], r["superphotons"]))
         med = float(np.median(res)) if all(s is not None for s in res) else None
-        out[{"cells": "adaptive", "network": "learned"}[form]] = {
+        parts = []
+        if use_bias:
+            parts.append("weight-window bias b = clamp(c_b w I_sc, 1, %g)" % b_max)
+        if use_em:
+            parts.append("defensive emission proposal w / [(1 - %g) + %g I_em / I_mean]" % (alpha, alpha))
+        out[name] = {
             "seconds_median": med, "seconds": res, "runs": infos,
             "what": ("importance per (8x8x8-zone cell, energy node) from summed scores / summed weights"
                      if form == "cells" else
                      "network 6-64-64-2 trained on the library's matrix-core kernels (Poisson deviance)")
-                    + "; weight-window bias b = clamp(c_b w I_sc, 1, %g) and emission proposal w ~ 1/I_em; "
-                      "%d plain pilot rounds counted in the time" % (b_max, pilot_rounds),
+                    + "; " + " and ".join(parts) + "; %d plain pilot rounds counted in the time" % pilot_rounds,
             "plain_over_form": (med_p / med) if (med_p and med) else None,
         }
     ctx.read_spectrum(inst, reset=True)
