@@ -180,7 +180,8 @@ def _trace_rows(d):
         return list(csv.DictReader(open(st[0]))), list(csv.DictReader(open(tr[0])))
     import sqlite3
     con = sqlite3.connect(_db(d))
-    stats = [{"Name": n, "Calls": c, "TotalDurationNs": t, "AverageNs": a, "Percentage": p}
+    # the summary view reports microseconds, the per-launch view nanoseconds
+    stats = [{"Name": n, "Calls": c, "TotalDurationNs": 1e3 * t, "AverageNs": 1e3 * a, "Percentage": p}
              for n, c, t, a, p in con.execute(
                  "select name, total_calls, total_duration, average, percentage from top_kernels "
                  "order by total_duration desc").fetchall()]

@@ -193,6 +193,12 @@ gm_status gm_load_zones(gm_ctx *ctx, int instance, const gm_grid *grid, const gm
  * again.  Synchronises. */
 gm_status gm_unload_zones(gm_ctx *ctx, int instance);
 
+/* The expected number of roots gm_make_superphotons would draw for these
+ * parameters (the sum of the zones' expected counts under the instance's
+ * emission table), without drawing or allocating any; the instance has to
+ * be made again before tracking.  Synchronises. */
+gm_status gm_expected_roots(gm_ctx *ctx, int instance, const gm_emit_params *params, double *expected);
+
 /* Superphoton generation (Creation of superphotons and Sampling procedure
  * sections): builds the weight table w(nu) (eq:weight_calc), draws each
  * zone's superphoton count by stochastic rounding of its expectation, and
@@ -262,6 +268,17 @@ gm_status gm_set_tuning(gm_ctx *ctx, int track_waves, int refill_min);
  * photons -- in groups of at most this many (GPU implementation section:
  * batches).  Results do not depend on it. */
 gm_status gm_set_batch(gm_ctx *ctx, int max_instances);
+
+/* HIP graphs (scheduling; results do not depend on it): with enable = 1,
+ * gm_track_scatter records each root chunk's launch sequence -- counter
+ * reset, birth, and per generation the tracking, event-count and
+ * scattering kernels -- as a HIP graph by stream capture on a private
+ * stream and launches that graph on the context's stream, updating the
+ * executable graph in place when only kernel arguments changed (a new
+ * instantiation otherwise).  Per-launch event timing (gm_set_timing) is not
+ * recorded in this mode.  enable = 0 launches directly (default), -1 only
+ * reads the counters: graph launches and instantiations since creation. */
+gm_status gm_set_graph(gm_ctx *ctx, int enable, uint64_t *launches, uint64_t *instantiations);
 
 /* Photon queues (scheduling; results do not depend on it beyond the order
  * of FP64 tally sums).  gm_track_scatter runs the roots in chunks of half the
@@ -410,6 +427,55 @@ typedef struct {
 } gm_event_rec;
 gm_status gm_set_event_log(gm_ctx *ctx, void *device_buffer, uint64_t capacity, uint64_t root_stride);
 gm_status gm_event_count(gm_ctx *ctx, uint64_t *n);
+
+/* Tables of an instance built on the device from importance estimates.  A
+ * map says which table (bias: nodes in ln eps of the incoming fluid-frame
+ * photon energy; emission: nodes in ln nu, Hz, of the emitted photon), its
+ * n_nodes nodes over [lo, hi], and how an estimate ln I of the importance of
+ * a unit-weight photon created at (zone, node) becomes a table value:
+ *   GM_IMP_LINEAR   T = a ln I + b + shift
+ *   GM_IMP_MIXTURE  T = ln((1 - alpha) + alpha exp(a ln I + b)) + shift, 0 <= alpha < 1
+ * (for the emission table a defensive proposal: no zone emits fewer than
+ * 1 - alpha of its plain roots).  Zones without plasma get 0.  The table
+ * replaces the instance's table of that kind; an emission table takes
+ * effect at the next gm_make_superphotons.  Synchronises. */
+#define GM_TABLE_BIAS 0
+#define GM_TABLE_EMISSION 1
+#define GM_IMP_LINEAR 0
+#define GM_IMP_MIXTURE 1
+typedef struct {
+    int    table;           /* GM_TABLE_*                                          */
+    int    n_nodes;         /* 2..4096                                             */
+    double lo, hi;          /* node range of the table variable                   */
+    int    kind;            /* GM_IMP_*                                            */
+    double a, b, alpha;
+    double shift;           /* added to every value after the mapping             */
+} gm_importance_map;
+
+/* ln I from the network's output `output` (0 or 1) for every (zone, node):
+ * features ln Theta_e, ln n_e, ln(B + 1e-10 G), ln eps, radius (Kerr: ln r
+ * of the zone centre; flat: |x| over the grid half-size), cos theta of the
+ * centre, standardised as (f - mu) / sd, evaluated on the matrix cores. */
+gm_status gm_mlp_fill_table(gm_ctx *ctx, int instance, const gm_importance_map *map, int output,
+                            const float mu[6], const float sd[6]);
+
+/* ln I from the event log's records (scattering records for the bias
+ * table, emission records for the emission table): summed scores and
+ * weights per cell of blocks[0] x blocks[1] x blocks[2] zones and node
+ * (nearest node of the record's ln eps, resp. ln nu); gm_cells_accumulate
+ * forms the sums (kept in the context) and returns their totals [3]
+ * {sum score, sum weight, records}; gm_cells_fill_table then writes the
+ * ratio score / weight of each zone's cell, shrunk towards the overall
+ * ratio with `prior` records' mean weight (cells without records take the
+ * overall ratio).  The map of both calls must name the same table and
+ * nodes. */
+gm_status gm_cells_accumulate(gm_ctx *ctx, int instance, const gm_importance_map *map, const int blocks[3],
+                              double totals[3]);
+/* Copy an instance's bias or emission table (GM_TABLE_*) into a host
+ * buffer of n = nzones x nodes doubles; n_nodes (may be NULL) receives the
+ * node count; host_out = NULL only reports it.  Synchronises. */
+gm_status gm_read_table(gm_ctx *ctx, int instance, int table, double *host_out, int64_t n, int *n_nodes);
+gm_status gm_cells_fill_table(gm_ctx *ctx, int instance, const gm_importance_map *map, double prior);
 
 /* Score weights of an instance's event records: host array [n_theta][n_nu]
  * (n must match the tally of the next gm_track_scatter), copied; NULL

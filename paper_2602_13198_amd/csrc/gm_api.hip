@@ -14,6 +14,7 @@
 #include "gm_bound.h"
 #include "gm_emit.h"
 #include "gm_host_tables.h"
+#include "gm_importance.h"
 #include "gm_mlp.h"
 #include "gm_track.h"
 #include "gm_track_ks.h"
@@ -82,6 +83,7 @@ struct Instance {
     bool loaded = false, made = false;
     gm_grid grid{};
     int nz = 0;
+    int max_i1 = -1;                           // last first-axis zone index holding plasma
     DevBuf<double> zrec, vol;
     DevBuf<float> zrec32;
     DevBuf<int> emits;
@@ -152,6 +154,13 @@ struct gm_ctx {
     int max_batch = GM_MAX_INSTANCES;
     DevBuf<TArgs> inst_args;
     DevBuf<unsigned long long> root_off, inst_ctr;
+    // HIP graph of a chunk's launch sequence (captured on a private stream,
+    // launched on the context's stream; the executable graph is updated in
+    // place while only kernel arguments change)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    unsigned long long graph_launches = 0, graph_instantiations = 0;
     // optional event timing of the tracking launches
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -174,6 +183,12 @@ struct gm_ctx {
     long long mlp_t = 0;
     int mlp_loss = 0;
     float *scratch = nullptr;                   // this device's copy of the scratch array
+    // cell sums of the event records (adaptive form) and their layout
+    DevBuf<double> cell_acc;
+    gm_importance_map cell_map{};
+    int cell_blocks[3] = {0, 0, 0}, cell_nc[3] = {0, 0, 0};
+    int cell_inst = -1;
+    double cell_tot[3] = {0.0, 0.0, 0.0};
 };
 
 static gm_status set_device(gm_ctx *c)
@@ -297,6 +312,7 @@ gm_status gm_destroy(gm_ctx *c)
     }
     c->inst_args.release(); c->root_off.release(); c->inst_ctr.release();
     c->bak_d.release(); c->bak_u.release(); c->call_bak_d.release(); c->call_bak_u.release();
+    c->cell_acc.release();
     c->mlp_p.release(); c->mlp_m.release(); c->mlp_v.release(); c->mlp_g.release();
     c->mlp_gpart.release(); c->mlp_pb.release(); c->evlog_n.release();
     c->gcheb.release(); c->sh_table.release(); c->sh_table32.release(); c->gl_x.release(); c->gl_w.release();
@@ -306,6 +322,8 @@ gm_status gm_destroy(gm_ctx *c)
         for (auto &d : c->qi[b]) d.release();
     }
     c->ctr.release(); c->flags.release(); c->trace_n.release();
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &pr : c->ev_pending) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -411,14 +429,19 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
     P.a_spin = g->a_spin;
     P.h_slope = g->h_slope;
     P.r_h = kerr_horizon(g->a_spin);
+    P.max_i1 = c->flags.p + 3;
+    int max_i1 = -1;
+    HIPCHK(hipMemcpyAsync(P.max_i1, &max_i1, sizeof(int), hipMemcpyHostToDevice, c->stream));
     zone_prep_kernel<<<(nz + 255) / 256, 256, 0, c->stream>>>(P);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&max_i1, P.max_i1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     hipError_t e2 = hipStreamSynchronize(c->stream);     // staging buffers are freed next
     for (auto &b : stage) b.release();
     if (e != hipSuccess || e2 != hipSuccess)
         return fail(GM_EDEVICE, "zone prep: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     I.grid = *g;
     I.nz = nz;
+    I.max_i1 = max_i1;
     I.loaded = true;
     I.made = false;
     I.pending = false;
@@ -442,7 +465,8 @@ gm_status gm_unload_zones(gm_ctx *c, int instance)
     return GM_OK;
 }
 
-static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint64_t *n_made)
+static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint64_t *n_made,
+                          double *expected = nullptr)
 {
     Instance &I = c->inst[instance];
     if (!I.loaded) return fail(GM_ESTATE, "instance %d has no zones", instance);
@@ -485,6 +509,21 @@ static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint
         weight_table_kernel<<<1, 256, 0, c->stream>>>(E);
         count_kernel<<<nblk, 256, 0, c->stream>>>(E);
     }
+    if (expected) {
+        // expected roots only: no draw, no root table
+        std::vector<double> nb(nz);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(nb.data(), I.nbar.p, (size_t)nz * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        int status = 0;
+        HIPCHK(hipMemcpyAsync(&status, c->flags.p + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        I.made = false;
+        if (status != 0) return fail(GM_EINVAL, "no zone emits in the band [%g, %g] Hz", p->nu_min, p->nu_max);
+        double t = 0.0;
+        for (double v : nb) t += v;
+        *expected = t;
+        return GM_OK;
+    }
     const int ntile = (nz + kScanTile - 1) / kScanTile;
     scan_tiles_kernel<<<ntile, 256, 0, c->stream>>>(I.count.p, nz, I.tile.p);
     scan_sums_kernel<<<1, 256, 0, c->stream>>>(I.tile.p, ntile, I.offset.p + nz);
@@ -514,6 +553,18 @@ static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint
     I.pending = true;
     if (n_made) *n_made = total;
     return GM_OK;
+}
+
+gm_status gm_expected_roots(gm_ctx *c, int instance, const gm_emit_params *p, double *expected)
+{
+    if (!c || !p || !expected) return fail(GM_EINVAL, "NULL argument");
+    if (!(p->nu_min > 0.0) || !(p->nu_max > p->nu_min) || p->n_wnodes < 3 || p->n_wnodes > 4097 ||
+        !(p->n_wnodes & 1) || !(p->n_target > 0.0) || !(p->w_floor_rel >= 0.0))
+        return fail(GM_EINVAL, "bad emission parameters");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    return make_one(c, instance, p, nullptr, expected);
 }
 
 gm_status gm_make_superphotons(gm_ctx *c, int instance, const gm_emit_params *p, uint64_t *n_made)
@@ -695,6 +746,7 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
     A.r_h = kerr_horizon(I.grid.a_spin);
     A.r_capture = A.r_h * (1.0 + tp->horizon_eps);
     A.r_record = I.grid.r_record;
+    A.i1_plasma_max = (double)I.max_i1;
     A.verlet_tol = tp->verlet_tol;
     A.verlet_max_it = tp->verlet_max_it;
     A.inv_sc[0] = 1.0 / I.grid.dx[0];
@@ -813,10 +865,13 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
         HIPCHK(hipMemcpyAsync(&ev_lo, c->evlog_n.p, sizeof(ev_lo), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
     }
-    for (unsigned long long start = 0; start < total;) {
-        const unsigned long long cnt = std::min(chunk, total - start);
-        bs = save(c->bak_d, c->bak_u);
-        if (bs != GM_OK) return bs;
+    const hipStream_t run_stream = c->stream;
+    if (c->use_graph && !c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    // the launches of one chunk: issued on c->stream, which is the capture
+    // stream while a graph is being recorded (nothing runs then)
+    auto issue_chunk = [&](unsigned long long start, unsigned long long cnt) -> gm_status {
+        gm_status st = save(c->bak_d, c->bak_u);
+        if (st != GM_OK) return st;
         reset_counters_kernel<<<1, 64, 0, c->stream>>>(c->ctr.p, 64, c->flags.p);
         L.root_begin = start;
         L.root_count = cnt;
@@ -836,15 +891,17 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
             L.src_count = c->ctr.p + 2 * g;
             L.src_cursor = c->ctr.p + 2 * g + 1;
             L.dst_count = c->ctr.p + 2 * (g + 1);
+            // per-launch event timing only when launched directly
+            const bool timed = c->timing && !c->use_graph;
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (c->timing) {
+            if (timed) {
                 gm_status ts = take_event_pair(c, e0, e1);
                 if (ts != GM_OK) return ts;
                 HIPCHK(hipEventRecord(e0, c->stream));
             }
             track_fn<<<grid, 256, lds_track, c->stream>>>(L);
             HIPCHK(hipGetLastError());
-            if (c->timing) HIPCHK(hipEventRecord(e1, c->stream));
+            if (timed) HIPCHK(hipEventRecord(e1, c->stream));
             if (g + 1 < ngen) {
                 if (batched) {
                     reset_counters_kernel<<<1, 2 * GM_MAX_INSTANCES, 0, c->stream>>>(c->inst_ctr.p, 2 * GM_MAX_INSTANCES, nullptr);
@@ -853,6 +910,47 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
                 scatter_fn<<<c->n_cu * 8, 256, lds_small, c->stream>>>(L);
                 HIPCHK(hipGetLastError());
             }
+        }
+        return GM_OK;
+    };
+    for (unsigned long long start = 0; start < total;) {
+        const unsigned long long cnt = std::min(chunk, total - start);
+        if (!c->use_graph) {
+            bs = issue_chunk(start, cnt);
+            if (bs != GM_OK) return bs;
+        } else {
+            HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            c->stream = c->cap_stream;
+            bs = issue_chunk(start, cnt);
+            hipGraph_t gr = nullptr;
+            const hipError_t ec = hipStreamEndCapture(c->cap_stream, &gr);
+            c->stream = run_stream;
+            if (bs != GM_OK || ec != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return bs != GM_OK ? bs : fail(GM_EDEVICE, "graph capture: %s", hipGetErrorString(ec));
+            }
+            // reuse the executable graph when only kernel arguments changed
+            if (c->graph_exec) {
+                hipGraphNode_t bad = nullptr;
+                hipGraphExecUpdateResult res;
+                if (hipGraphExecUpdate(c->graph_exec, gr, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+                    (void)hipGetLastError();
+                    (void)hipGraphExecDestroy(c->graph_exec);
+                    c->graph_exec = nullptr;
+                }
+            }
+            hipError_t ei = hipSuccess;
+            if (!c->graph_exec) {
+                ei = hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0);
+                c->graph_instantiations += 1;
+            }
+            (void)hipGraphDestroy(gr);
+            if (ei != hipSuccess) {
+                c->graph_exec = nullptr;
+                return fail(GM_EDEVICE, "graph instantiation: %s", hipGetErrorString(ei));
+            }
+            HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
+            c->graph_launches += 1;
         }
         int ovf = 0;
         HIPCHK(hipMemcpyAsync(&ovf, c->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1086,6 +1184,15 @@ gm_status gm_queue_stats(gm_ctx *c, uint64_t *capacity, uint64_t *chunk_retries)
     return GM_OK;
 }
 
+gm_status gm_set_graph(gm_ctx *c, int enable, uint64_t *launches, uint64_t *instantiations)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (launches) *launches = c->graph_launches;
+    if (instantiations) *instantiations = c->graph_instantiations;
+    if (enable >= 0) c->use_graph = enable != 0;
+    return GM_OK;
+}
+
 gm_status gm_set_batch(gm_ctx *c, int max_instances)
 {
     if (!c) return fail(GM_EINVAL, "NULL context");
@@ -1293,6 +1400,188 @@ gm_status gm_set_tally_mode(gm_ctx *c, int mode)
     if (!c) return fail(GM_EINVAL, "NULL context");
     if (mode < 0 || mode > 2) return fail(GM_EINVAL, "tally mode %d not in 0..2", mode);
     c->tally_mode = mode;
+    return GM_OK;
+}
+
+// ---- tables of the importance-driven forms --------------------------------
+static gm_status check_map(const gm_ctx *c, int instance, const gm_importance_map *m)
+{
+    if (!c || !m) return fail(GM_EINVAL, "NULL argument");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    if (!c->inst[instance].loaded) return fail(GM_ESTATE, "instance %d has no zones", instance);
+    if ((m->table != GM_TABLE_BIAS && m->table != GM_TABLE_EMISSION) || m->n_nodes < 2 || m->n_nodes > 4096 ||
+        !(m->hi > m->lo) || (m->kind != GM_IMP_LINEAR && m->kind != GM_IMP_MIXTURE) || !std::isfinite(m->a) ||
+        !std::isfinite(m->b) || !std::isfinite(m->shift) ||
+        (m->kind == GM_IMP_MIXTURE && !(m->alpha >= 0.0 && m->alpha < 1.0)))
+        return fail(GM_EINVAL, "bad importance map");
+    return GM_OK;
+}
+
+static ZoneGeo zone_geo_of(const gm_grid &g)
+{
+    ZoneGeo G{};
+    for (int j = 0; j < 3; ++j) { G.n[j] = g.n[j]; G.xs[j] = g.x_start[j]; G.dx[j] = g.dx[j]; }
+    G.metric = g.metric;
+    G.h_slope = g.h_slope;
+    G.half = 0.0;
+    for (int j = 0; j < 3; ++j) G.half = std::max(G.half, 0.5 * g.n[j] * g.dx[j]);
+    return G;
+}
+
+// The instance's table a map writes (allocated as needed), with its node
+// layout recorded; the emission table invalidates the stored counts.
+static gm_status map_target(gm_ctx *c, int instance, const gm_importance_map *m, double **out)
+{
+    Instance &I = c->inst[instance];
+    const size_t n = (size_t)I.nz * m->n_nodes;
+    if (m->table == GM_TABLE_BIAS) {
+        if (I.lnb.ensure(n) != hipSuccess) return fail(GM_ENOMEM, "bias table");
+        I.lnb_n = m->n_nodes; I.lnb_lo = m->lo; I.lnb_hi = m->hi;
+        *out = I.lnb.p;
+    } else {
+        if (I.mtab.ensure(n) != hipSuccess) return fail(GM_ENOMEM, "emission table");
+        I.mt_n = m->n_nodes; I.mt_lo = m->lo; I.mt_hi = m->hi; I.mt_on = true;
+        I.made = false;
+        *out = I.mtab.p;
+    }
+    return GM_OK;
+}
+
+static double map_v_shift(const gm_importance_map *m)
+{
+    return m->table == GM_TABLE_EMISSION ? std::log(kMeC2 / kH) : 0.0;
+}
+
+gm_status gm_mlp_fill_table(gm_ctx *c, int instance, const gm_importance_map *m, int output, const float *mu,
+                            const float *sd)
+{
+    gm_status s = check_map(c, instance, m);
+    if (s != GM_OK) return s;
+    if (output < 0 || output >= kMlpOut || !mu || !sd) return fail(GM_EINVAL, "bad network output or scaling");
+    for (int i = 0; i < kMlpIn; ++i)
+        if (!std::isfinite(mu[i]) || !(sd[i] > 0.0f)) return fail(GM_EINVAL, "feature scaling %d", i);
+    if (!c->mlp_ready) return fail(GM_ESTATE, "network parameters not set");
+    s = set_device(c);
+    if (s != GM_OK) return s;
+    Instance &I = c->inst[instance];
+    double *tab = nullptr;
+    s = map_target(c, instance, m, &tab);
+    if (s != GM_OK) return s;
+    TableFill T{};
+    T.zrec = I.zrec.p;
+    T.G = zone_geo_of(I.grid);
+    T.nz = I.nz;
+    T.n_nodes = m->n_nodes;
+    T.lo = m->lo; T.hi = m->hi; T.v_shift = map_v_shift(m);
+    for (int i = 0; i < kMlpIn; ++i) { T.mu[i] = mu[i]; T.inv_sd[i] = 1.0f / sd[i]; }
+    T.out_col = output;
+    T.map = ImpMap{m->kind, m->a, m->b, m->alpha, m->shift};
+    T.neutral = 0.0;
+    T.table = tab;
+    MlpArgs M{};
+    M.n = (long long)I.nz * m->n_nodes;
+    M.P = c->mlp_p.p;
+    M.Pb = c->mlp_pb.p;
+    const long long rows_per_block = 16LL * kMlpWaves;
+    mlp_table_kernel<<<(unsigned)((M.n + rows_per_block - 1) / rows_per_block), 64 * kMlpWaves, 0, c->stream>>>(M, T);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_read_table(gm_ctx *c, int instance, int table, double *host_out, int64_t n, int *n_nodes)
+{
+    if (!c) return fail(GM_EINVAL, "NULL context");
+    if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
+    const Instance &I = c->inst[instance];
+    const bool bias = table == GM_TABLE_BIAS;
+    if (!bias && table != GM_TABLE_EMISSION) return fail(GM_EINVAL, "table %d", table);
+    const double *src = bias ? I.lnb.p : (I.mt_on ? I.mtab.p : nullptr);
+    const int nn = bias ? I.lnb_n : I.mt_n;
+    if (!src || nn < 2) return fail(GM_ESTATE, "instance %d has no such table", instance);
+    if (n_nodes) *n_nodes = nn;
+    if (!host_out) return GM_OK;
+    if (n != (int64_t)I.nz * nn) return fail(GM_EINVAL, "table holds %lld values", (long long)I.nz * nn);
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    HIPCHK(hipMemcpyAsync(host_out, src, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return GM_OK;
+}
+
+gm_status gm_cells_accumulate(gm_ctx *c, int instance, const gm_importance_map *m, const int *blocks,
+                              double *totals)
+{
+    gm_status s = check_map(c, instance, m);
+    if (s != GM_OK) return s;
+    if (!blocks || blocks[0] < 1 || blocks[1] < 1 || blocks[2] < 1) return fail(GM_EINVAL, "bad cell blocks");
+    if (!c->evlog) return fail(GM_ESTATE, "no event log set");
+    s = set_device(c);
+    if (s != GM_OK) return s;
+    const Instance &I = c->inst[instance];
+    CellArgs C{};
+    C.G = zone_geo_of(I.grid);
+    for (int j = 0; j < 3; ++j) { C.b[j] = blocks[j]; C.nc[j] = (I.grid.n[j] + blocks[j] - 1) / blocks[j]; }
+    C.n_nodes = m->n_nodes;
+    C.lo = m->lo; C.hi = m->hi; C.v_shift = map_v_shift(m);
+    C.records = m->table == GM_TABLE_BIAS ? 1 : 0;
+    const size_t n_acc = (size_t)C.nc[0] * C.nc[1] * C.nc[2] * m->n_nodes * 3;
+    if (c->cell_acc.ensure(n_acc) != hipSuccess) return fail(GM_ENOMEM, "cell sums");
+    HIPCHK(hipMemsetAsync(c->cell_acc.p, 0, n_acc * sizeof(double), c->stream));
+    unsigned long long n_ev = 0;
+    HIPCHK(hipMemcpyAsync(&n_ev, c->evlog_n.p, sizeof(n_ev), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    C.ev = c->evlog;
+    C.n_ev = std::min(n_ev, c->evlog_cap);
+    C.acc = c->cell_acc.p;
+    if (C.n_ev > 0) {
+        const unsigned nb = (unsigned)std::min<unsigned long long>((C.n_ev + 255) / 256, 8192);
+        cells_accumulate_kernel<<<nb, 256, 0, c->stream>>>(C);
+        HIPCHK(hipGetLastError());
+    }
+    std::vector<double> acc(n_acc);
+    HIPCHK(hipMemcpyAsync(acc.data(), c->cell_acc.p, n_acc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double t[3] = {0.0, 0.0, 0.0};
+    for (size_t i = 0; i < n_acc; i += 3) { t[0] += acc[i]; t[1] += acc[i + 1]; t[2] += acc[i + 2]; }
+    for (int j = 0; j < 3; ++j) { c->cell_tot[j] = t[j]; c->cell_blocks[j] = C.b[j]; c->cell_nc[j] = C.nc[j]; }
+    c->cell_map = *m;
+    c->cell_inst = instance;
+    if (totals) for (int j = 0; j < 3; ++j) totals[j] = t[j];
+    return GM_OK;
+}
+
+gm_status gm_cells_fill_table(gm_ctx *c, int instance, const gm_importance_map *m, double prior)
+{
+    gm_status s = check_map(c, instance, m);
+    if (s != GM_OK) return s;
+    if (c->cell_inst != instance || c->cell_map.table != m->table || c->cell_map.n_nodes != m->n_nodes ||
+        c->cell_map.lo != m->lo || c->cell_map.hi != m->hi)
+        return fail(GM_ESTATE, "no cell sums of this instance, table and node layout (gm_cells_accumulate first)");
+    if (!(prior >= 0.0) || !(c->cell_tot[1] > 0.0)) return fail(GM_EINVAL, "bad prior or no record weight");
+    s = set_device(c);
+    if (s != GM_OK) return s;
+    const Instance &I = c->inst[instance];
+    double *tab = nullptr;
+    s = map_target(c, instance, m, &tab);
+    if (s != GM_OK) return s;
+    CellArgs C{};
+    C.G = zone_geo_of(I.grid);
+    for (int j = 0; j < 3; ++j) { C.b[j] = c->cell_blocks[j]; C.nc[j] = c->cell_nc[j]; }
+    C.n_nodes = m->n_nodes;
+    C.lo = m->lo; C.hi = m->hi; C.v_shift = map_v_shift(m);
+    C.acc = c->cell_acc.p;
+    C.nz = I.nz;
+    C.zrec = I.zrec.p;
+    C.ratio_all = c->cell_tot[0] / c->cell_tot[1];
+    C.prior_w = prior * c->cell_tot[1] / std::max(c->cell_tot[2], 1.0);     // `prior` records' mean weight
+    C.map = ImpMap{m->kind, m->a, m->b, m->alpha, m->shift};
+    C.neutral = 0.0;
+    C.table = tab;
+    const long long n = (long long)I.nz * m->n_nodes;
+    cells_fill_kernel<<<(unsigned)std::min<long long>((n + 255) / 256, 65536), 256, 0, c->stream>>>(C);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
     return GM_OK;
 }
 

@@ -21,6 +21,7 @@ struct PrepArgs {
     int nz;
     int metric;                  // 0 flat Cartesian, 1 Kerr (modified Kerr-Schild)
     double a_spin, h_slope, r_h;
+    int *max_i1;                 // largest first-axis index of a zone holding plasma (-1: none)
 };
 
 __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
@@ -71,6 +72,7 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
     r[Z_INVNUC] = nuc > 0.0 ? 1.0 / nuc : 0.0;
     P.vol[z] = sqrt_g * P.dx[0] * P.dx[1] * P.dx[2] * P.L3;
     P.emits[z] = (A > 0.0 && !inside) ? 1 : 0;
+    if (ne > 0.0) atomicMax(P.max_i1, z / (P.n[2] * P.n[1]));
     // the FP32 record of the precision form
     float *f = P.zrec32 + (size_t)z * F_STRIDE;
 #pragma unroll

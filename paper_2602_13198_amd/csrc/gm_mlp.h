@@ -132,9 +132,11 @@ GM_D bf16x4 w_load_BT(const short *W, int ld, int k0, int n0)
     return b;
 }
 
-// Forward pass of one 16-row tile; leaves H1 and H2 (post-tanh) in LDS
+// Forward pass of one 16-row tile whose input features come from
+// feat(row, k) (k < kMlpIn, row < n); leaves H1 and H2 (post-tanh) in LDS
 // tiles h1, h2 and returns the output accumulator (cols 0, 1 valid).
-GM_D f32x4 mlp_tile_forward(const MlpArgs &M, long long r0, float *h1, float *h2)
+template <class Feat>
+GM_D f32x4 mlp_tile_forward_f(const MlpArgs &M, long long r0, float *h1, float *h2, Feat feat)
 {
     const int l = lane_id();
     // layer 1: X [16 x 16 (6 used)] x W1 [16 x 64]
@@ -143,7 +145,7 @@ GM_D f32x4 mlp_tile_forward(const MlpArgs &M, long long r0, float *h1, float *h2
     for (int j = 0; j < 4; ++j) {
         int k = 4 * (l >> 4) + j;
         long long r = r0 + (l & 15);
-        float v = (k < kMlpIn && r < M.n) ? M.X[r * kMlpXStride + k] : 0.0f;
+        float v = (k < kMlpIn && r < M.n) ? feat(r, k) : 0.0f;
         ax[j] = f2bf(v);
     }
 #pragma unroll
@@ -176,6 +178,11 @@ GM_D f32x4 mlp_tile_forward(const MlpArgs &M, long long r0, float *h1, float *h2
 #pragma unroll
     for (int j = 0; j < 4; ++j) y[j] += bias;
     return y;
+}
+
+GM_D f32x4 mlp_tile_forward(const MlpArgs &M, long long r0, float *h1, float *h2)
+{
+    return mlp_tile_forward_f(M, r0, h1, h2, [&](long long r, int k) { return M.X[r * kMlpXStride + k]; });
 }
 
 __global__ __launch_bounds__(64 * kMlpWaves) void mlp_forward_kernel(MlpArgs M)

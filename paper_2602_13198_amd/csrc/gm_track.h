@@ -110,6 +110,7 @@ struct TArgs {
     // Kerr (modified Kerr-Schild): spin, polar slope, horizon, capture and
     // record radii, corrector, reciprocal step scales (dx1, dx2, min(dx3, pi dx2))
     double a_spin, h_slope, r_h, r_capture, r_record;
+    double i1_plasma_max;          // no zone with a larger first-axis index holds plasma
     double verlet_tol;
     int verlet_max_it;
     double inv_sc[3];

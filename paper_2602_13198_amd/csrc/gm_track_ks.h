@@ -279,7 +279,10 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 #pragma unroll
                 for (int m = 0; m < 4; ++m) ph.k[m] = kn[m];
             }
-            const int zn = zone_ks(A, P[0], P[1], P[2]);
+            // beyond the outermost plasma zone the point is vacuum: no zone
+            // lookup and no record load (most steps on the way out)
+            const bool beyond = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
+            const int zn = beyond ? -1 : zone_ks(A, P[0], P[1], P[2]);
             Coef c1 = coefficients_at<false, F32>(A, zn, GKerr{K}, kn, ph.n_sc);
             ph.ncoef += 1;
             if (mode != MODE_STEP) {

@@ -57,7 +57,9 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_set_event_log", "gm_event_count", "gm_set_batch",
            "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
            "gm_queue_stats", "gm_set_emission_table", "gm_set_score_weights", "gm_set_tally_mode",
-           "gm_mlp_set_loss", "gm_unload_zones", "gm_mlp_grad_noalloc"]
+           "gm_mlp_set_loss", "gm_unload_zones", "gm_mlp_grad_noalloc", "gm_mlp_fill_table",
+           "gm_cells_accumulate", "gm_cells_fill_table", "gm_expected_roots", "gm_read_table",
+           "gm_set_graph"]
 
 
 class GmGrid(C.Structure):
@@ -74,6 +76,16 @@ class GmZones(C.Structure):
 class GmEmitParams(C.Structure):
     _fields_ = [("n_target", C.c_double), ("nu_min", C.c_double), ("nu_max", C.c_double),
                 ("n_wnodes", C.c_int), ("w_floor_rel", C.c_double), ("seed", C.c_uint64)]
+
+
+class GmImportanceMap(C.Structure):
+    _fields_ = [("table", C.c_int), ("n_nodes", C.c_int), ("lo", C.c_double), ("hi", C.c_double),
+                ("kind", C.c_int), ("a", C.c_double), ("b", C.c_double), ("alpha", C.c_double),
+                ("shift", C.c_double)]
+
+
+TABLE_BIAS, TABLE_EMISSION = 0, 1
+IMP_LINEAR, IMP_MIXTURE = 0, 1
 
 
 class GmTrackParams(C.Structure):
@@ -127,6 +139,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_mlp_set_loss": (i, [vp, i]),
         "gm_unload_zones": (i, [vp, i]),
         "gm_mlp_grad_noalloc": (i, [vp, vp, vp, vp, C.c_int64, vp]),
+        "gm_mlp_fill_table": (i, [vp, i, C.POINTER(GmImportanceMap), i, vp, vp]),
+        "gm_cells_accumulate": (i, [vp, i, C.POINTER(GmImportanceMap), C.POINTER(C.c_int), dp]),
+        "gm_cells_fill_table": (i, [vp, i, C.POINTER(GmImportanceMap), C.c_double]),
+        "gm_expected_roots": (i, [vp, i, C.POINTER(GmEmitParams), dp]),
+        "gm_read_table": (i, [vp, i, i, dp, C.c_int64, C.POINTER(C.c_int)]),
+        "gm_set_graph": (i, [vp, i, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
         "gm_event_count": (i, [vp, C.POINTER(C.c_uint64)]),
         "gm_set_batch": (i, [vp, i]),
         "gm_set_instance_bias": (i, [vp, i, i, C.c_double, C.c_double]),
@@ -243,6 +261,13 @@ class Context:
         G = grid_struct(grid)
         _check(load_library().gm_load_zones(self._h, int(instance), C.byref(G), C.byref(Z)))
         self.shapes[instance] = int(np.prod(grid["n"]))
+
+    def expected_roots(self, emit: dict, instance: int = 0) -> float:
+        """Expected roots of a make with these parameters (nothing drawn)."""
+        P = emit_struct(emit)
+        v = C.c_double(0.0)
+        _check(load_library().gm_expected_roots(self._h, int(instance), C.byref(P), C.byref(v)))
+        return v.value
 
     def unload(self, instance: int = 0):
         """Free an instance's device memory."""
@@ -429,6 +454,36 @@ class Context:
         """0 automatic, 1 per-block LDS tallies, 2 direct HBM tallies."""
         _check(load_library().gm_set_tally_mode(self._h, int(mode)))
 
+    @staticmethod
+    def importance_map(table, n_nodes, lo, hi, kind=IMP_LINEAR, a=1.0, b=0.0, alpha=0.0, shift=0.0):
+        return GmImportanceMap(int(table), int(n_nodes), float(lo), float(hi), int(kind), float(a), float(b),
+                               float(alpha), float(shift))
+
+    def mlp_fill_table(self, instance, imap, output, mu, sd):
+        m = np.ascontiguousarray(mu, dtype=np.float32)
+        s = np.ascontiguousarray(sd, dtype=np.float32)
+        _check(load_library().gm_mlp_fill_table(self._h, int(instance), C.byref(imap), int(output),
+                                                C.c_void_p(m.ctypes.data), C.c_void_p(s.ctypes.data)))
+
+    def cells_accumulate(self, instance, imap, blocks=(8, 8, 8)):
+        """(sum score, sum weight, records) of the event log's records for the map's table."""
+        b = (C.c_int * 3)(*[int(x) for x in blocks])
+        tot = np.zeros(3)
+        _check(load_library().gm_cells_accumulate(self._h, int(instance), C.byref(imap), b, _dp(tot)))
+        return tot
+
+    def read_table(self, instance, table):
+        """The instance's bias (0) or emission (1) table, [nz][nodes]."""
+        nz = self.shapes[instance]
+        nn = C.c_int(0)
+        _check(load_library().gm_read_table(self._h, int(instance), int(table), None, 0, C.byref(nn)))
+        buf = np.zeros(nz * nn.value)
+        _check(load_library().gm_read_table(self._h, int(instance), int(table), _dp(buf), buf.size, None))
+        return buf.reshape(nz, nn.value)
+
+    def cells_fill_table(self, instance, imap, prior=20.0):
+        _check(load_library().gm_cells_fill_table(self._h, int(instance), C.byref(imap), float(prior)))
+
     def sigma_hot_table(self) -> np.ndarray:
         t = np.zeros((64, 256))
         _check(load_library().gm_sigma_hot_table(self._h, _dp(t)))
@@ -446,6 +501,13 @@ class Context:
         _check(load_library().gm_set_instance_bias(self._h, int(instance), int(track.get("bias_mode", 0)),
                                                    float(track.get("bias_value", 1.0)),
                                                    float(track.get("bias_max", 1e6))))
+
+    def set_graph(self, enable: int):
+        """1: launch each root chunk as a captured HIP graph; 0: directly;
+        -1: no change.  Returns (graph launches, instantiations) so far."""
+        a, b = C.c_uint64(0), C.c_uint64(0)
+        _check(load_library().gm_set_graph(self._h, int(enable), C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
 
     def set_batch(self, max_instances: int):
         _check(load_library().gm_set_batch(self._h, int(max_instances)))

@@ -29,8 +29,9 @@ c_b and c_w hold the children and roots to the plain run's budget.
 Score weights are the relative-error weights of the measure, 1 / L(bin) on
 the bins the pilot rounds resolve; the pilot rounds are plain rounds and
 their cost is counted in the form's time.  The host part here prepares
-arrays and drives the library; transport, network training and inference
-run in the library's kernels."""
+training arrays and drives the library; transport, the records' scores,
+network training, the cell sums and both tables (inference over every
+zone and node) run in the library's kernels."""
 from __future__ import annotations
 
 import math
@@ -89,36 +90,29 @@ def rows(zf, zone, ln_e):
 # records
 # ---------------------------------------------------------------------------
 def pilot(ctx, wl, inst, rounds, seed0, n_s, root_stride=4, track=None):
-    """Plain rounds with the event log on: the records (with scores under
-    unit score weights first, to learn the spectrum) are collected after
-    the score weights are set from the pilot's own first round."""
+    """Plain rounds with the event log on.  Round 0 only measures the
+    spectrum, whose resolved bins (relative standard error <= 10 %, >= 100
+    superphotons) get the score weight 1 / L(bin); the next `rounds` rounds
+    log their records into one device buffer, where they stay (the caller
+    reads them if it needs them on the host)."""
     track = dict(track or wl.track)
     emit = dict(wl.emit, n_target=float(n_s))
-    ev_all, spec_acc = [], None
-    # round 0: the spectrum, for the relative-error score weights
     ctx.read_spectrum(inst, reset=True)
     ctx.make_superphotons(dict(emit, seed=seed0), instance=inst)
     ctx.track_scatter(track)
     sp, _ = ctx.read_spectrum(inst, reset=True)
     S1, S2, N = sp[..., 0], sp[..., 1], sp[..., 2]
-    # relative-error weights on the bins this round resolves (relative
-    # standard error <= 10 %, >= 100 superphotons)
     with np.errstate(divide="ignore", invalid="ignore"):
         rse = np.where(S1 > 0, np.sqrt(S2) / S1, np.inf)
     sw = np.where((N >= 100) & (rse <= 0.1), 1.0 / np.maximum(S1, 1e-300), 0.0)
     ctx.set_score_weights(inst, sw)
+    ctx.set_event_log(int(rounds * 6 * n_s) + 100000, root_stride)
     for r in range(rounds):
-        cap = int(6 * n_s) + 100000
-        ctx.set_event_log(cap, root_stride)
         ctx.make_superphotons(dict(emit, seed=seed0 + 1 + r), instance=inst)
         ctx.track_scatter(track)
-        sp, _ = ctx.read_spectrum(inst, reset=True)
-        spec_acc = sp if spec_acc is None else spec_acc + sp
-        ev = ctx.read_event_log()
-        ev_all.append(ev)
-    ctx.set_event_log(0)
+    ctx.read_spectrum(inst, reset=True)
     ctx.set_score_weights(inst, None)
-    return np.concatenate(ev_all), sw, spec_acc
+    return sw
 
 
 def split_records(ev, root_stride):
@@ -127,54 +121,6 @@ def split_records(ev, root_stride):
     ok = (ev["w"] > 0) & np.isfinite(ev["w"]) & np.isfinite(ev["score"])
     ev = ev[ok]
     return ev[ev["gen"] > 0], ev[ev["gen"] == 0]
-
-
-# ---------------------------------------------------------------------------
-# the adaptive form: cell x energy-node ratio estimates
-# ---------------------------------------------------------------------------
-class CellTable:
-    """Importance per (coarse cell, ln-energy node) from summed scores over
-    summed weights, shrunk towards the overall ratio with `prior` records'
-    worth of weight.  Cells are blocks of (c1, c2, c3) zones."""
-
-    def __init__(self, wl, blocks=(8, 8, 8), n_nodes=16, lo=LN_EPS[0], hi=LN_EPS[1], prior=20.0):
-        g = wl.grid
-        self.n = g["n"]
-        self.blocks = blocks
-        self.nc = [max(1, -(-self.n[j] // blocks[j])) for j in range(3)]
-        (i1, i2, i3), _, _ = zone_geometry(wl)
-        self.cell_of_zone = ((i1 // blocks[0]) * self.nc[1] + (i2 // blocks[1])) * self.nc[2] + (i3 // blocks[2])
-        self.n_cells = self.nc[0] * self.nc[1] * self.nc[2]
-        self.n_nodes, self.lo, self.hi, self.prior = n_nodes, lo, hi, prior
-
-    def node(self, ln_e):
-        p = (ln_e - self.lo) / (self.hi - self.lo) * (self.n_nodes - 1)
-        return np.clip(np.rint(p), 0, self.n_nodes - 1).astype(np.int64)
-
-    def fit(self, zone, ln_e, w, score):
-        """ln importance [n_cells][n_nodes] (NaN where no record)."""
-        idx = self.cell_of_zone[zone] * self.n_nodes + self.node(ln_e)
-        m = self.n_cells * self.n_nodes
-        sw = np.bincount(idx, weights=w, minlength=m)
-        ss = np.bincount(idx, weights=score, minlength=m)
-        cnt = np.bincount(idx, minlength=m)
-        tot = ss.sum() / max(w.sum(), 1e-300)
-        wbar = w.sum() / max(len(w), 1)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            ratio = (ss + self.prior * wbar * tot) / (sw + self.prior * wbar)
-        ratio = np.where(cnt > 0, ratio, np.nan)
-        self.ln_I = np.log(np.maximum(ratio, 1e-300)).reshape(self.n_cells, self.n_nodes)
-        self.ln_tot = math.log(max(tot, 1e-300))
-        return self.ln_I
-
-    def zone_table(self, n_zone_nodes, lo, hi):
-        """Per zone [nz][n_zone_nodes] ln importance on nodes over [lo, hi]
-        (cells without records take the overall value)."""
-        x = np.linspace(lo, hi, n_zone_nodes)
-        k = self.node(x)
-        t = self.ln_I[:, k]
-        t = np.where(np.isfinite(t), t, self.ln_tot)
-        return t[self.cell_of_zone]
 
 
 # ---------------------------------------------------------------------------
@@ -242,111 +188,67 @@ class Network:
 
 
 # ---------------------------------------------------------------------------
-# tables from importances
+# tables (built on the device by the library)
 # ---------------------------------------------------------------------------
-def window_table(ln_I_sc_zone, sc, sc_lnI, b_plain, b_max):
-    """ln(c_b I) per zone and node, c_b chosen so that the mean bias over the
-    pilot's scattering opportunities equals b_plain (the parent's weight at
-    a pilot scattering is b_plain times its child's)."""
-    w_par = sc["w"] * b_plain
-    lo, hi = -60.0, 60.0
-    for _ in range(100):
-        mid = 0.5 * (lo + hi)
-        b = np.clip(w_par * np.exp(mid + sc_lnI), 1.0, b_max)
-        if b.mean() > b_plain:
-            hi = mid
-        else:
-            lo = mid
-    return ln_I_sc_zone + 0.5 * (lo + hi)
-
-
-def emission_modulation(ctx, wl, inst, ln_I_em_zone, ln_I_mean, n_nodes, n_s, alpha=0.5):
-    """Defensive emission proposal: zone i's superphotons at nu get the
-    weight w(nu) / [(1 - alpha) + alpha I_em(zone, nu) / I_mean] (times the
-    constant that keeps the expected roots at the plain run's), I_mean the
-    plain run's mean importance per unit weight.  Where the importance is
-    high the proposal emits up to alpha I/I_mean times more roots; nowhere
-    does it emit fewer than 1 - alpha of the plain number, which bounds the
-    weights by w / (1 - alpha) however wrong the estimate.  The expected
-    count scales exactly with the constant, so it is found from one make at
-    a constant low enough that the make allocates almost nothing."""
-    e = wl.emit
-    lo, hi = math.log(e["nu_min"]), math.log(e["nu_max"])
-    nb0 = float(ctx.read_emission(inst)["nbar"].sum())
-    ratio = np.exp(np.clip(ln_I_em_zone - ln_I_mean, -50.0, 50.0))
-    m = np.log((1.0 - alpha) + alpha * ratio)
-    shift = m.max() + 20.0
-    ctx.set_emission_table(inst, m - shift, lo, hi)
-    ctx.make_superphotons(dict(e, n_target=float(n_s), seed=1), instance=inst)
-    nb1 = float(ctx.read_emission(inst)["nbar"].sum())
-    m = m - shift + math.log(nb0 / max(nb1, 1e-300))
-    ctx.set_emission_table(inst, m, lo, hi)
-    return m, lo, hi
-
-
-def build_tables(ctx, wl, inst, ev, root_stride, b_plain, b_max, n_s, mode, net_seed=1, log=None,
-                 use_bias=True, use_emission=True, alpha=0.5):
+def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=True, use_emission=True,
+                 alpha=0.5, nodes=16, root_stride=4):
     """Tables of the adaptive ("cells") or learned ("network") form from the
-    pilot records; sets the instance's bias (window) and emission tables."""
-    sc, em = split_records(ev, root_stride)
-    nodes = 16
-    zf = zone_features(wl)
-    nz = wl.n_zones
-    ln_nodes_eps = np.linspace(LN_EPS[0], LN_EPS[1], nodes)
+    records in the context's event log, built on the device; sets the
+    instance's weight-window bias table and defensive emission table.
+    Window bias: ln(c_b I_sc) with c_b = records / summed score, so that
+    the mean bias over the pilot's scattering opportunities is the plain b
+    (the parent's weight at a pilot scattering is b times its child's, and
+    the sum over records of w_child I_sc is the summed score).  Emission:
+    mixture with I_em / I_mean, I_mean = summed score / summed weight of the
+    emission records, the constant fixed by the expected roots."""
+    info, t0 = {}, time.perf_counter()
     e = wl.emit
     lo_nu, hi_nu = math.log(e["nu_min"]), math.log(e["nu_max"])
-    ln_nodes_nu = np.linspace(lo_nu, hi_nu, nodes)
-    # emission records carry the fluid-frame energy of the emitted photon;
-    # the emission table is in ln nu of the fluid frame (the comoving emitter)
-    em_lnnu = np.log(em["eps"] * MEC2_OVER_H)
-    info = {"scatter_records": int(len(sc)), "emission_records": int(len(em))}
-    t_sc = sc["score"] / sc["w"]
-    t_em = em["score"] / em["w"]
-    n_sc_mean, n_em_mean = max(t_sc.mean(), 1e-300), max(t_em.mean(), 1e-300)
+    emit_round = dict(e, n_target=float(n_s))
+    nb0 = ctx.expected_roots(emit_round, inst)
+    m_bias = GM.Context.importance_map(GM.TABLE_BIAS, nodes, LN_EPS[0], LN_EPS[1], GM.IMP_LINEAR)
+    m_em = GM.Context.importance_map(GM.TABLE_EMISSION, nodes, lo_nu, hi_nu, GM.IMP_MIXTURE, alpha=alpha)
     if mode == "cells":
-        ct = CellTable(wl, n_nodes=nodes)
-        ct.fit(sc["zone"], np.log(sc["eps"]), sc["w"], sc["score"])
-        sc_lnI = ct.ln_I[ct.cell_of_zone[sc["zone"]], ct.node(np.log(sc["eps"]))]
-        sc_lnI = np.where(np.isfinite(sc_lnI), sc_lnI, ct.ln_tot)
-        lnI_sc = ct.zone_table(nodes, LN_EPS[0], LN_EPS[1])
-        ce = CellTable(wl, n_nodes=nodes, lo=lo_nu, hi=hi_nu)
-        ce.fit(em["zone"], em_lnnu, em["w"], em["score"])
-        lnI_em = ce.zone_table(nodes, lo_nu, hi_nu)
+        tot_sc = ctx.cells_accumulate(inst, m_bias)
+        if use_bias:
+            m_bias.b = math.log(tot_sc[2] / max(tot_sc[0], 1e-300))
+            ctx.cells_fill_table(inst, m_bias)
+        tot_em = ctx.cells_accumulate(inst, m_em)
+        m_em.b = -math.log(max(tot_em[0], 1e-300) / tot_em[1])
+        fill = lambda m: ctx.cells_fill_table(inst, m)       # noqa: E731
+        info["records"] = [int(tot_sc[2]), int(tot_em[2])]
     else:
-        X = np.concatenate([rows(zf, sc["zone"], np.log(sc["eps"])), rows(zf, em["zone"], em_lnnu - math.log(MEC2_OVER_H))])
+        ev = ctx.read_event_log()
+        info["read_s"] = time.perf_counter() - t0
+        sc, em = split_records(ev, root_stride)
+        del ev
+        zf = zone_features(wl)
+        X = np.concatenate([rows(zf, sc["zone"], np.log(sc["eps"])), rows(zf, em["zone"], np.log(em["eps"]))])
+        t_sc, t_em = sc["score"] / sc["w"], em["score"] / em["w"]
+        m_sc, m_em_mean = max(t_sc.mean(), 1e-300), max(t_em.mean(), 1e-300)
         T = np.zeros((len(X), 2))
-        C = np.zeros((len(X), 2))
-        T[:len(sc), 0] = t_sc / n_sc_mean
-        C[:len(sc), 0] = 1.0
-        T[len(sc):, 1] = t_em / n_em_mean
-        C[len(sc):, 1] = 1.0
+        Cw = np.zeros((len(X), 2))
+        T[:len(sc), 0], Cw[:len(sc), 0] = t_sc / m_sc, 1.0
+        T[len(sc):, 1], Cw[len(sc):, 1] = t_em / m_em_mean, 1.0
         net = Network(seed=net_seed)
-        t0 = time.perf_counter()
-        hist = net.fit(ctx, X, T, C)
-        info["train_s"] = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        hist = net.fit(ctx, X, T, Cw)
+        info["train_s"] = time.perf_counter() - t1
         info["loss_first_last"] = [hist[0][1], hist[-1][1]]
-        y_sc = net.predict(ctx, rows(zf, sc["zone"], np.log(sc["eps"])))[:, 0]
-        sc_lnI = y_sc + math.log(n_sc_mean)
-        # tables on zones with plasma only (others never scatter or emit)
-        on = np.flatnonzero(wl.n_e > 0)
-        zon = np.repeat(on, nodes)
-        Xs = rows(zf, zon, np.tile(ln_nodes_eps, len(on)))
-        ys = net.predict(ctx, Xs)
-        lnI_sc = np.full((nz, nodes), math.log(n_sc_mean))
-        lnI_sc[on] = ys[:, 0].reshape(len(on), nodes) + math.log(n_sc_mean)
-        emits = np.flatnonzero(wl.B > 0)
-        zem = np.repeat(emits, nodes)
-        Xe = rows(zf, zem, np.tile(ln_nodes_nu - math.log(MEC2_OVER_H), len(emits)))
-        ye = net.predict(ctx, Xe)
-        lnI_em = np.full((nz, nodes), math.log(n_em_mean))
-        lnI_em[emits] = ye[:, 1].reshape(len(emits), nodes) + math.log(n_em_mean)
-    if use_bias:
-        wt = window_table(lnI_sc, sc, sc_lnI, b_plain, b_max)
-        ctx.set_bias_table(inst, wt, LN_EPS[0], LN_EPS[1])
-        info["bias_table_range"] = [float(np.min(wt)), float(np.max(wt))]
+        info["records"] = [int(len(sc)), int(len(em))]
+        if use_bias:
+            # ln I = y + ln(mean t); c_b = records / summed score
+            m_bias.b = math.log(m_sc) + math.log(len(sc) / max(sc["score"].sum(), 1e-300))
+            ctx.mlp_fill_table(inst, m_bias, 0, net.mu, net.sd)
+        m_em.b = math.log(m_em_mean) - math.log(max(em["score"].sum(), 1e-300) / em["w"].sum())
+        fill = lambda m: ctx.mlp_fill_table(inst, m, 1, net.mu, net.sd)   # noqa: E731
     if use_emission:
-        m, _, _ = emission_modulation(ctx, wl, inst, lnI_em, math.log(n_em_mean), nodes, n_s, alpha)
-        info["emission_table_range"] = [float(np.min(m)), float(np.max(m))]
+        fill(m_em)
+        nb1 = ctx.expected_roots(emit_round, inst)
+        m_em.shift = math.log(nb0 / max(nb1, 1e-300))
+        fill(m_em)
+        info["emission_shift"] = m_em.shift
+    info["tables_s"] = time.perf_counter() - t0
     return info
 
 
@@ -403,11 +305,10 @@ def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rou
             torch.cuda.synchronize()
             ta = time.perf_counter()
             try:
-                ev, sw, _ = pilot(ctx, wl, inst, pilot_rounds, 300000 + 1000 * k, n_round, root_stride)
-                info = build_tables(ctx, wl, inst, ev, root_stride, b_plain, b_max, n_round, form,
-                                    net_seed=1 + k, log=log, use_bias=use_bias, use_emission=use_em,
-                                    alpha=alpha)
-                del ev
+                pilot(ctx, wl, inst, pilot_rounds, 300000 + 1000 * k, n_round, root_stride)
+                info = build_tables(ctx, wl, inst, b_plain, b_max, n_round, form, net_seed=1 + k,
+                                    use_bias=use_bias, use_emission=use_em, alpha=alpha, root_stride=root_stride)
+                ctx.set_event_log(0)
                 torch.cuda.synchronize()
                 t_prep = time.perf_counter() - ta
                 over = dict(bias_mode=GM.BIAS_WINDOW, bias_max=b_max) if use_bias else None

@@ -1,0 +1,127 @@
+"""The device-side tables of the importance-driven forms, through the C ABI:
+the network table against the oracle network evaluated on the same zone
+features (BF16 operands emulated), the cell tables against the plain sums
+of the event records written out with numpy, the defensive mixture, and
+the expected-roots call against the counts of a real make."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from paper_2602_13198_amd import importance as IM
+from paper_2602_13198_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_13198_amd import gm as _gm
+    _gm.load_library()
+    return _gm
+
+
+def _wl():
+    return W.corona_torus(n1=24, n2=12, n3=8, n_target=3000, seed=71)
+
+
+def forward_bf16(p, Z):
+    Wd = OM.unpack(p)
+    x = OM.bf16(Z[:, :6])
+    h1 = np.tanh(x @ OM.bf16(Wd["W1"]) + Wd["b1"])
+    h2 = np.tanh(OM.bf16(h1) @ OM.bf16(Wd["W2"]) + Wd["b2"])
+    return OM.bf16(h2) @ OM.bf16(Wd["W3"]) + Wd["b3"]
+
+
+@pytest.mark.parametrize("table", [0, 1], ids=["bias", "emission"])
+def test_network_table(gm, table):
+    wl = _wl()
+    c = gm.Context(0)
+    c.load_zones(wl)
+    p = OM.init(3).astype(np.float32)
+    p[-2:] = [0.4, -0.7]
+    c.mlp_set_params(p)
+    zf = IM.zone_features(wl)
+    mu = np.array([-1.0, 10.0, -5.0, 0.0, 2.0, 0.0], np.float32)
+    sd = np.array([1.5, 4.0, 8.0, 10.0, 1.5, 0.6], np.float32)
+    n = 7
+    if table == 0:
+        lo, hi, shift = math.log(1e-12), math.log(1e6), 0.0
+        m = gm.Context.importance_map(gm.TABLE_BIAS, n, lo, hi, gm.IMP_LINEAR, a=1.5, b=-0.3, shift=0.2)
+    else:
+        lo, hi = math.log(1e8), math.log(1e16)
+        shift = math.log(8.187105776823886e-07 / 6.62607015e-27)       # ln nu -> ln eps
+        m = gm.Context.importance_map(gm.TABLE_EMISSION, n, lo, hi, gm.IMP_MIXTURE, a=1.0, b=0.5, alpha=0.6, shift=-0.1)
+    c.mlp_fill_table(0, m, table, mu, sd)
+    tab = c.read_table(0, table)
+    c.close()
+    on = np.flatnonzero(wl.n_e > 0)
+    v = np.linspace(lo, hi, n)
+    zone = np.repeat(on, n)
+    X = IM.rows(zf, zone, np.tile(v - shift, len(on)))
+    Z = (X[:, :6] - mu) / sd
+    y = forward_bf16(p.astype(np.float64), Z)[:, table]
+    if table == 0:
+        ref = 1.5 * y - 0.3 + 0.2
+    else:
+        ref = np.log(0.4 + 0.6 * np.exp(y + 0.5)) - 0.1
+    got = tab[on].reshape(-1)
+    assert np.max(np.abs(got - ref)) < 3e-2, np.max(np.abs(got - ref))
+    assert np.all(tab[wl.n_e <= 0] == 0.0)
+
+
+def test_cell_tables_and_expected_roots(gm):
+    """Cell sums and ratios against numpy on the same records; the expected
+    roots equal the make's summed expected counts, with and without the
+    emission table."""
+    wl = _wl()
+    c = gm.Context(0)
+    c.load_zones(wl)
+    c.make_superphotons(wl.emit)
+    nb_make = c.read_emission()["nbar"].sum()
+    assert c.expected_roots(wl.emit) == pytest.approx(nb_make, rel=1e-12)
+    c.make_superphotons(wl.emit)
+    c.set_event_log(2_000_000, 2)
+    c.set_score_weights(0, np.random.default_rng(1).uniform(0.5, 1.5, (wl.track["n_theta"], wl.track["n_nu"])))
+    c.track_scatter(wl.track)
+    ev = c.read_event_log()
+    n = 6
+    lo, hi = math.log(1e-12), math.log(1e6)
+    mb = gm.Context.importance_map(gm.TABLE_BIAS, n, lo, hi, gm.IMP_LINEAR, a=1.0, b=0.7)
+    blocks = (4, 3, 2)
+    tot = c.cells_accumulate(0, mb, blocks)
+    c.cells_fill_table(0, mb, prior=5.0)
+    tab = c.read_table(0, 0)
+    # numpy: scattering records, nearest node of ln eps, cell of the zone
+    sc = ev[(ev["gen"] > 0) & (ev["w"] > 0) & (ev["eps"] > 0)]
+    n1, n2, n3 = wl.grid["n"]
+    nc = [-(-n1 // 4), -(-n2 // 3), -(-n3 // 2)]
+    z = sc["zone"]
+    i1, i2, i3 = z // (n2 * n3), (z // n3) % n2, z % n3
+    cell = ((i1 // 4) * nc[1] + i2 // 3) * nc[2] + i3 // 2
+    node = np.clip(np.rint((np.log(sc["eps"]) - lo) / (hi - lo) * (n - 1)), 0, n - 1).astype(int)
+    idx = cell * n + node
+    m = nc[0] * nc[1] * nc[2] * n
+    S = np.bincount(idx, sc["score"], m)
+    Wt = np.bincount(idx, sc["w"], m)
+    N = np.bincount(idx, minlength=m)
+    np.testing.assert_allclose(tot, [S.sum(), Wt.sum(), N.sum()], rtol=1e-12)
+    ratio_all = S.sum() / Wt.sum()
+    pw = 5.0 * Wt.sum() / N.sum()
+    on = np.flatnonzero(wl.n_e > 0)
+    zi1, zi2, zi3 = on // (n2 * n3), (on // n3) % n2, on % n3
+    zcell = ((zi1 // 4) * nc[1] + zi2 // 3) * nc[2] + zi3 // 2
+    for k in range(n):
+        j = zcell * n + k
+        r = np.where(N[j] > 0, (S[j] + pw * ratio_all) / (Wt[j] + pw), ratio_all)
+        np.testing.assert_allclose(tab[on, k], np.log(r) + 0.7, rtol=0, atol=1e-10)
+    # the emission table changes the expected roots by the mapped factor
+    me = gm.Context.importance_map(gm.TABLE_EMISSION, n, math.log(1e8), math.log(1e16), gm.IMP_LINEAR, a=0.0, b=0.5)
+    c.cells_accumulate(0, me, blocks)
+    c.cells_fill_table(0, me, prior=5.0)
+    assert c.expected_roots(wl.emit) == pytest.approx(nb_make * math.exp(0.5), rel=1e-11)
+    c.close()

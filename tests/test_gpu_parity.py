@@ -344,3 +344,42 @@ def test_bench_configuration_sampled(gm, oracle_lib):
         assert len(bad) <= max(1, 1e-3 * m), describe(sub, ora, bad)
         wr, er = ledger_residuals(leds[i])
         assert abs(wr) < 1e-12 and abs(er) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["flat_batched", "kerr"])
+def test_graph_launch_equals_direct(gm, kind):
+    """Root chunks launched as captured HIP graphs give bitwise the photon
+    histories of direct launches, call after call (the graph is updated in
+    place when only the kernel arguments change: other seeds, other root
+    counts), with eager reads and synchronisations between the calls."""
+    if kind == "kerr":
+        wls = [W.torus(n1=64, n2=32, step_h=0.125, n_target=1200, seed=91)]
+    else:
+        wls = [W.scattering_sphere(t, n_target=2000, seed=92, instance=i) for i, t in enumerate((1e-2, 1e-1))]
+    runs = {}
+    for mode in (0, 1):
+        c = gm.Context(0)
+        c.set_graph(mode)
+        for i, wl in enumerate(wls):
+            c.load_zones(wl, i)
+            c.set_instance_bias(i, wl.track)
+        out = []
+        for call, seed in enumerate((5, 6, 7)):
+            for i, wl in enumerate(wls):
+                c.make_superphotons(dict(wl.emit, seed=seed, n_target=wl.emit["n_target"] * (1 + call)), i)
+            c.set_trace(400000)
+            st = c.track_scatter(wls[0].track)
+            tr = np.sort(c.read_trace(), order=["s2", "s1", "s0"])
+            specs = [c.read_spectrum(i, reset=True)[0] for i in range(len(wls))]
+            out.append((st, tr, specs))
+        launches, inst = c.set_graph(-1)
+        c.close()
+        if mode == 1:
+            assert launches >= 3 and inst >= 1
+        runs[mode] = out
+    for (s0, t0, p0), (s1, t1, p1) in zip(runs[0], runs[1]):
+        assert len(t0) == len(t1) > 500
+        assert np.array_equal(t0.view(np.uint8), t1.view(np.uint8))
+        np.testing.assert_array_equal(s0, s1)
+        for a, b in zip(p0, p1):
+            np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
