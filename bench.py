@@ -299,6 +299,38 @@ def timed_steps(ctx, wl, inst, steps, seed0, precision=0):
     return dt, tot, ms, launches
 
 
+def graph_form(ctx, wl, inst, rounds=12, div=32, log=lambda m: None):
+    """Whole-step time with each root chunk launched directly and as a
+    captured HIP graph, on the headline workload at N_s / div per round (the
+    rounds of the time-to-1 % measurement, where launches are shortest) and
+    at full N_s."""
+    import torch
+    out = {}
+    for name, n_s, reps in (("round_n_s_over_%d" % div, wl.emit["n_target"] / div, rounds),
+                            ("full_n_s", wl.emit["n_target"], 2)):
+        res = {}
+        for mode in (0, 1, 0, 1):           # alternated, the second of each kept
+            ctx.set_graph(mode)
+            emit = dict(wl.emit, n_target=n_s)
+            ctx.make_superphotons(dict(emit, seed=8000), instance=inst)
+            ctx.track_scatter(wl.track)
+            ctx.read_spectrum(inst, reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r in range(reps):
+                ctx.make_superphotons(dict(emit, seed=8001 + r), instance=inst)
+                ctx.track_scatter(wl.track)
+                ctx.read_spectrum(inst, reset=True)
+            torch.cuda.synchronize()
+            res["graph" if mode else "direct"] = (time.perf_counter() - t0) / reps * 1e3
+            log("graph form: %s %s %.2f ms per step" % (name, "graph" if mode else "direct",
+                                                        res["graph" if mode else "direct"]))
+        out[name] = {"ms_per_step_direct": res["direct"], "ms_per_step_graph": res["graph"],
+                     "graph_speedup": res["direct"] / res["graph"]}
+    ctx.set_graph(0)
+    return out
+
+
 def flat_sphere_form(ctx, base_inst, steps=5):
     """The flat scattering synchrotron sphere (32^3 Cartesian zones, Theta_e
     = 4, tau_T in {1e-3, 1e-2, 1e-1} with b = 1/tau_T, N_s = 1e6 each, three
@@ -344,7 +376,7 @@ def flat_sphere_form(ctx, base_inst, steps=5):
             "tracker_algorithmic_tflops": fl / (ms * 1e-3) / 1e12 if ms else None}
 
 
-def survey_form(ctx, steps=2, n_inst=64):
+def survey_form(ctx, steps=2, n_inst=64, log=lambda m: None):
     """The batched survey: 64 tori (spins -0.5 .. 0.9375, R_high 1 .. 160,
     M_unit log-uniform over two decades, N_s log-uniform on [1e5, 1e7])
     on 192x96x96 grids, FP32 emissivity, tracked in shared launches with
@@ -358,6 +390,7 @@ def survey_form(ctx, steps=2, n_inst=64):
         ctx.set_instance_bias(i, dict(wl.track))
     torch.cuda.synchronize()
     t_load = time.perf_counter() - t0
+    log("survey: %d instances loaded in %.2f s" % (len(wls), t_load))
     ctx.set_batch(64)
     track = dict(wls[0].track, precision=1)
 
@@ -368,14 +401,17 @@ def survey_form(ctx, steps=2, n_inst=64):
         for i in range(len(wls)):
             ctx.read_spectrum(i, reset=True)
         return st
-    step(7000)
+    tw = time.perf_counter()
+    st = step(7000)
     torch.cuda.synchronize()
+    log("survey: warm-up step %.2f s, %d superphotons" % (time.perf_counter() - tw, int(st[0] + st[1])))
     t1 = time.perf_counter()
     tot = None
     for s in range(steps):
         st = step(7100 + 100 * s)
         tot = st if tot is None else tot + st
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("survey: step %d done at %.2f s" % (s, time.perf_counter() - t1))
     dt = time.perf_counter() - t1
     for i in range(len(wls)):
         ctx.unload(i)
@@ -432,6 +468,7 @@ def main():
     ap.add_argument("--refill-min", type=int, default=0, help="idle lanes before a refill; 0 = timed trial")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--survey-inst", type=int, default=64, help="tori of the survey form (at most 64)")
     ap.add_argument("--ttx-seeds", type=int, default=3, help="seeds of the time-to-1%% measurement (0 = skip)")
     ap.add_argument("--ttx-ref-rounds", type=int, default=24, help="N_s rounds of the plain reference")
     ap.add_argument("--ttx-round-div", type=int, default=32, help="measured rounds are N_s / this")
@@ -580,11 +617,13 @@ def main():
                                                round_div=args.ttx_round_div, log=log)
         print(json.dumps({"partial": True, "time_to_1pct": out["time_to_1pct"]}), file=sys.stderr, flush=True)
     if not args.no_forms:
+        out["forms"]["hip_graph"] = graph_form(ctx, wl, 0, log=log)
+        log("graph form done")
         out["forms"]["flat_scattering_sphere"] = flat_sphere_form(ctx, 1)
-        log("flat sphere done")
+        log("flat sphere: %.4g superphotons/s" % out["forms"]["flat_scattering_sphere"]["value"])
         ctx.unload(0)
-        out["forms"]["survey"] = survey_form(ctx)
-        log("survey done")
+        out["forms"]["survey"] = survey_form(ctx, n_inst=args.survey_inst, log=log)
+        log("survey: %.4g superphotons/s" % out["forms"]["survey"]["value"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     ctx.close()

@@ -91,13 +91,17 @@ GM_HD void kerr_metric(double a, double hs, double x1, double x2, KMetric &K)
     K.g00 = g[0].v; K.g01 = g[1].v; K.g03 = g[2].v; K.g11 = g[3].v; K.g13 = g[4].v; K.g22 = g[5].v; K.g33 = g[6].v;
 #pragma unroll
     for (int i = 0; i < 7; ++i) { K.d1[i] = g[i].d1; K.d2[i] = g[i].d2; }
+    // inverse: one reciprocal of Sigma r^2 dth^2 serves four quotients; the
+    // sin^2 quotient keeps its own division (infinite on the axis, as before)
     double D = r * r - 2.0 * r + a * a;
     double Sv = S.v, z = Z.v;
+    const double q = 1.0 / (Sv * r * r * dth * dth);
+    const double iSr2 = q * (dth * dth);                   // 1 / (Sigma r^2)
     K.u00 = -(1.0 + z);
-    K.u01 = z / r;
-    K.u11 = D / (Sv * r * r);
-    K.u13 = a / (Sv * r);
-    K.u22 = 1.0 / (Sv * dth * dth);
+    K.u01 = z * (iSr2 * Sv * r);                           // z / r
+    K.u11 = D * iSr2;
+    K.u13 = a * (iSr2 * r);                                // a / (Sigma r)
+    K.u22 = q * (r * r);                                   // 1 / (Sigma dth^2)
     K.u33 = 1.0 / (Sv * S2.v);
 }
 

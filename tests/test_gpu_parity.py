@@ -353,7 +353,7 @@ def test_graph_launch_equals_direct(gm, kind):
     place when only the kernel arguments change: other seeds, other root
     counts), with eager reads and synchronisations between the calls."""
     if kind == "kerr":
-        wls = [W.torus(n1=64, n2=32, step_h=0.125, n_target=1200, seed=91)]
+        wls = [W.torus(n1=64, n2=32, step_h=0.125, n_target=4000, seed=91)]
     else:
         wls = [W.scattering_sphere(t, n_target=2000, seed=92, instance=i) for i, t in enumerate((1e-2, 1e-1))]
     runs = {}
