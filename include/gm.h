@@ -53,23 +53,28 @@ typedef enum {
 #define GM_METRIC_KS_MKS         1   /* Kerr, Kerr-Schild in modified coordinates:
                                         r = exp(x1), theta = pi x2 + (1-h)/2 sin(2 pi x2),
                                         phi = x3, lengths in r_g = ell              */
+#define GM_METRIC_FLAT_SPH       2   /* flat spacetime in the same (ln r, x2, phi)
+                                        coordinates, lengths in ell (the sphere
+                                        tests of the paper's Tests section: a grid
+                                        in t, log r, theta, phi); a_spin must be 0,
+                                        no horizon, photons recorded at r_record    */
 
 typedef struct {
     int    metric;          /* GM_METRIC_*                                        */
     int    n[3];            /* zones per coordinate, each >= 1                    */
     double x_start[3];      /* lower coordinate edge                              */
     double dx[3];           /* coordinate zone width, > 0                         */
-    double a_spin;          /* Kerr spin |a| < 1 (KS only)                        */
-    double h_slope;         /* modified-coordinate polar slope h (KS only)        */
+    double a_spin;          /* Kerr spin |a| < 1 (KS); 0 (flat spherical)         */
+    double h_slope;         /* polar slope h in (0, 1] (KS, flat spherical)       */
     double L_unit_cm;       /* length unit ell in cm, > 0                         */
-    double r_record;        /* record radius in ell (KS only)                     */
+    double r_record;        /* record radius in ell (KS, flat spherical)          */
 } gm_grid;
 
 /* Zone plasma in double precision, zone index z = (i1*n2 + i2)*n3 + i3.
  * ucon and bcon are [4][nzones] (component-major).  on_device = 1 means the
  * pointers are device pointers, else host pointers.  Every zone needs finite
  * n_e >= 0, B >= 0 and theta_e; zones with n_e > 0 need theta_e > 0 and
- * u^t > 0, and in Kerr a timelike u at the zone centre.  These checks run on
+ * u^t > 0, and on (ln r, x2, phi) grids a timelike u at the zone centre.  These checks run on
  * the host for host inputs and in a kernel for device inputs; a failure is
  * GM_EINVAL with the first bad zone named.  bcon gives only the field
  * direction; its normalisation is ignored. */

@@ -36,6 +36,9 @@ extern "C" {
 /* ---- metric / grid --------------------------------------------------- */
 #define GMO_METRIC_MINKOWSKI_CART 0   /* x^i Cartesian, Gamma == 0          */
 #define GMO_METRIC_KS_MKS         1   /* Kerr-Schild in modified coordinates */
+#define GMO_METRIC_FLAT_SPH       2   /* flat spacetime, x = (t, ln r, x2, phi),
+                                         theta(x2) as in the modified coordinates;
+                                         a_spin must be 0, no horizon           */
 
 typedef struct {
     int    metric;
@@ -43,9 +46,9 @@ typedef struct {
     double x_start[3];      /* lower coordinate edge of the grid           */
     double dx[3];           /* coordinate zone width                       */
     double a_spin;          /* KS only: dimensionless spin                 */
-    double h_slope;         /* KS only: MKS polar slope parameter          */
+    double h_slope;         /* KS, SPH: polar slope parameter              */
     double L_unit_cm;       /* length unit ell in cm                       */
-    double r_record;        /* KS only: record radius in ell               */
+    double r_record;        /* KS, SPH: record radius in ell               */
 } gmo_grid;
 
 /* Zone plasma, row-major zone index z = (i1*n2 + i2)*n3 + i3. */

@@ -14,6 +14,10 @@
  *   S = r^2 + a^2 cos^2th, z = 2r/S,
  * and the modified-coordinate metric is g_mn = g^KS_mn (dX^m/dx^m)(dX^n/dx^n)
  * with the diagonal Jacobian (1, r, dth/dx2, 1).
+ * Flat spherical (the sphere tests of the paper, coordinates t, ln r, theta,
+ * phi): the Minkowski line element in spherical coordinates,
+ *   ds^2 = -dt^2 + dr^2 + r^2 dth^2 + r^2 sin^2th dph^2,
+ * with the same diagonal Jacobian (1, r, dth/dx2, 1).
  * Christoffel symbols come from the definition
  *   Gamma^m_ab = 1/2 g^mn (d_a g_nb + d_b g_na - d_n g_ab)
  * with the metric derivatives taken by complex-step differentiation
@@ -59,6 +63,26 @@ static void ks_mks_gcov_c(double a, double hs, double complex x1, double complex
             gm[m][n] = gk[m][n] * J[m] * J[n];
 }
 
+static void sph_gcov_c(double hs, double complex x1, double complex x2, double complex gm[4][4])
+{
+    double complex r = cexp(x1);
+    double complex th = M_PI * x2 + 0.5 * (1.0 - hs) * csin(2.0 * M_PI * x2);
+    double complex dth = M_PI * (1.0 + (1.0 - hs) * ccos(2.0 * M_PI * x2));
+    double complex s = csin(th);
+    memset(gm, 0, 16 * sizeof(double complex));
+    gm[0][0] = -1.0;
+    gm[1][1] = r * r;                    /* dr^2 with dr = r dx1 */
+    gm[2][2] = r * r * dth * dth;
+    gm[3][3] = r * r * s * s;
+}
+
+/* Metric of the curved-coordinate grids at complex (x1, x2). */
+static void gcov_c(const gmo_grid *grid, double complex x1, double complex x2, double complex gm[4][4])
+{
+    if (grid->metric == GMO_METRIC_FLAT_SPH) sph_gcov_c(grid->h_slope, x1, x2, gm);
+    else ks_mks_gcov_c(grid->a_spin, grid->h_slope, x1, x2, gm);
+}
+
 void gmo_gcov(const gmo_grid *grid, const double x[4], double gcov[4][4])
 {
     memset(gcov, 0, 16 * sizeof(double));
@@ -67,7 +91,7 @@ void gmo_gcov(const gmo_grid *grid, const double x[4], double gcov[4][4])
         return;
     }
     double complex gm[4][4];
-    ks_mks_gcov_c(grid->a_spin, grid->h_slope, x[1], x[2], gm);
+    gcov_c(grid, x[1], x[2], gm);
     for (int m = 0; m < 4; ++m)
         for (int n = 0; n < 4; ++n) gcov[m][n] = creal(gm[m][n]);
 }
@@ -140,7 +164,7 @@ void gmo_christoffel(const gmo_grid *grid, const double x[4], double Gam[4][4][4
         double complex x1 = x[1], x2 = x[2];
         if (c == 1) x1 += I * hstep; else x2 += I * hstep;
         double complex gm[4][4];
-        ks_mks_gcov_c(grid->a_spin, grid->h_slope, x1, x2, gm);
+        gcov_c(grid, x1, x2, gm);
         for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b) dg[c][a][b] = cimag(gm[a][b]) / hstep;
     }

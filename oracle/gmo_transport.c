@@ -89,7 +89,14 @@ void gmo_destroy(gmo_ctx *c)
 /* ---------------------------------------------------------------------
  * Geometry helpers
  * ------------------------------------------------------------------- */
-static double horizon_r(const gmo_grid *g) { return 1.0 + sqrt(1.0 - g->a_spin * g->a_spin); }
+/* Kerr: outer horizon (M = 1); flat spherical coordinates: none (0). */
+static double horizon_r(const gmo_grid *g)
+{
+    return g->metric == GMO_METRIC_KS_MKS ? 1.0 + sqrt(1.0 - g->a_spin * g->a_spin) : 0.0;
+}
+
+/* Grids in (ln r, x2, phi) coordinates: Kerr-Schild and flat spherical. */
+static int spherical_grid(const gmo_grid *g) { return g->metric != GMO_METRIC_MINKOWSKI_CART; }
 
 static double dot4(const double g[4][4], const double a[4], const double b[4])
 {
@@ -228,7 +235,8 @@ int gmo_load_zones(gmo_ctx *c, const gmo_grid *grid, const gmo_zones *z)
     if (!c || !grid || !z) { gmo_set_error("null argument"); return GMO_EINVAL; }
     for (int j = 0; j < 3; ++j)
         if (grid->n[j] < 1 || !(grid->dx[j] > 0.0)) { gmo_set_error("bad grid"); return GMO_EINVAL; }
-    if (grid->metric != GMO_METRIC_MINKOWSKI_CART && grid->metric != GMO_METRIC_KS_MKS) {
+    if (grid->metric != GMO_METRIC_MINKOWSKI_CART && grid->metric != GMO_METRIC_KS_MKS &&
+        !(grid->metric == GMO_METRIC_FLAT_SPH && grid->a_spin == 0.0)) {
         gmo_set_error("unknown metric"); return GMO_EINVAL;
     }
     free_zones(c);
@@ -258,7 +266,7 @@ int gmo_load_zones(gmo_ctx *c, const gmo_grid *grid, const gmo_zones *z)
         c->vol[i] = gmo_sqrt_neg_g(grid, xc) * grid->dx[0] * grid->dx[1] * grid->dx[2] * L3;
         c->emits[i] = (c->A[i] > 0.0);
         /* Kerr: no emission from zones centred inside the horizon (reading) */
-        if (grid->metric == GMO_METRIC_KS_MKS && exp(xc[1]) < rh) c->emits[i] = 0;
+        if (spherical_grid(grid) && exp(xc[1]) < rh) c->emits[i] = 0;
     }
     return GMO_OK;
 }
@@ -691,7 +699,7 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
 static double step_size(const gmo_grid *G, double h, const double x[4], const double k[4])
 {
     double dl;
-    if (G->metric != GMO_METRIC_KS_MKS) {
+    if (!spherical_grid(G)) {
         dl = INFINITY;
         for (int j = 1; j <= 3; ++j)
             if (k[j] != 0.0) {
@@ -782,10 +790,10 @@ int gmo_integrate_geodesic(const gmo_grid *G, const double x0[4], const double k
         double dl = step_size(G, h, x, k);
         double xn[4], kn[4], an[4];
         verlet(G, tol, max_it, x, k, a, dl, xn, kn, an);
-        if (G->metric == GMO_METRIC_KS_MKS) pole_reflect(xn, kn, an);
+        if (spherical_grid(G)) pole_reflect(xn, kn, an);
         memcpy(x, xn, sizeof(x)); memcpy(k, kn, sizeof(k)); memcpy(a, an, sizeof(a));
         for (int m = 0; m < 4; ++m) { out[8 * s + m] = x[m]; out[8 * s + 4 + m] = k[m]; }
-        if (G->metric == GMO_METRIC_KS_MKS) {
+        if (spherical_grid(G)) {
             double r = exp(x[1]);
             if (r < r_min || r > r_max) { ++s; break; }
         }
@@ -797,7 +805,7 @@ int gmo_integrate_geodesic(const gmo_grid *G, const double x0[4], const double k
 static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk, photon *ph)
 {
     const gmo_grid *G = &c->grid;
-    const int ks_metric = (G->metric == GMO_METRIC_KS_MKS);
+    const int ks_metric = spherical_grid(G);
     const double rh = horizon_r(G);
     const double Cc = GMO_HPL * G->L_unit_cm / MEC2;   /* C = h ell / m_e c^2 */
     coef c0;

@@ -330,17 +330,23 @@ gm_status gm_destroy(gm_ctx *c)
     return GM_OK;
 }
 
+// Mass of the Kerr-Schild form a grid uses: 1 for Kerr, 0 for flat spherical.
+static double metric_mass(int metric) { return metric == GM_METRIC_KS_MKS ? 1.0 : 0.0; }
+
 gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zones *z)
 {
     if (!c || !g || !z) return fail(GM_EINVAL, "NULL argument");
     if (instance < 0 || instance >= GM_MAX_INSTANCES) return fail(GM_EINVAL, "instance %d", instance);
-    if (g->metric != GM_METRIC_MINKOWSKI_CART && g->metric != GM_METRIC_KS_MKS)
+    if (g->metric != GM_METRIC_MINKOWSKI_CART && g->metric != GM_METRIC_KS_MKS && g->metric != GM_METRIC_FLAT_SPH)
         return fail(GM_EINVAL, "unknown metric %d", g->metric);
+    if (g->metric == GM_METRIC_FLAT_SPH && g->a_spin != 0.0)
+        return fail(GM_EINVAL, "the flat spherical grid takes a_spin = 0");
     for (int j = 0; j < 3; ++j)
         if (g->n[j] < 1 || !(g->dx[j] > 0.0) || !std::isfinite(g->x_start[j]))
             return fail(GM_EINVAL, "grid axis %d", j);
     if (!(g->L_unit_cm > 0.0)) return fail(GM_EINVAL, "L_unit_cm must be > 0");
-    const bool kerr = g->metric == GM_METRIC_KS_MKS;
+    const bool kerr = g->metric != GM_METRIC_MINKOWSKI_CART;     // (ln r, x2, phi) grid
+    const double mass = metric_mass(g->metric);
     if (kerr) {
         if (!(std::fabs(g->a_spin) < 1.0)) return fail(GM_EINVAL, "spin |a| must be < 1");
         if (!(g->h_slope > 0.0 && g->h_slope <= 1.0)) return fail(GM_EINVAL, "h_slope must be in (0, 1]");
@@ -370,7 +376,7 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
                 // the fluid velocity must be timelike at the zone centre
                 int i2 = (i / g->n[2]) % g->n[1], i1 = i / (g->n[2] * g->n[1]);
                 KMetric K;
-                kerr_metric<false>(g->a_spin, g->h_slope, g->x_start[0] + (i1 + 0.5) * g->dx[0],
+                kerr_metric<false>(g->a_spin, mass, g->h_slope, g->x_start[0] + (i1 + 0.5) * g->dx[0],
                                    g->x_start[1] + (i2 + 0.5) * g->dx[1], K);
                 double gm4[4][4], u[4];
                 kerr_full(K, gm4);
@@ -389,6 +395,7 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
         for (int j = 0; j < 3; ++j) { V.n[j] = g->n[j]; V.xs[j] = g->x_start[j]; V.dx[j] = g->dx[j]; }
         V.kerr = kerr ? 1 : 0;
         V.a_spin = g->a_spin;
+        V.mass = mass;
         V.h_slope = g->h_slope;
         V.first_bad = c->flags.p + 2;
         int first = INT_MAX;
@@ -428,7 +435,7 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
     P.metric = g->metric;
     P.a_spin = g->a_spin;
     P.h_slope = g->h_slope;
-    P.r_h = kerr_horizon(g->a_spin);
+    P.r_h = kerr_horizon(g->a_spin, mass);
     P.max_i1 = c->flags.p + 3;
     int max_i1 = -1;
     HIPCHK(hipMemcpyAsync(P.max_i1, &max_i1, sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -742,8 +749,9 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
     A.cap = c->queue_cap;
     A.refill_min = c->refill_min;
     A.a_spin = I.grid.a_spin;
+    A.mass = metric_mass(I.grid.metric);
     A.h_slope = I.grid.h_slope;
-    A.r_h = kerr_horizon(I.grid.a_spin);
+    A.r_h = kerr_horizon(I.grid.a_spin, A.mass);
     A.r_capture = A.r_h * (1.0 + tp->horizon_eps);
     A.r_record = I.grid.r_record;
     A.i1_plasma_max = (double)I.max_i1;
@@ -769,7 +777,7 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     const size_t lds_stride = L_N + S_N + (hbm_tally ? 0 : nspec);
     const size_t lds_track = (size_t)n_inst * lds_stride * 8 + kEvBytesPerBlock;
     const size_t lds_small = (size_t)n_inst * (L_N + S_N) * 8;
-    const bool kerr = c->inst[ids[0]].grid.metric == GM_METRIC_KS_MKS;
+    const bool kerr = c->inst[ids[0]].grid.metric != GM_METRIC_MINKOWSKI_CART;
     const bool f32 = tp->precision == GM_PRECISION_F32_EMISSIVITY;
     using KernelFn = void (*)(TArgs);
 #define GM_TRACK_VARIANTS(K, F, B) {K<2, F, B>, K<3, F, B>, K<4, F, B>}
@@ -1045,7 +1053,7 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     const size_t per_inst = per_small + (size_t)tp->n_theta * tp->n_nu * 3 * 8;
     const size_t acc_budget = 56 * 1024;
     std::vector<long long> acc(S_N, 0);
-    for (int metric = 0; metric < 2; ++metric) {
+    for (int metric = 0; metric < 3; ++metric) {
         std::vector<int> pend;
         for (int i = 0; i < GM_MAX_INSTANCES; ++i)
             if (c->inst[i].pending && c->inst[i].grid.metric == metric) pend.push_back(i);

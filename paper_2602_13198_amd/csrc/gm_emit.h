@@ -19,7 +19,7 @@ struct PrepArgs {
     double xs[3], dx[3];
     double L3;
     int nz;
-    int metric;                  // 0 flat Cartesian, 1 Kerr (modified Kerr-Schild)
+    int metric;                  // 0 flat Cartesian; else (ln r, x2, phi) grids: Kerr, flat spherical
     double a_spin, h_slope, r_h;
     int *max_i1;                 // largest first-axis index of a zone holding plasma (-1: none)
 };
@@ -96,8 +96,8 @@ struct CheckArgs {
     int nz;
     int n[3];
     double xs[3], dx[3];
-    int kerr;
-    double a_spin, h_slope;
+    int kerr;                    // (ln r, x2, phi) grid: Kerr or flat spherical
+    double a_spin, mass, h_slope;
     int *first_bad;
 };
 
@@ -112,7 +112,8 @@ __global__ __launch_bounds__(256) void zone_check_kernel(CheckArgs C)
         if (!bad && C.kerr) {
             int i2 = (i / C.n[2]) % C.n[1], i1 = i / (C.n[2] * C.n[1]);
             KMetric K;
-            kerr_metric<false>(C.a_spin, C.h_slope, C.xs[0] + (i1 + 0.5) * C.dx[0], C.xs[1] + (i2 + 0.5) * C.dx[1], K);
+            kerr_metric<false>(C.a_spin, C.mass, C.h_slope, C.xs[0] + (i1 + 0.5) * C.dx[0],
+                               C.xs[1] + (i2 + 0.5) * C.dx[1], K);
             double g[4][4], u[4];
             kerr_full(K, g);
 #pragma unroll

@@ -1,15 +1,17 @@
 // gm_kerr.h -- Kerr spacetime in modified Kerr-Schild coordinates (device).
 //
 // Coordinates (t, x1, x2, x3): r = exp(x1), theta = pi x2 + (1-h)/2 sin(2 pi x2),
-// phi = x3, M = 1.  The Kerr-Schild line element
+// phi = x3, mass M (1 for the black hole, lengths in r_g; 0 with a = 0 for
+// flat spacetime in spherical coordinates, the sphere grids of the paper's
+// tests).  The Kerr-Schild line element
 //   ds^2 = -(1-z)dt^2 + 2z dt dr + (1+z)dr^2 + S dth^2 + sin^2th [S + a^2(1+z)sin^2th] dph^2
-//          - 2az sin^2th dt dph - 2a(1+z) sin^2th dr dph,   S = r^2 + a^2 cos^2th, z = 2r/S,
+//          - 2az sin^2th dt dph - 2a(1+z) sin^2th dr dph,   S = r^2 + a^2 cos^2th, z = 2Mr/S,
 // carried to the modified coordinates by the Jacobian (1, r, dtheta/dx2, 1).
 // Seven components are non-zero: g00 g01 g03 g11 g13 g22 g33.  Their x1 and
 // x2 derivatives come from forward-mode dual numbers; the inverse is the
 // closed form of the Kerr-Schild inverse metric,
 //   g^tt = -(1+z), g^tr = z, g^rr = D/S, g^rph = a/S, g^thth = 1/S, g^phph = 1/(S sin^2),
-// D = r^2 - 2r + a^2, divided by the Jacobian factors.
+// D = r^2 - 2Mr + a^2, divided by the Jacobian factors.
 #pragma once
 
 #include "gm_common.h"
@@ -44,7 +46,7 @@ struct KMetric {
 };
 
 template <bool DERIV>
-GM_HD void kerr_metric(double a, double hs, double x1, double x2, KMetric &K)
+GM_HD void kerr_metric(double a, double M, double hs, double x1, double x2, KMetric &K)
 {
     double r = exp(x1);
     double st, ct;
@@ -55,7 +57,7 @@ GM_HD void kerr_metric(double a, double hs, double x1, double x2, KMetric &K)
     sincos(th, &s, &c);
     K.r = r;
     if (!DERIV) {
-        double s2 = s * s, S = r * r + a * a * c * c, z = 2.0 * r / S;
+        double s2 = s * s, S = r * r + a * a * c * c, z = 2.0 * M * r / S;
         K.g00 = z - 1.0;
         K.g01 = z * r;
         K.g03 = -a * z * s2;
@@ -63,7 +65,7 @@ GM_HD void kerr_metric(double a, double hs, double x1, double x2, KMetric &K)
         K.g13 = -a * (1.0 + z) * s2 * r;
         K.g22 = S * dth * dth;
         K.g33 = s2 * (S + a * a * (1.0 + z) * s2);
-        double D = r * r - 2.0 * r + a * a;
+        double D = r * r - 2.0 * M * r + a * a;
         K.u00 = -(1.0 + z);
         K.u01 = z / r;
         K.u11 = D / (S * r * r);
@@ -77,7 +79,7 @@ GM_HD void kerr_metric(double a, double hs, double x1, double x2, KMetric &K)
     D3 Sn{s, 0.0, c * dth}, Cs{c, 0.0, -s * dth};
     D3 S2 = Sn * Sn, C2 = Cs * Cs;
     D3 S = R * R + (a * a) * C2;
-    D3 Z = (2.0 * R) / S;
+    D3 Z = (2.0 * M * R) / S;
     D3 one{1.0, 0.0, 0.0};
     D3 Zp = 1.0 + Z;
     D3 g[7];
@@ -93,7 +95,7 @@ GM_HD void kerr_metric(double a, double hs, double x1, double x2, KMetric &K)
     for (int i = 0; i < 7; ++i) { K.d1[i] = g[i].d1; K.d2[i] = g[i].d2; }
     // inverse: one reciprocal of Sigma r^2 dth^2 serves four quotients; the
     // sin^2 quotient keeps its own division (infinite on the axis, as before)
-    double D = r * r - 2.0 * r + a * a;
+    double D = r * r - 2.0 * M * r + a * a;
     double Sv = S.v, z = Z.v;
     const double q = 1.0 / (Sv * r * r * dth * dth);
     const double iSr2 = q * (dth * dth);                   // 1 / (Sigma r^2)
@@ -171,6 +173,7 @@ GM_HD double kerr_sqrt_neg_g(double a, double hs, double x1, double x2)
     return (r * r + a * a * c * c) * fabs(sin(th)) * r * dth;
 }
 
-GM_HD double kerr_horizon(double a) { return 1.0 + sqrt(1.0 - a * a); }
+// Outer horizon M + sqrt(M^2 - a^2); 0 in flat spacetime.
+GM_HD double kerr_horizon(double a, double M) { return M > 0.0 ? M + sqrt(M * M - a * a) : 0.0; }
 
 }  // namespace gm

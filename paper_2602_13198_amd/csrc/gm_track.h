@@ -109,7 +109,7 @@ struct TArgs {
     float ln_c2_2h;                // ln(c^2 / (2 h)), set on the host from the CGS constants
     // Kerr (modified Kerr-Schild): spin, polar slope, horizon, capture and
     // record radii, corrector, reciprocal step scales (dx1, dx2, min(dx3, pi dx2))
-    double a_spin, h_slope, r_h, r_capture, r_record;
+    double a_spin, mass, h_slope, r_h, r_capture, r_record;   // mass 1 (Kerr) or 0 (flat spherical)
     double i1_plasma_max;          // no zone with a larger first-axis index holds plasma
     double verlet_tol;
     int verlet_max_it;
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
         double g[4][4], u[4], bh[4], e[4][4];
         if constexpr (M::kCurved) {
             KMetric K;
-            kerr_metric<false>(A.a_spin, A.h_slope, x[1], x[2], K);
+            kerr_metric<false>(A.a_spin, A.mass, A.h_slope, x[1], x[2], K);
             kerr_full(K, g);
             fluid_frame(zr, g, u, bh);
         } else {

@@ -123,12 +123,19 @@ GM_D void finish_ks(const TArgs &A, BlockAcc &B, const PhotonK &ph, int kind)
 // leaves the corrector without a fixed point).
 GM_D double step_ks(const TArgs &A, const PhotonK &ph)
 {
-    double m = fmax(fmax(fabs(ph.k[1]) * A.inv_sc[0], fabs(ph.k[2]) * A.inv_sc[1]),
-                    fabs(ph.k[3]) * A.inv_sc[2]);
-    double dl = A.step_h / m;
-    if (ph.k[1] < 0.0) dl = fmin(dl, 0.5 * (ph.r - A.r_h) / (ph.r * fabs(ph.k[1])));
-    double dp = fmax(fmin(ph.x[1], 1.0 - ph.x[1]), 1e-9);
-    return fmin(dl, 0.1 * dp / fabs(ph.k[2]));       // +inf when k^2 = 0
+    // the least of the quotients num/den (positive denominators) is chosen by
+    // cross-multiplied comparisons, so the step costs one division
+    double num = A.step_h;
+    double den = fmax(fmax(fabs(ph.k[1]) * A.inv_sc[0], fabs(ph.k[2]) * A.inv_sc[1]),
+                      fabs(ph.k[3]) * A.inv_sc[2]);
+    if (ph.k[1] < 0.0) {
+        const double n1 = 0.5 * (ph.r - A.r_h), d1 = ph.r * fabs(ph.k[1]);
+        if (n1 * den < num * d1) { num = n1; den = d1; }
+    }
+    const double dp = fmax(fmin(ph.x[1], 1.0 - ph.x[1]), 1e-9);
+    const double n2 = 0.1 * dp, d2 = fabs(ph.k[2]);   // no bound when k^2 = 0
+    if (n2 * den < num * d2) { num = n2; den = d2; }
+    return num / den;
 }
 
 // Plasma zone of a scattering point: the point's own zone when it holds
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                 for (int m = 0; m < 3; ++m) P[m] = ph.x[m];
             }
             KMetric K;
-            kerr_metric<true>(A.a_spin, A.h_slope, P[0], P[1], K);
+            kerr_metric<true>(A.a_spin, A.mass, A.h_slope, P[0], P[1], K);
             if (mode != MODE_LOAD) {
                 // corrector: a' at the predicted wavevector, k' = k + (a + a') dl / 2
                 double kp[4];
@@ -330,7 +337,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                         }
                     }
                     double wba = ph.w;
-                    ph.w *= exp(-tau_a);
+                    if (tau_a != 0.0) ph.w *= exp(-tau_a);      // vacuum steps skip the exp
                     ph.acc_wabs += wba - ph.w;
                     ph.acc_eabs += (wba - ph.w) * e_old;
 #pragma unroll
@@ -439,7 +446,7 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_ks(TArgs L)
         const Rng r_child = r;
         uint32_t cev = kNoEvent;
         KMetric K;
-        kerr_metric<false>(A.a_spin, A.h_slope, Q.x[0][i], Q.x[1][i], K);
+        kerr_metric<false>(A.a_spin, A.mass, A.h_slope, Q.x[0][i], Q.x[1][i], K);
         double g[4][4];
         kerr_full(K, g);
         double kc[4];

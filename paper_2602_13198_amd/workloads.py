@@ -40,6 +40,7 @@ M_E = 9.1093837015e-28
 
 METRIC_MINKOWSKI_CART = 0
 METRIC_KS_MKS = 1
+METRIC_FLAT_SPH = 2
 
 BIAS_CONST, BIAS_THETA2, BIAS_GEN2, BIAS_TABLE, BIAS_WINDOW = 0, 1, 2, 3, 4
 BIAS_LEARNED = BIAS_TABLE
@@ -116,6 +117,74 @@ def sphere(n: int = 32, R_cm: float = 1e14, theta_e: float = 10.0, n_e: float = 
                 w_floor_rel=1e-30, seed=int(seed), instance=0)
     return Workload(name, grid, ne, th, Bz, ucon, bcon, emit, default_track(**track_kw),
                     meta=dict(R_cm=R_cm, fill=f, n_e0=n_e, theta_e=theta_e, B=B))
+
+
+def log_r_sphere(n1=8192, n2=128, R_cm=1.0, r_in=1e-2, r_out=1e4, r_record=3000.0, theta_e=100.0,
+                 n_e=1e13, B=1.0, n_target=1e5, seed=0, nu_min=1e8, nu_max=None, n_nu=2500, dln_nu=0.01,
+                 n_theta=6, sub=5, step_h=2.0, name="log_r_sphere", **track_kw) -> Workload:
+    """Uniform synchrotron sphere of radius R on the flat spherical grid of
+    the paper's sphere tests: coordinates (t, ln r, theta, phi), n1 x n2 x 1
+    zones over r in [r_in, r_out] (cm; ell = 1 cm) and theta uniform in
+    [0, pi]; static plasma, vertical field B^z = B, i.e. B^r = B cos theta,
+    B^theta = -B sin theta / r; photons recorded at r_record; n_nu bins of
+    width dln_nu in ln nu from nu_min (2500 x 0.01 by default) and emission
+    over the same band.  Cells that straddle r = R hold n_e times the
+    fraction of their sub x sub sub-cells (in x1, x2) whose centres lie
+    inside.  The step factor is in zone widths: 2 keeps a step within
+    0.34 % of r and 0.05 rad of theta on the 8192 x 128 grid (8 lets the
+    polar steps reach 0.2 rad, and photons passing near the axis then miss
+    the polar inclination bins by a quarter)."""
+    x1a, x1b = math.log(r_in), math.log(r_out)
+    dx = [(x1b - x1a) / n1, 1.0 / n2, 2.0 * math.pi]
+    if nu_max is None:
+        nu_max = nu_min * math.exp(n_nu * dln_nu)
+    # fraction of sub-cells inside the sphere, per radial zone
+    o = (np.arange(sub) + 0.5) / sub
+    r_sub = np.exp(x1a + (np.arange(n1)[:, None] + o[None, :]) * dx[0])
+    frac = (r_sub < R_cm).mean(axis=1)
+    x2c = (np.arange(n2) + 0.5) * dx[1]
+    th = math.pi * x2c
+    r_c = np.exp(x1a + (np.arange(n1) + 0.5) * dx[0])
+    nz = n1 * n2
+    ne = np.repeat(n_e * frac, n2)
+    the = np.where(ne > 0, float(theta_e), 0.0)
+    Bf = np.where(ne > 0, float(B), 0.0)
+    ucon = np.zeros((4, nz))
+    ucon[0] = 1.0
+    bcon = np.zeros((4, nz))
+    # coordinate components in (ln r, x2): b^1 = B^r / r, b^2 = B^theta / (dtheta/dx2)
+    bcon[1] = (np.cos(th)[None, :] / r_c[:, None]).reshape(-1)
+    bcon[2] = (-np.sin(th)[None, :] / (r_c[:, None] * math.pi)).reshape(-1)
+    grid = dict(metric=METRIC_FLAT_SPH, n=[n1, n2, 1], x_start=[x1a, 0.0, 0.0], dx=dx, a_spin=0.0,
+                h_slope=1.0, L_unit_cm=1.0, r_record=float(r_record))
+    emit = dict(n_target=float(n_target), nu_min=nu_min, nu_max=nu_max, n_wnodes=257,
+                w_floor_rel=1e-30, seed=int(seed), instance=0)
+    tk = dict(step_h=step_h, n_nu=n_nu, nu_lo=nu_min, nu_hi=nu_min * math.exp(n_nu * dln_nu),
+              n_theta=n_theta)
+    tk.update(track_kw)
+    vol = (4.0 * math.pi / 3.0) * np.sum(frac * (np.exp(x1a + (np.arange(n1) + 1) * dx[0]) ** 3
+                                                 - np.exp(x1a + np.arange(n1) * dx[0]) ** 3))
+    return Workload(name, grid, ne, the, Bf, ucon, bcon, emit, default_track(**tk),
+                    meta=dict(R_cm=R_cm, n_e0=n_e, theta_e=theta_e, B=B, frac=frac, V_eff=vol))
+
+
+def paper_thin_sphere(n1=8192, n2=128, n_target=1e5, seed=0, **kw) -> Workload:
+    """The optically thin synchrotron sphere of the paper's tests: R = 1 cm,
+    Theta_e = 100, n_e = 1e13 cm^-3, B = 1 G, 8192 x 128 x 1 log-r grid out
+    to 1e4 cm, record at 3000 cm, 2500 bins of 0.01 in ln nu, no scattering."""
+    return log_r_sphere(n1=n1, n2=n2, n_target=n_target, seed=seed, name="paper_thin_sphere", **kw)
+
+
+def paper_scattering_sphere(n1=8192, n2=128, n_target=1e5, seed=0, n_sc_max=4, **kw) -> Workload:
+    """The scattering sphere of the paper's tests: the same cloud with
+    n_e = 1e18 cm^-3 and Theta_e = 3, thermal Compton with the generation
+    bias b = (n_sc + 1)^2 / (n_e sigma_T R) (the printed product inverted,
+    so that b >= 1), up to n_sc_max scatterings."""
+    R = 1.0
+    tau = 1e18 * SIGMA_T * R
+    return log_r_sphere(n1=n1, n2=n2, theta_e=3.0, n_e=1e18, n_target=n_target, seed=seed,
+                        name="paper_scattering_sphere", scattering=1, bias_mode=BIAS_GEN2,
+                        bias_value=R, n_sc_max=n_sc_max, **kw)
 
 
 def thin_sphere(n_target=1e5, seed=0, n=32) -> Workload:
@@ -350,15 +419,21 @@ SURVEY_RADII = {-0.5: (10.0, 20.0), 0.0: (8.0, 16.0), 0.5: (7.0, 14.0), 0.9375: 
 
 
 def survey(n1=192, n2=96, n3=96, n_draw=4, M_c=1e27, ns_lo=1e5, ns_hi=1e7, seed=4, step_h=0.5,
-           **track_kw):
+           bias_c=1e4, **track_kw):
     """Batched survey: for every spin in SURVEY_SPINS and R_high in
     SURVEY_R_HIGH, n_draw density scales M_unit log-uniform on
     [M_c / 10, 10 M_c] (4 x 4 x 4 = 64 instances by default), each with its
     own N_s log-uniform on [ns_lo, ns_hi] and its own emission seed.  One
     torus structure per spin (shared perturbations); R_high and M_unit only
     rescale it (Theta_e through R-beta, n_e by M_unit, B by sqrt(M_unit)),
-    so the instances are built without recomputing the torus.  Returns the
-    list of workloads, instance i at emit["instance"] = i."""
+    so the instances are built without recomputing the torus.  The
+    coefficient c of the bias b = c Theta_e^2 is bias_c (M_c / M_unit)
+    ((1 + R) / (1 + R(40)))^2 per instance, which keeps b tau_T where the
+    torus is densest and hottest at the value of the R_high = 40,
+    M_unit = M_c torus with c = bias_c, so every instance scatters about
+    as much (a fixed c would give the hot R_high = 1 tori about a thousand
+    scattered superphotons per root, an exponential cascade over the
+    generations).  Returns the list of workloads, instance i at emit["instance"] = i."""
     rng = np.random.Generator(np.random.Philox(seed))
     out = []
     i = 0
@@ -367,6 +442,7 @@ def survey(n1=192, n2=96, n3=96, n_draw=4, M_c=1e27, ns_lo=1e5, ns_hi=1e7, seed=
         base = torus(n1=n1, n2=n2, n3=n3, a=a, r_in=rin, r_max=rmax, R_high=1.0, M_unit=1.0,
                      step_h=step_h, **track_kw)
         beta = 100.0
+        R40 = (40.0 * beta ** 2 + 1.0) / (1 + beta ** 2)
         for rh_ in SURVEY_R_HIGH:
             Rf = (rh_ * beta ** 2 + 1.0) / (1 + beta ** 2)
             R1 = (1.0 * beta ** 2 + 1.0) / (1 + beta ** 2)
@@ -377,8 +453,9 @@ def survey(n1=192, n2=96, n3=96, n_draw=4, M_c=1e27, ns_lo=1e5, ns_hi=1e7, seed=
                 Mu = M_c * 10.0 ** rng.uniform(-1.0, 1.0)
                 ns = 10.0 ** rng.uniform(math.log10(ns_lo), math.log10(ns_hi))
                 emit = dict(base.emit, n_target=float(ns), seed=int(1000 + i), instance=i)
+                tk = dict(base.track, bias_value=bias_c * (M_c / Mu) * ((1 + Rf) / (1 + R40)) ** 2)
                 wl = Workload("survey_%d" % i, base.grid, base.n_e * Mu, theta_e, base.B * math.sqrt(Mu),
-                              base.ucon, base.bcon, emit, dict(base.track),
+                              base.ucon, base.bcon, emit, tk,
                               meta=dict(a=a, R_high=rh_, M_unit=Mu, N_s=ns, r_h=base.meta["r_h"]))
                 out.append(wl)
                 i += 1

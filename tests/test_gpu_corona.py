@@ -46,7 +46,7 @@ def test_corona_same_seed(gm, oracle_lib):
     m, bad = compare_traces(tr, ores.trace)
     print("corona torus 48x24x24: %d photons, %d differ, generations %s" % (m, len(bad), np.bincount(tr["n_sc"])))
     assert m > 3000
-    assert len(bad) <= 5e-3 * m, describe(tr, ores.trace, bad)
+    assert len(bad) <= 1e-3 * m, describe(tr, ores.trace, bad)
     kinds = np.bincount(tr["kind"], minlength=7)
     assert kinds[1] > 0 and kinds[3] > 0 and np.bincount(tr["n_sc"]).size >= 3
     wr, er = ledger_residuals(led)
@@ -79,7 +79,7 @@ def test_corona_full_size_sampled(gm, oracle_lib):
     print("corona torus full size: %d roots, %d superphotons; %d sampled photons, %d differ"
           % (st[0], st[0] + st[1], m, len(bad)))
     assert m == len(ora) and m >= 120
-    assert len(bad) <= max(1, 5e-3 * m), describe(sub, ora, bad)
+    assert len(bad) <= max(1, 1e-3 * m), describe(sub, ora, bad)
     wr, er = ledger_residuals(led)
     assert abs(wr) < 1e-12 and abs(er) < 1e-12
 

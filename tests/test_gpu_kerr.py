@@ -8,7 +8,8 @@ tally bin, step count) exactly, weights, wavevectors and positions within
 derivatives and a numerical inverse of g, which agree with the exact
 symbolic values to ~1e-12 at r ~ 200 (pinned in test_oracle_kerr.py); a
 photon whose history differs is allowed only where a threshold decision
-lands within that rounding, at most 0.5 % of photons, each one reported."""
+lands within that rounding, at most 0.1 % of photons (one photon on small
+runs), each one reported."""
 import numpy as np
 import pytest
 
@@ -78,8 +79,9 @@ def test_torus_same_seed_histories(gm, oracle_lib, wl):
     g = run_gpu(gm, wl, trace_cap=1_000_000)
     ores, _ = oracle_lib.run(wl, trace_cap=1_000_000)
     n, bad = compare_traces(g["trace"], ores.trace)
+    print("%d photons compared, %d differ" % (n, len(bad)))
     assert n > 500
-    assert len(bad) <= 5e-3 * n, describe(g["trace"], ores.trace, bad)
+    assert len(bad) <= max(1, 1e-3 * n), describe(g["trace"], ores.trace, bad)
     kinds = np.bincount(g["trace"]["kind"], minlength=7)
     assert kinds[1] > 0 and kinds[3] > 0            # escapes and captures
     wr, er = ledger_residuals(g["ledger"])

@@ -76,7 +76,8 @@ def test_torus_3d_perturbations():
 def test_survey_instances():
     """64 instances: every spin x R_high pair with four density scales
     within [M_c / 10, 10 M_c], N_s within [1e5, 1e7], distinct instance ids;
-    n_e scales with M_unit and B with its square root."""
+    n_e scales with M_unit and B with its square root; the bias coefficient
+    with M_unit and R_high as stated."""
     S = W.survey(n1=24, n2=12, n3=8)
     assert len(S) == 64
     assert [w.emit["instance"] for w in S] == list(range(64))
@@ -95,3 +96,9 @@ def test_survey_instances():
     t1 = [w for w in hot if w.meta["R_high"] == 1.0][0].theta_e
     t160 = [w for w in hot if w.meta["R_high"] == 160.0][0].theta_e
     assert np.all(t160 <= t1 + 1e-15) and t160.max() < t1.max()
+    # the bias coefficient keeps b tau_T of the hottest, densest zone: with
+    # b = c Theta_e^2 and tau_T ~ n_e ~ M_unit, c M_unit Theta_max^2 is the
+    # same for every instance of a spin
+    for a_ in {w.meta["a"] for w in S}:
+        v = [w.track["bias_value"] * w.meta["M_unit"] * w.theta_e.max() ** 2 for w in S if w.meta["a"] == a_]
+        np.testing.assert_allclose(v, v[0], rtol=1e-9)
