@@ -376,6 +376,41 @@ def flat_sphere_form(ctx, base_inst, steps=5):
             "tracker_algorithmic_tflops": fl / (ms * 1e-3) / 1e12 if ms else None}
 
 
+def paper_sphere_form(ctx, inst, steps=2, n_s=1e7):
+    """The paper's optically thin sphere on its own grid: flat spacetime in
+    (t, ln r, theta, phi), 8192 x 128 x 1 zones out to 1e4 cm, R = 1 cm,
+    Theta_e = 100, n_e = 1e13, B = 1 G, record at 3000 cm, 2500 bins of 0.01
+    in ln nu (tallies in HBM), FP64."""
+    import torch
+    from paper_2602_13198_amd import workloads as W
+    wl = W.paper_thin_sphere(n_target=n_s, seed=0)
+    wl.emit["instance"] = inst
+    ctx.load_zones(wl, inst)
+    ctx.set_instance_bias(inst, wl.track)
+
+    def step(seed):
+        ctx.make_superphotons(dict(wl.emit, seed=seed), instance=inst)
+        st = ctx.track_scatter(wl.track)
+        ctx.read_spectrum(inst, reset=True)
+        return st
+    step(9500)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = None
+    for s in range(steps):
+        st = step(9501 + s)
+        tot = st if tot is None else tot + st
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.unload(inst)
+    n = int(tot[0] + tot[1])
+    return {"workload": "the paper's optically thin synchrotron sphere on its log-r grid: R=1 cm, Theta_e=100, "
+                        "n_e=1e13, B=1 G, 8192x128x1 (t, ln r, theta, phi) zones to 1e4 cm, record at 3000 cm, "
+                        "2500 bins of 0.01 in ln nu, N_s=%g, FP64" % n_s,
+            "value": n / dt, "unit": "superphotons/s", "ms_per_step": dt / steps * 1e3,
+            "geodesic_steps_per_superphoton": float(tot[2]) / max(n, 1)}
+
+
 def survey_form(ctx, steps=2, n_inst=64, log=lambda m: None):
     """The batched survey: 64 tori (spins -0.5 .. 0.9375, R_high 1 .. 160,
     M_unit log-uniform over two decades, N_s log-uniform on [1e5, 1e7])
@@ -621,6 +656,8 @@ def main():
         log("graph form done")
         out["forms"]["flat_scattering_sphere"] = flat_sphere_form(ctx, 1)
         log("flat sphere: %.4g superphotons/s" % out["forms"]["flat_scattering_sphere"]["value"])
+        out["forms"]["paper_thin_sphere"] = paper_sphere_form(ctx, 4)
+        log("paper thin sphere: %.4g superphotons/s" % out["forms"]["paper_thin_sphere"]["value"])
         ctx.unload(0)
         out["forms"]["survey"] = survey_form(ctx, n_inst=args.survey_inst, log=log)
         log("survey: %.4g superphotons/s" % out["forms"]["survey"]["value"])

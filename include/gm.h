@@ -455,6 +455,8 @@ typedef struct {
     int    kind;            /* GM_IMP_*                                            */
     double a, b, alpha;
     double shift;           /* added to every value after the mapping             */
+    int    per_photon;      /* cells: 0 = I per unit weight (score / weight),
+                               1 = I per photon (score / records)                  */
 } gm_importance_map;
 
 /* ln I from the network's output `output` (0 or 1) for every (zone, node):
@@ -470,10 +472,10 @@ gm_status gm_mlp_fill_table(gm_ctx *ctx, int instance, const gm_importance_map *
  * (nearest node of the record's ln eps, resp. ln nu); gm_cells_accumulate
  * forms the sums (kept in the context) and returns their totals [3]
  * {sum score, sum weight, records}; gm_cells_fill_table then writes the
- * ratio score / weight of each zone's cell, shrunk towards the overall
- * ratio with `prior` records' mean weight (cells without records take the
- * overall ratio).  The map of both calls must name the same table and
- * nodes. */
+ * ratio score / weight (per_photon = 0) or score / records (per_photon =
+ * 1) of each zone's cell, shrunk towards the overall ratio with `prior`
+ * records (cells without records take the overall ratio).  The map of
+ * both calls must name the same table and nodes. */
 gm_status gm_cells_accumulate(gm_ctx *ctx, int instance, const gm_importance_map *map, const int blocks[3],
                               double totals[3]);
 /* Copy an instance's bias or emission table (GM_TABLE_*) into a host

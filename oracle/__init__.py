@@ -61,9 +61,20 @@ class Grid(C.Structure):
                 ("L_unit_cm", C.c_double), ("r_record", C.c_double)]
 
 
+class Dist(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double), ("g1", C.c_double), ("g2", C.c_double)]
+
+
+def make_dist(el) -> Dist:
+    """Electron distribution of a workload (None: thermal)."""
+    if not el:
+        return Dist(0, 0.0, 0.0, 0.0)
+    return Dist(int(el["kind"]), float(el["p"]), float(el["gamma_min"]), float(el["gamma_max"]))
+
+
 class Zones(C.Structure):
     _fields_ = [("n_e", C.c_void_p), ("theta_e", C.c_void_p), ("B", C.c_void_p),
-                ("ucon", C.c_void_p), ("bcon", C.c_void_p)]
+                ("ucon", C.c_void_p), ("bcon", C.c_void_p), ("dist", Dist)]
 
 
 class EmitParams(C.Structure):
@@ -116,6 +127,12 @@ def lib() -> C.CDLL:
                                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
             "gmo_sample_electron": (None, [u64, u32p, u32p, d, d, dp, dp,
                                            C.POINTER(C.c_int64)]),
+            "gmo_pl_jnu": (d, [C.POINTER(Dist), d, d, d, d]),
+            "gmo_pl_Jnu": (d, [C.POINTER(Dist), d, d, d]),
+            "gmo_pl_nualpha": (d, [C.POINTER(Dist), d, d, d, d]),
+            "gmo_sigma_pl_direct": (d, [C.POINTER(Dist), d]),
+            "gmo_sample_scatter_frame_dist": (None, [u64, u32p, u32p, C.POINTER(Dist), d, d, dp, dp, dp,
+                                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
             "gmo_gcov": (None, [C.POINTER(Grid), dp, dp]),
             "gmo_gcon": (None, [C.POINTER(Grid), dp, dp]),
             "gmo_christoffel": (None, [C.POINTER(Grid), dp, dp]),
@@ -216,6 +233,25 @@ def sample_scatter_frame(seed, stream, block, theta, eps):
     et, at = C.c_int64(0), C.c_int64(0)
     lib().gmo_sample_scatter_frame(seed, sp, b.ctypes.data_as(C.POINTER(C.c_uint32)), theta,
                                    eps, C.byref(g), C.byref(m), _dp(k), C.byref(et), C.byref(at))
+    return g.value, m.value, k, int(b[0]), et.value, at.value
+
+
+def pl_jnu(el, n, B, nu, c): return lib().gmo_pl_jnu(C.byref(make_dist(el)), n, B, nu, c)
+def pl_Jnu(el, n, B, nu): return lib().gmo_pl_Jnu(C.byref(make_dist(el)), n, B, nu)
+def pl_nualpha(el, n, B, nu, c): return lib().gmo_pl_nualpha(C.byref(make_dist(el)), n, B, nu, c)
+def sigma_pl_direct(el, e): return lib().gmo_sigma_pl_direct(C.byref(make_dist(el)), e)
+
+
+def sample_scatter_frame_dist(seed, stream, block, el, theta, eps):
+    """sample_scatter_frame with the electrons of el (None: thermal)."""
+    s, sp = _u32(stream)
+    b = np.array([block], np.uint32)
+    g, m = C.c_double(), C.c_double()
+    k = np.zeros(4)
+    et, at = C.c_int64(0), C.c_int64(0)
+    D = make_dist(el)
+    lib().gmo_sample_scatter_frame_dist(seed, sp, b.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(D), theta,
+                                        eps, C.byref(g), C.byref(m), _dp(k), C.byref(et), C.byref(at))
     return g.value, m.value, k, int(b[0]), et.value, at.value
 
 
@@ -326,7 +362,7 @@ class Oracle:
         G = make_grid(wl.grid)
         arrs = [np.ascontiguousarray(a, dtype=np.float64)
                 for a in (wl.n_e, wl.theta_e, wl.B, wl.ucon, wl.bcon)]
-        Z = Zones(*[a.ctypes.data for a in arrs])
+        Z = Zones(*[a.ctypes.data for a in arrs], make_dist(getattr(wl, "electrons", None)))
         _check(lib().gmo_load_zones(self._c, C.byref(G), C.byref(Z)))
         self.nz = int(np.prod(wl.grid["n"]))
         self.grid = wl.grid

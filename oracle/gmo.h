@@ -51,6 +51,17 @@ typedef struct {
     double r_record;        /* KS, SPH: record radius in ell               */
 } gmo_grid;
 
+/* Electron distribution of a loaded plasma: thermal (Maxwell-Juttner at
+ * the zone's Theta_e) or an isotropic power law n(gamma) = n_e C gamma^-p
+ * on [g1, g2], the same in every zone (the non-thermal distributions the
+ * paper names as future work, Conclusions). */
+#define GMO_DIST_THERMAL  0
+#define GMO_DIST_POWERLAW 1
+typedef struct {
+    int    kind;            /* GMO_DIST_*                                   */
+    double p, g1, g2;       /* power law: index p > 1, 1 <= g1 < g2         */
+} gmo_dist;
+
 /* Zone plasma, row-major zone index z = (i1*n2 + i2)*n3 + i3. */
 typedef struct {
     const double *n_e;      /* [nz] electron density cm^-3                 */
@@ -58,6 +69,7 @@ typedef struct {
     const double *B;        /* [nz] field strength, Gauss                   */
     const double *ucon;     /* [4][nz] fluid 4-velocity, code components    */
     const double *bcon;     /* [4][nz] field direction 4-vector (any norm)  */
+    gmo_dist dist;          /* electrons of every zone                     */
 } gmo_zones;
 
 typedef struct {
@@ -172,6 +184,19 @@ void   gmo_sample_scatter_frame(uint64_t seed, const uint32_t stream[3], uint32_
 void   gmo_sample_electron(uint64_t seed, const uint32_t stream[3], uint32_t *block,
                            double theta_e, double eps, double *gamma, double *mu,
                            int64_t *trials);
+
+/* Power-law electrons: emissivity (per steradian) and invariant absorption
+ * nu alpha at angle arccos(cos_th) to the field, their angle integral, the
+ * hot cross section by quadrature, and the scattering of one photon with an
+ * electron of the distribution (thermal at theta_e when d is thermal). */
+double gmo_pl_jnu(const gmo_dist *d, double n_e, double B, double nu, double cos_th);
+double gmo_pl_Jnu(const gmo_dist *d, double n_e, double B, double nu);
+double gmo_pl_nualpha(const gmo_dist *d, double n_e, double B, double nu, double cos_th);
+double gmo_sigma_pl_direct(const gmo_dist *d, double eps);
+void   gmo_sample_scatter_frame_dist(uint64_t seed, const uint32_t stream[3], uint32_t *block,
+                                     const gmo_dist *d, double theta_e, double eps,
+                                     double *gamma_out, double *mu_out, double kout[4],
+                                     int64_t *e_trials, int64_t *ang_trials);
 
 /* Metric at a code-coordinate point: g_{mu nu} (gcov) and, when gcon is not
  * NULL, its inverse.  Christoffel symbols of the second kind, Gam[mu][a][b]. */

@@ -43,6 +43,14 @@ void   gmo_sample_electron_rng(gmo_rng *r, double theta, double eps, double *gam
 void   gmo_scatter_in_frame(gmo_rng *r, double theta, double eps, double *gamma_out,
                             double *mu_out, double kout[4], int64_t *e_trials,
                             int64_t *ang_trials);
+void   gmo_scatter_in_frame_dist(gmo_rng *r, const gmo_dist *d, double theta, double eps,
+                                 double *gamma_out, double *mu_out, double kout[4],
+                                 int64_t *e_trials, int64_t *ang_trials);
+/* power law in the j = A s g(X) form, X = nu / (nu_c s) */
+double gmo_pl_A(const gmo_dist *d, double n_e, double B);
+double gmo_pl_nu_c(double B);
+double gmo_pl_g(double X, double p);
+double gmo_pl_ang(double p);            /* int_0^1 (1 - mu^2)^{(p+1)/4} dmu */
 void   gmo_set_error(const char *msg);
 
 #endif

@@ -49,6 +49,12 @@ struct gmo_ctx {
     uint64_t *offset;                         /* [nz+1] exclusive prefix       */
     /* hot cross-section table, built on first use */
     double *sh;
+    /* electrons: thermal, or the power law with its angular factor and its
+     * hot cross-section table (ln sigma/sigma_T on the thermal table's eps
+     * nodes), built on first use */
+    gmo_dist dist;
+    double pl_ang;
+    double *shpl;
     /* accumulators */
     int n_nu, n_theta;
     double *spec;
@@ -82,7 +88,7 @@ void gmo_destroy(gmo_ctx *c)
 {
     if (!c) return;
     free_zones(c);
-    free(c->sh); free(c->spec); free(c->btab); free(c->mtab); free(c->sw);
+    free(c->sh); free(c->shpl); free(c->spec); free(c->btab); free(c->mtab); free(c->sw);
     free(c);
 }
 
@@ -239,8 +245,19 @@ int gmo_load_zones(gmo_ctx *c, const gmo_grid *grid, const gmo_zones *z)
         !(grid->metric == GMO_METRIC_FLAT_SPH && grid->a_spin == 0.0)) {
         gmo_set_error("unknown metric"); return GMO_EINVAL;
     }
+    const gmo_dist *dd = &z->dist;
+    if (dd->kind != GMO_DIST_THERMAL &&
+        !(dd->kind == GMO_DIST_POWERLAW && dd->p > 1.0 && dd->g1 >= 1.0 && dd->g2 > dd->g1 && isfinite(dd->g2))) {
+        gmo_set_error("bad electron distribution"); return GMO_EINVAL;
+    }
     free_zones(c);
     c->grid = *grid;
+    if (c->shpl && (dd->kind != c->dist.kind || dd->p != c->dist.p || dd->g1 != c->dist.g1 || dd->g2 != c->dist.g2)) {
+        free(c->shpl);
+        c->shpl = NULL;
+    }
+    c->dist = *dd;
+    c->pl_ang = dd->kind == GMO_DIST_POWERLAW ? gmo_pl_ang(dd->p) : 0.0;
     int nz = grid->n[0] * grid->n[1] * grid->n[2];
     c->nz = nz;
     c->n_e = malloc(sizeof(double) * nz); c->theta = malloc(sizeof(double) * nz);
@@ -257,8 +274,13 @@ int gmo_load_zones(gmo_ctx *c, const gmo_grid *grid, const gmo_zones *z)
     const double rh = horizon_r(grid);
     for (int i = 0; i < nz; ++i) {
         if (c->n_e[i] > 0.0 && !(c->theta[i] > 0.0)) { gmo_set_error("n_e > 0 needs Theta_e > 0"); return GMO_EINVAL; }
-        c->A[i] = gmo_A_coef(c->n_e[i], c->theta[i], c->B[i]);
-        c->nu_c[i] = gmo_nu_c(c->theta[i], c->B[i]);
+        if (c->dist.kind == GMO_DIST_POWERLAW) {
+            c->A[i] = gmo_pl_A(&c->dist, c->n_e[i], c->B[i]);
+            c->nu_c[i] = gmo_pl_nu_c(c->B[i]);
+        } else {
+            c->A[i] = gmo_A_coef(c->n_e[i], c->theta[i], c->B[i]);
+            c->nu_c[i] = gmo_nu_c(c->theta[i], c->B[i]);
+        }
         int i3 = i % grid->n[2], i2 = (i / grid->n[2]) % grid->n[1], i1 = i / (grid->n[2] * grid->n[1]);
         double xc[4] = {0.0, grid->x_start[0] + (i1 + 0.5) * grid->dx[0],
                         grid->x_start[1] + (i2 + 0.5) * grid->dx[1],
@@ -271,6 +293,17 @@ int gmo_load_zones(gmo_ctx *c, const gmo_grid *grid, const gmo_zones *z)
     return GMO_OK;
 }
 
+/* Shape g(X) and its angle integral G(X_c) of the loaded electrons. */
+static double shape_g(const gmo_ctx *c, double X)
+{
+    return c->dist.kind == GMO_DIST_POWERLAW ? gmo_pl_g(X, c->dist.p) : gmo_g_of_X(X);
+}
+
+static double shape_G(const gmo_ctx *c, double Xc)
+{
+    return c->dist.kind == GMO_DIST_POWERLAW ? gmo_pl_g(Xc, c->dist.p) * c->pl_ang : gmo_G_of_Xc(Xc);
+}
+
 /* j at (nu, angle) in zone z; cos_th = cosine to the field. */
 static double zone_j(const gmo_ctx *c, int z, double nu, double cos_th)
 {
@@ -278,13 +311,13 @@ static double zone_j(const gmo_ctx *c, int z, double nu, double cos_th)
     double s2 = 1.0 - cos_th * cos_th;
     if (!(s2 > 0.0)) return 0.0;
     double s = sqrt(s2);
-    return c->A[z] * s * gmo_g_of_X(nu / (c->nu_c[z] * s));
+    return c->A[z] * s * shape_g(c, nu / (c->nu_c[z] * s));
 }
 
 static double zone_J(const gmo_ctx *c, int z, double nu)
 {
     if (c->A[z] == 0.0) return 0.0;
-    return 4.0 * M_PI * c->A[z] * gmo_G_of_Xc(nu / c->nu_c[z]);
+    return 4.0 * M_PI * c->A[z] * shape_G(c, nu / c->nu_c[z]);
 }
 
 /* ln w at ln nu: linear between nodes (reading), clamped at the ends. */
@@ -415,7 +448,7 @@ int gmo_make_superphotons(gmo_ctx *c, const gmo_emit_params *p, uint64_t *n_made
                 continue;
             }
             if (c->nu_c[i] != last_nuc) {
-                for (int k = 0; k < nw; ++k) Gk[k] = gmo_G_of_Xc(nu[k] / c->nu_c[i]);
+                for (int k = 0; k < nw; ++k) Gk[k] = shape_G(c, nu[k] / c->nu_c[i]);
                 last_nuc = c->nu_c[i];
             }
             for (int k = 0; k < nw; ++k) Jz[(size_t)i * nw + k] = 4.0 * M_PI * c->A[i] * Gk[k];
@@ -531,6 +564,20 @@ static int64_t add_event(worker *wk, const uint32_t s[3], const uint32_t par[3],
     return (int64_t)wk->ev_n++;
 }
 
+/* ln sigma/sigma_T of the power law, linear in ln eps between the nodes,
+ * clamped to the end nodes (as the thermal table). */
+static double pl_sigma_lookup(const double *t, double eps)
+{
+    const double le0 = log(GMO_SH_E_MIN), le1 = log(GMO_SH_E_MAX);
+    double b = (log(eps) - le0) / ((le1 - le0) / (GMO_SH_NE - 1));
+    if (b < 0.0) b = 0.0;
+    if (b > GMO_SH_NE - 1) b = GMO_SH_NE - 1;
+    int j = (int)floor(b);
+    if (j > GMO_SH_NE - 2) j = GMO_SH_NE - 2;
+    double f = b - j;
+    return exp((1.0 - f) * t[j] + f * t[j + 1]);
+}
+
 typedef struct {
     double nua, nus, b;
     int vacuum;
@@ -556,15 +603,21 @@ static void coefficients(const gmo_ctx *c, const gmo_track_params *tp, const dou
         double cth = dot4(g, k, bh) / ef;
         if (cth > 1.0) cth = 1.0;
         if (cth < -1.0) cth = -1.0;
-        double j = zone_j(c, z, nuf, cth);
-        if (j > 0.0) {
-            double x_ = ef / c->theta[z];
-            double alpha = j * expm1(x_) / (2.0 * GMO_HPL * nuf * nuf * nuf / (GMO_CL * GMO_CL));
-            out->nua = nuf * alpha;
+        if (c->dist.kind == GMO_DIST_POWERLAW) {
+            out->nua = gmo_pl_nualpha(&c->dist, c->n_e[z], c->B[z], nuf, cth);
+        } else {
+            double j = zone_j(c, z, nuf, cth);
+            if (j > 0.0) {
+                double x_ = ef / c->theta[z];
+                double alpha = j * expm1(x_) / (2.0 * GMO_HPL * nuf * nuf * nuf / (GMO_CL * GMO_CL));
+                out->nua = nuf * alpha;
+            }
         }
     }
     if (tp->scattering)
-        out->nus = nuf * c->n_e[z] * GMO_SIGT * gmo_sigma_hot_lookup(c->sh, c->theta[z], ef);
+        out->nus = nuf * c->n_e[z] * GMO_SIGT *
+                   (c->dist.kind == GMO_DIST_POWERLAW ? pl_sigma_lookup(c->shpl, ef)
+                                                      : gmo_sigma_hot_lookup(c->sh, c->theta[z], ef));
     double b = 1.0;
     switch (tp->bias_mode) {
     case GMO_BIAS_CONST: b = tp->bias_value; break;
@@ -666,8 +719,8 @@ static void scatter_event(const gmo_ctx *c, const gmo_track_params *tp, worker *
         scatter_tetrad(g, u, bh, has_b, ks, e, &eps);
         eps_in = eps;
         double kf[4];
-        gmo_scatter_in_frame(&ch.rng, c->theta[z], eps, NULL, NULL, kf,
-                             &wk->stats[GMO_S_E_TRIALS], &wk->stats[GMO_S_ANG_TRIALS]);
+        gmo_scatter_in_frame_dist(&ch.rng, &c->dist, c->theta[z], eps, NULL, NULL, kf,
+                                  &wk->stats[GMO_S_E_TRIALS], &wk->stats[GMO_S_ANG_TRIALS]);
         from_frame(e, kf, kchild);
     } else {
         for (int m = 0; m < 4; ++m) kchild[m] = ks[m];   /* unreachable: tau_s > 0 */
@@ -1068,6 +1121,13 @@ int gmo_track_scatter(gmo_ctx *c, const gmo_track_params *tp, uint64_t root_begi
             }
         }
         memcpy(c->sh, sh_cache, sizeof(double) * GMO_SH_NT * GMO_SH_NE);
+    }
+    if (tp->scattering && c->dist.kind == GMO_DIST_POWERLAW && !c->shpl) {
+        c->shpl = malloc(sizeof(double) * GMO_SH_NE);
+        const double le0 = log(GMO_SH_E_MIN), le1 = log(GMO_SH_E_MAX);
+        #pragma omp parallel for schedule(dynamic, 4)
+        for (int j = 0; j < GMO_SH_NE; ++j)
+            c->shpl[j] = log(gmo_sigma_pl_direct(&c->dist, exp(le0 + (le1 - le0) * j / (GMO_SH_NE - 1))));
     }
 #ifdef _OPENMP
     int nt = n_threads > 0 ? n_threads : omp_get_max_threads();

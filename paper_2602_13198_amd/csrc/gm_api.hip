@@ -1581,8 +1581,14 @@ gm_status gm_cells_fill_table(gm_ctx *c, int instance, const gm_importance_map *
     C.acc = c->cell_acc.p;
     C.nz = I.nz;
     C.zrec = I.zrec.p;
-    C.ratio_all = c->cell_tot[0] / c->cell_tot[1];
-    C.prior_w = prior * c->cell_tot[1] / std::max(c->cell_tot[2], 1.0);     // `prior` records' mean weight
+    C.per_photon = m->per_photon ? 1 : 0;
+    if (C.per_photon) {
+        C.ratio_all = c->cell_tot[0] / std::max(c->cell_tot[2], 1.0);
+        C.prior_w = prior;                                                    // `prior` records
+    } else {
+        C.ratio_all = c->cell_tot[0] / c->cell_tot[1];
+        C.prior_w = prior * c->cell_tot[1] / std::max(c->cell_tot[2], 1.0);  // `prior` records' mean weight
+    }
     C.map = ImpMap{m->kind, m->a, m->b, m->alpha, m->shift};
     C.neutral = 0.0;
     C.table = tab;

@@ -142,7 +142,8 @@ struct CellArgs {
     // fill
     int nz;
     const double *zrec;
-    double prior_w, ratio_all;     // shrinkage: prior weight and the overall ratio
+    double prior_w, ratio_all;     // shrinkage: prior weight (or records) and the overall ratio
+    int per_photon;                // ratio over records instead of summed weight
     ImpMap map;
     double neutral;
     double *table;
@@ -190,7 +191,8 @@ __global__ __launch_bounds__(256) void cells_fill_kernel(CellArgs C)
         // the node's centre in v, and the cell node holding it
         const double v = C.lo + (C.hi - C.lo) * k / (C.n_nodes - 1);
         const double *a = C.acc + ((size_t)cell_of_zone(C, z) * C.n_nodes + node_of(C, v)) * 3;
-        const double ratio = a[2] > 0.0 ? (a[0] + C.prior_w * C.ratio_all) / (a[1] + C.prior_w) : C.ratio_all;
+        const double den = C.per_photon ? a[2] : a[1];
+        const double ratio = a[2] > 0.0 ? (a[0] + C.prior_w * C.ratio_all) / (den + C.prior_w) : C.ratio_all;
         C.table[r] = imp_value(C.map, log(fmax(ratio, 1e-300)));
     }
 }

@@ -81,7 +81,7 @@ class GmEmitParams(C.Structure):
 class GmImportanceMap(C.Structure):
     _fields_ = [("table", C.c_int), ("n_nodes", C.c_int), ("lo", C.c_double), ("hi", C.c_double),
                 ("kind", C.c_int), ("a", C.c_double), ("b", C.c_double), ("alpha", C.c_double),
-                ("shift", C.c_double)]
+                ("shift", C.c_double), ("per_photon", C.c_int)]
 
 
 TABLE_BIAS, TABLE_EMISSION = 0, 1
@@ -455,9 +455,10 @@ class Context:
         _check(load_library().gm_set_tally_mode(self._h, int(mode)))
 
     @staticmethod
-    def importance_map(table, n_nodes, lo, hi, kind=IMP_LINEAR, a=1.0, b=0.0, alpha=0.0, shift=0.0):
+    def importance_map(table, n_nodes, lo, hi, kind=IMP_LINEAR, a=1.0, b=0.0, alpha=0.0, shift=0.0,
+                       per_photon=0):
         return GmImportanceMap(int(table), int(n_nodes), float(lo), float(hi), int(kind), float(a), float(b),
-                               float(alpha), float(shift))
+                               float(alpha), float(shift), int(per_photon))
 
     def mlp_fill_table(self, instance, imap, output, mu, sd):
         m = np.ascontiguousarray(mu, dtype=np.float32)

@@ -8,10 +8,12 @@ sampled root emission, each carrying the score of the photon it created --
 the sum, over that photon and every descendant that escapes into a tally
 bin, of its escaping energy times the bin's score weight):
 
-* adaptive: no network.  The importance of a unit-weight photon created at
-  (zone, photon energy) is estimated by the ratio of summed scores to summed
-  weights of the records that fall in a coarse spatial cell and an energy
-  node, shrunk towards the overall mean where records are few;
+* adaptive: no network.  The importance of a photon created at (zone,
+  photon energy) is estimated from the records that fall in a coarse
+  spatial cell and an energy node -- summed scores over summed weights
+  (per unit weight, for the bias) or over the number of records (per
+  photon, for the emission) -- shrunk towards the overall mean where
+  records are few;
 * learned: a network 6 -> 64 -> 64 -> 2 (the library's matrix-core kernels,
   BF16 operands, FP32 accumulation) trained on the same records with the
   log-link Poisson deviance, whose minimiser is the log of the mean
@@ -20,11 +22,14 @@ bin, of its escaping energy times the bin's score weight):
 
 Both give the same two tables: the weight-window bias b = clamp(c_b w I_sc,
 1, b_max), so that children carry weights near 1/(c_b I_sc), and the
-emission proposal w_i(nu) = c_w / I_em(zone, nu), which spends roots where
-they contribute most.  Any b >= 1 and any positive emission weight keep the
+defensive emission proposal w_i(nu) = w(nu) / [(1 - alpha) + alpha S_em /
+S_bar] (S_em the score a root born there carries, S_bar its mean over the
+plain roots), which spends roots where they contribute most and keeps at
+least 1 - alpha of the plain roots elsewhere.  Any b >= 1 and any positive emission weight keep the
 estimator unbiased (child w/b and parent w(1 - 1/b), Scattering section;
 the expected emitted luminosity of eq:weight_calc does not depend on w).
-c_b and c_w hold the children and roots to the plain run's budget.
+c_b and the emission table's shift hold the children and roots to the plain
+run's budget.
 
 Score weights are the relative-error weights of the measure, 1 / L(bin) on
 the bins the pilot rounds resolve; the pilot rounds are plain rounds and
@@ -190,8 +195,18 @@ class Network:
 # ---------------------------------------------------------------------------
 # tables (built on the device by the library)
 # ---------------------------------------------------------------------------
+def emission_band(ev, nodes, pad=0.5):
+    """ln nu range of the emission records (the band the plain roots are
+    born in), padded by `pad` node spacings on each side."""
+    em = ev[(ev["gen"] == 0) & (ev["w"] > 0)]
+    ln_nu = np.log(em["eps"] * MEC2_OVER_H)
+    lo, hi = float(ln_nu.min()), float(ln_nu.max())
+    d = (hi - lo) / max(nodes - 1, 1)
+    return lo - pad * d, hi + pad * d
+
+
 def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=True, use_emission=True,
-                 alpha=0.5, nodes=16, root_stride=4):
+                 alpha=0.5, nodes=16, em_nodes=32, root_stride=4, train_steps=300):
     """Tables of the adaptive ("cells") or learned ("network") form from the
     records in the context's event log, built on the device; sets the
     instance's weight-window bias table and defensive emission table.
@@ -199,32 +214,43 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
     the mean bias over the pilot's scattering opportunities is the plain b
     (the parent's weight at a pilot scattering is b times its child's, and
     the sum over records of w_child I_sc is the summed score).  Emission:
-    mixture with I_em / I_mean, I_mean = summed score / summed weight of the
-    emission records, the constant fixed by the expected roots."""
+    em_nodes nodes over the band the pilot's roots were born in; S_em is
+    the score a root born at (zone, nu) carries (per photon, not per unit
+    weight: a root density r times the plain one and weights divided by r
+    leave the estimator unbiased, and its variance, the plain roots' mean
+    of (w S)^2 / r, is least for r proportional to w S, the plain root's
+    score); the table is ln((1 - alpha) + alpha S_em / S_bar) with S_bar
+    the mean of S_em over the plain roots (the expected roots of the table
+    ln S_em over those of the plain method), so that the plain roots' mean
+    of the density ratio is 1 and every region keeps at least 1 - alpha of
+    its plain roots; a last shift, fixed by the expected roots, absorbs
+    what the interpolation between nodes leaves."""
     info, t0 = {}, time.perf_counter()
     e = wl.emit
-    lo_nu, hi_nu = math.log(e["nu_min"]), math.log(e["nu_max"])
     emit_round = dict(e, n_target=float(n_s))
     nb0 = ctx.expected_roots(emit_round, inst)
+    ev = ctx.read_event_log()
+    info["read_s"] = time.perf_counter() - t0
+    lo_nu, hi_nu = emission_band(ev, em_nodes)
+    info["emission_band_hz"] = [math.exp(lo_nu), math.exp(hi_nu)]
     m_bias = GM.Context.importance_map(GM.TABLE_BIAS, nodes, LN_EPS[0], LN_EPS[1], GM.IMP_LINEAR)
-    m_em = GM.Context.importance_map(GM.TABLE_EMISSION, nodes, lo_nu, hi_nu, GM.IMP_MIXTURE, alpha=alpha)
+    m_em = GM.Context.importance_map(GM.TABLE_EMISSION, em_nodes, lo_nu, hi_nu, GM.IMP_LINEAR, per_photon=1)
     if mode == "cells":
+        del ev
         tot_sc = ctx.cells_accumulate(inst, m_bias)
         if use_bias:
             m_bias.b = math.log(tot_sc[2] / max(tot_sc[0], 1e-300))
             ctx.cells_fill_table(inst, m_bias)
         tot_em = ctx.cells_accumulate(inst, m_em)
-        m_em.b = -math.log(max(tot_em[0], 1e-300) / tot_em[1])
+        b_I = 0.0                                            # the cells' table is ln S itself
         fill = lambda m: ctx.cells_fill_table(inst, m)       # noqa: E731
         info["records"] = [int(tot_sc[2]), int(tot_em[2])]
     else:
-        ev = ctx.read_event_log()
-        info["read_s"] = time.perf_counter() - t0
         sc, em = split_records(ev, root_stride)
         del ev
         zf = zone_features(wl)
         X = np.concatenate([rows(zf, sc["zone"], np.log(sc["eps"])), rows(zf, em["zone"], np.log(em["eps"]))])
-        t_sc, t_em = sc["score"] / sc["w"], em["score"] / em["w"]
+        t_sc, t_em = sc["score"] / sc["w"], em["score"]
         m_sc, m_em_mean = max(t_sc.mean(), 1e-300), max(t_em.mean(), 1e-300)
         T = np.zeros((len(X), 2))
         Cw = np.zeros((len(X), 2))
@@ -232,7 +258,7 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
         T[len(sc):, 1], Cw[len(sc):, 1] = t_em / m_em_mean, 1.0
         net = Network(seed=net_seed)
         t1 = time.perf_counter()
-        hist = net.fit(ctx, X, T, Cw)
+        hist = net.fit(ctx, X, T, Cw, steps=train_steps)
         info["train_s"] = time.perf_counter() - t1
         info["loss_first_last"] = [hist[0][1], hist[-1][1]]
         info["records"] = [int(len(sc)), int(len(em))]
@@ -240,9 +266,14 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
             # ln I = y + ln(mean t); c_b = records / summed score
             m_bias.b = math.log(m_sc) + math.log(len(sc) / max(sc["score"].sum(), 1e-300))
             ctx.mlp_fill_table(inst, m_bias, 0, net.mu, net.sd)
-        m_em.b = math.log(m_em_mean) - math.log(max(em["score"].sum(), 1e-300) / em["w"].sum())
+        b_I = math.log(m_em_mean)                            # ln S = y + ln(mean t)
         fill = lambda m: ctx.mlp_fill_table(inst, m, 1, net.mu, net.sd)   # noqa: E731
     if use_emission:
+        # the plain roots' mean of S: expected roots of the table ln S over the plain ones
+        m_em.b = b_I
+        fill(m_em)
+        i_bar = ctx.expected_roots(emit_round, inst) / nb0
+        m_em.kind, m_em.alpha, m_em.b = GM.IMP_MIXTURE, alpha, b_I - math.log(max(i_bar, 1e-300))
         fill(m_em)
         nb1 = ctx.expected_roots(emit_round, inst)
         m_em.shift = math.log(nb0 / max(nb1, 1e-300))
@@ -262,7 +293,7 @@ FORMS = {
 }
 
 
-def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rounds=4, b_max=100.0,
+def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rounds=1, b_max=100.0,
                   forms=("adaptive", "learned"), log=None, alpha=0.5, variants=None):
     """Time to 1 % spectral error of the plain uniform bias and of the
     adaptive and learned forms on one workload (median over seeds), against
@@ -336,7 +367,8 @@ def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rou
         if use_bias:
             parts.append("weight-window bias b = clamp(c_b w I_sc, 1, %g)" % b_max)
         if use_em:
-            parts.append("defensive emission proposal w / [(1 - %g) + %g I_em / I_mean]" % (alpha, alpha))
+            parts.append("defensive emission proposal w / [(1 - %g) + %g S_em / S_bar] (S_em the score per root, "
+                         "S_bar its plain mean)" % (alpha, alpha))
         out[name] = {
             "seconds_median": med, "seconds": res, "runs": infos,
             "what": ("importance per (8x8x8-zone cell, energy node) from summed scores / summed weights"

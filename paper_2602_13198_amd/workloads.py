@@ -43,6 +43,7 @@ METRIC_KS_MKS = 1
 METRIC_FLAT_SPH = 2
 
 BIAS_CONST, BIAS_THETA2, BIAS_GEN2, BIAS_TABLE, BIAS_WINDOW = 0, 1, 2, 3, 4
+DIST_THERMAL, DIST_POWERLAW = 0, 1
 BIAS_LEARNED = BIAS_TABLE
 
 
@@ -58,6 +59,9 @@ class Workload:
     emit: dict
     track: dict
     meta: dict = field(default_factory=dict)
+    # electrons of every zone: None (thermal at theta_e) or a power law
+    # dict(kind=DIST_POWERLAW, p=..., gamma_min=..., gamma_max=...)
+    electrons: dict | None = None
 
     @property
     def n_zones(self) -> int:
@@ -67,13 +71,13 @@ class Workload:
         e = dict(self.emit)
         e.update(kw)
         return Workload(self.name, self.grid, self.n_e, self.theta_e, self.B, self.ucon,
-                        self.bcon, e, self.track, dict(self.meta))
+                        self.bcon, e, self.track, dict(self.meta), self.electrons)
 
     def with_track(self, **kw) -> "Workload":
         t = dict(self.track)
         t.update(kw)
         return Workload(self.name, self.grid, self.n_e, self.theta_e, self.B, self.ucon,
-                        self.bcon, self.emit, t, dict(self.meta))
+                        self.bcon, self.emit, t, dict(self.meta), self.electrons)
 
 
 def default_track(**kw) -> dict:
@@ -185,6 +189,29 @@ def paper_scattering_sphere(n1=8192, n2=128, n_target=1e5, seed=0, n_sc_max=4, *
     return log_r_sphere(n1=n1, n2=n2, theta_e=3.0, n_e=1e18, n_target=n_target, seed=seed,
                         name="paper_scattering_sphere", scattering=1, bias_mode=BIAS_GEN2,
                         bias_value=R, n_sc_max=n_sc_max, **kw)
+
+
+def power_law_sphere(n=32, R_cm=1e14, n_e=1.0, B=1.0, p=3.0, gamma_min=10.0, gamma_max=1e5, tau_T=0.0,
+                     n_target=1e5, seed=0, nu_min=1e9, nu_max=1e16, bias_value=None, name="power_law_sphere",
+                     **track_kw) -> Workload:
+    """Uniform sphere of non-thermal electrons (isotropic power law of index
+    p on [gamma_min, gamma_max], the same in every zone) on the 32^3
+    Cartesian grid of the flat spheres, B along z, static plasma; emission
+    over [nu_min, nu_max], inside nu_c(gamma_min) << nu << nu_c(gamma_max)
+    where the power law's asymptotic synchrotron forms hold.  tau_T > 0 sets
+    n_e = tau_T / (sigma_T R) and turns on Compton scattering off the same
+    electrons with a constant bias (1 / tau_T unless given), four
+    generations.  Theta_e is set to 1 (unused by a power law except by the
+    Theta_e^2 bias)."""
+    if tau_T > 0.0:
+        n_e = tau_T / (SIGMA_T * R_cm)
+        track_kw = dict(dict(scattering=1, bias_mode=BIAS_CONST,
+                             bias_value=bias_value if bias_value else 1.0 / tau_T, n_sc_max=4), **track_kw)
+    wl = sphere(n=n, R_cm=R_cm, theta_e=1.0, n_e=n_e, B=B, n_target=n_target, seed=seed, nu_min=nu_min,
+                nu_max=nu_max, name=name, **track_kw)
+    wl.electrons = dict(kind=DIST_POWERLAW, p=float(p), gamma_min=float(gamma_min), gamma_max=float(gamma_max))
+    wl.meta.update(p=p, gamma_min=gamma_min, gamma_max=gamma_max, tau_T=tau_T)
+    return wl
 
 
 def thin_sphere(n_target=1e5, seed=0, n=32) -> Workload:

@@ -75,9 +75,9 @@ def test_network_table(gm, table):
 
 
 def test_cell_tables_and_expected_roots(gm):
-    """Cell sums and ratios against numpy on the same records; the expected
-    roots equal the make's summed expected counts, with and without the
-    emission table."""
+    """Cell sums and ratios (per unit weight and per photon) against numpy
+    on the same records; the expected roots equal the make's summed
+    expected counts, with and without the emission table."""
     wl = _wl()
     c = gm.Context(0)
     c.load_zones(wl)
@@ -118,6 +118,15 @@ def test_cell_tables_and_expected_roots(gm):
     for k in range(n):
         j = zcell * n + k
         r = np.where(N[j] > 0, (S[j] + pw * ratio_all) / (Wt[j] + pw), ratio_all)
+        np.testing.assert_allclose(tab[on, k], np.log(r) + 0.7, rtol=0, atol=1e-10)
+    # per photon: score over records, shrunk with 5 records
+    mb.per_photon = 1
+    c.cells_fill_table(0, mb, prior=5.0)
+    tab = c.read_table(0, 0)
+    ratio_n = S.sum() / N.sum()
+    for k in range(n):
+        j = zcell * n + k
+        r = np.where(N[j] > 0, (S[j] + 5.0 * ratio_n) / (N[j] + 5.0), ratio_n)
         np.testing.assert_allclose(tab[on, k], np.log(r) + 0.7, rtol=0, atol=1e-10)
     # the emission table changes the expected roots by the mapped factor
     me = gm.Context.importance_map(gm.TABLE_EMISSION, n, math.log(1e8), math.log(1e16), gm.IMP_LINEAR, a=0.0, b=0.5)
