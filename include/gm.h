@@ -78,6 +78,23 @@ typedef struct {
  * the host for host inputs and in a kernel for device inputs; a failure is
  * GM_EINVAL with the first bad zone named.  bcon gives only the field
  * direction; its normalisation is ignored. */
+/* Electrons of every zone of an instance.  Thermal: Maxwell-Juttner at the
+ * zone's theta_e (Emissivity and Scattering sections).  Power law (the
+ * non-thermal distributions the paper's Conclusions name as future work):
+ * isotropic n(gamma) = n_e C gamma^-p on [gamma_min, gamma_max], with the
+ * power law's asymptotic synchrotron emissivity and absorption (valid for
+ * nu_c(gamma_min) << nu << nu_c(gamma_max)) and Compton scattering off the
+ * distribution itself; FP64 only (GM_PRECISION_F32_EMISSIVITY with a power
+ * law is GM_EUNSUPPORTED).  Instances share launches only with identical
+ * electrons. */
+#define GM_DIST_THERMAL  0
+#define GM_DIST_POWERLAW 1
+typedef struct {
+    int    kind;            /* GM_DIST_*                                          */
+    double p;               /* power law: index > 1                               */
+    double gamma_min, gamma_max;   /* power law: 1 <= gamma_min < gamma_max, finite */
+} gm_electrons;
+
 typedef struct {
     int           on_device;
     const double *n_e;      /* electron density, cm^-3                            */
@@ -85,6 +102,7 @@ typedef struct {
     const double *B;        /* field strength, Gauss                              */
     const double *ucon;     /* fluid 4-velocity, contravariant code components    */
     const double *bcon;     /* field direction 4-vector                            */
+    gm_electrons  electrons;/* zeroed: thermal                                     */
 } gm_zones;
 
 typedef struct {
@@ -478,6 +496,12 @@ gm_status gm_mlp_fill_table(gm_ctx *ctx, int instance, const gm_importance_map *
  * both calls must name the same table and nodes. */
 gm_status gm_cells_accumulate(gm_ctx *ctx, int instance, const gm_importance_map *map, const int blocks[3],
                               double totals[3]);
+/* Map an instance's table (map->table, with the map's node layout) in
+ * place, its values taken as ln I: T <- map(T) for every zone holding
+ * plasma (the others keep their neutral value) -- the mixture and the
+ * shift of the emission proposal without a second inference. */
+gm_status gm_remap_table(gm_ctx *ctx, int instance, const gm_importance_map *map);
+
 /* Copy an instance's bias or emission table (GM_TABLE_*) into a host
  * buffer of n = nzones x nodes doubles; n_nodes (may be NULL) receives the
  * node count; host_out = NULL only reports it.  Synchronises. */

@@ -118,6 +118,10 @@ struct Instance {
     // score weights [n_theta][n_nu] of the event records (none: 1)
     DevBuf<double> sw;
     int sw_n = 0;
+    // electrons; the power law's hot cross-section table, built on first use
+    gm_electrons el{};
+    DevBuf<double> sigpl;
+    bool sigpl_built = false;
 };
 
 }  // namespace
@@ -234,6 +238,55 @@ static gm_status build_tables(gm_ctx *c)
     HIPCHK(c->gl_w.ensure(16));
     HIPCHK(hipMemcpy(c->gl_x.p, x.data(), 16 * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->gl_w.p, w.data(), 16 * sizeof(double), hipMemcpyHostToDevice));
+    return GM_OK;
+}
+
+// Electron descriptor of an instance for the kernels.
+static Elec elec_of(const Instance &I)
+{
+    Elec E{};
+    E.kind = I.el.kind;
+    if (E.kind == GM_DIST_POWERLAW) {
+        const double p = I.el.p;
+        E.p = p;
+        E.ga = std::pow(I.el.gamma_min, 1.0 - p);
+        E.gb = std::pow(I.el.gamma_max, 1.0 - p);
+        E.inv1mp = 1.0 / (1.0 - p);
+        E.eg = -0.5 * (p - 1.0);
+        E.ea = -0.5 * (p + 2.0);
+        E.ang = 0.5 * std::sqrt(kPi) * std::tgamma(0.25 * (p + 5.0)) / std::tgamma(0.25 * (p + 7.0));
+        E.sig = I.sigpl.p;
+        E.le0 = std::log(kShEMin);
+        E.inv_de = (kShNE - 1) / (std::log(kShEMax) - std::log(kShEMin));
+    }
+    return E;
+}
+
+static bool same_electrons(const gm_electrons &a, const gm_electrons &b)
+{
+    return a.kind == b.kind && (a.kind == GM_DIST_THERMAL ||
+                                (a.p == b.p && a.gamma_min == b.gamma_min && a.gamma_max == b.gamma_max));
+}
+
+// The power law's hot cross section of an instance (its eps nodes those of
+// the thermal table).
+static gm_status ensure_sigma_pl(gm_ctx *c, Instance &I)
+{
+    if (I.sigpl_built) return GM_OK;
+    HIPCHK(I.sigpl.ensure(kShNE));
+    PlBuildArgs S;
+    S.gl_x = c->gl_x.p;
+    S.gl_w = c->gl_w.p;
+    S.table = I.sigpl.p;
+    S.le0 = std::log(kShEMin);
+    S.de = (std::log(kShEMax) - std::log(kShEMin)) / (kShNE - 1);
+    S.p = I.el.p;
+    S.lg1 = std::log(I.el.gamma_min);
+    S.lg2 = std::log(I.el.gamma_max);
+    sigma_pl_build_kernel<<<kShNE, 256, 0, c->stream>>>(S);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    I.sigpl_built = true;
     return GM_OK;
 }
 
@@ -359,6 +412,11 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
     if (nzl > (1ll << 31) - 1) return fail(GM_EINVAL, "too many zones");
     int nz = (int)nzl;
     if (!z->n_e || !z->theta_e || !z->B || !z->ucon || !z->bcon) return fail(GM_EINVAL, "zone array NULL");
+    const gm_electrons &el = z->electrons;
+    if (el.kind != GM_DIST_THERMAL &&
+        !(el.kind == GM_DIST_POWERLAW && el.p > 1.0 && el.gamma_min >= 1.0 && el.gamma_max > el.gamma_min &&
+          std::isfinite(el.gamma_max)))
+        return fail(GM_EINVAL, "bad electron distribution");
     gm_status s = set_device(c);
     if (s != GM_OK) return s;
     // stage inputs on the device
@@ -436,6 +494,16 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
     P.a_spin = g->a_spin;
     P.h_slope = g->h_slope;
     P.r_h = kerr_horizon(g->a_spin, mass);
+    P.dist = el.kind;
+    P.pl_aj = P.pl_aa = 0.0;
+    if (el.kind == GM_DIST_POWERLAW) {
+        const double p = el.p;
+        const double C = (p - 1.0) / (std::pow(el.gamma_min, 1.0 - p) - std::pow(el.gamma_max, 1.0 - p));
+        P.pl_aj = std::sqrt(3.0) * kE * kE * kE * C * std::tgamma((3.0 * p + 19.0) / 12.0) *
+                  std::tgamma((3.0 * p - 1.0) / 12.0) / (4.0 * kPi * kMe * kC * kC * (p + 1.0));
+        P.pl_aa = std::sqrt(3.0) * kE * kE * C * std::tgamma((3.0 * p + 2.0) / 12.0) *
+                  std::tgamma((3.0 * p + 22.0) / 12.0) / (12.0 * kMe * kC);
+    }
     P.max_i1 = c->flags.p + 3;
     int max_i1 = -1;
     HIPCHK(hipMemcpyAsync(P.max_i1, &max_i1, sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -449,6 +517,8 @@ gm_status gm_load_zones(gm_ctx *c, int instance, const gm_grid *g, const gm_zone
     I.grid = *g;
     I.nz = nz;
     I.max_i1 = max_i1;
+    if (!same_electrons(I.el, el)) I.sigpl_built = false;
+    I.el = el;
     I.loaded = true;
     I.made = false;
     I.pending = false;
@@ -498,7 +568,7 @@ static gm_status make_one(gm_ctx *c, int instance, const gm_emit_params *p, uint
     }
     EmitArgs E;
     E.zrec = I.zrec.p; E.vol = I.vol.p; E.emits = I.emits.p; E.nu_nodes = I.nu_nodes.p;
-    E.nz = nz; E.nw = nw; E.G = c->G; E.partial = I.partial.p; E.n_blocks = nblk;
+    E.nz = nz; E.nw = nw; E.G = c->G; E.el = elec_of(I); E.partial = I.partial.p; E.n_blocks = nblk;
     E.w_node = I.w_node.p; E.ln_w = I.ln_w.p; E.span = span; E.n_target = p->n_target;
     E.w_floor_rel = p->w_floor_rel; E.nbar = I.nbar.p; E.fmax = I.fmax.p; E.count = I.count.p;
     E.key0 = (uint32_t)p->seed; E.key1 = (uint32_t)(p->seed >> 32); E.inst = instance;
@@ -711,6 +781,7 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
     A.ln_w = I.ln_w.p;
     A.fmax = I.fmax.p;
     A.G = c->G;
+    A.el = elec_of(I);
     A.spec = I.spec.p;
     A.ledger = I.ledger.p;
     A.stats = I.stats.p;
@@ -1031,6 +1102,16 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
             return fail(GM_EINVAL, "instance %d: score weights of %d bins, tally of %d", i, I.sw_n,
                         tp->n_nu * tp->n_theta);
     }
+    for (int i = 0; i < GM_MAX_INSTANCES; ++i) {
+        Instance &I = c->inst[i];
+        if (!I.pending || I.el.kind == GM_DIST_THERMAL) continue;
+        if (tp->precision != GM_PRECISION_F64)
+            return fail(GM_EUNSUPPORTED, "instance %d: power-law electrons run in FP64 only", i);
+        if (tp->scattering) {
+            s = ensure_sigma_pl(c, I);
+            if (s != GM_OK) return s;
+        }
+    }
     if (tp->scattering) {
         s = ensure_sigma_hot(c);
         if (s != GM_OK) return s;
@@ -1053,11 +1134,17 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     const size_t per_inst = per_small + (size_t)tp->n_theta * tp->n_nu * 3 * 8;
     const size_t acc_budget = 56 * 1024;
     std::vector<long long> acc(S_N, 0);
-    for (int metric = 0; metric < 3; ++metric) {
+    std::vector<bool> taken(GM_MAX_INSTANCES, false);
+    for (int lead = 0; lead < GM_MAX_INSTANCES; ++lead) {
+        // the pending instances of lead's metric and electrons, in order
+        if (!c->inst[lead].pending || taken[lead]) continue;
         std::vector<int> pend;
-        for (int i = 0; i < GM_MAX_INSTANCES; ++i)
-            if (c->inst[i].pending && c->inst[i].grid.metric == metric) pend.push_back(i);
-        if (pend.empty()) continue;
+        for (int i = lead; i < GM_MAX_INSTANCES; ++i)
+            if (c->inst[i].pending && !taken[i] && c->inst[i].grid.metric == c->inst[lead].grid.metric &&
+                same_electrons(c->inst[i].el, c->inst[lead].el)) {
+                pend.push_back(i);
+                taken[i] = true;
+            }
         const int want = std::min((int)pend.size(), c->max_batch);
         const int lds_fit = (int)(acc_budget / per_inst);
         bool hbm = c->tally_mode == 2 || (c->tally_mode == 0 && lds_fit < want);
@@ -1458,6 +1545,33 @@ static gm_status map_target(gm_ctx *c, int instance, const gm_importance_map *m,
 static double map_v_shift(const gm_importance_map *m)
 {
     return m->table == GM_TABLE_EMISSION ? std::log(kMeC2 / kH) : 0.0;
+}
+
+gm_status gm_remap_table(gm_ctx *c, int instance, const gm_importance_map *m)
+{
+    gm_status s = check_map(c, instance, m);
+    if (s != GM_OK) return s;
+    Instance &I = c->inst[instance];
+    const bool bias = m->table == GM_TABLE_BIAS;
+    double *tab = bias ? I.lnb.p : I.mtab.p;
+    const int n = bias ? I.lnb_n : I.mt_n;
+    const double lo = bias ? I.lnb_lo : I.mt_lo, hi = bias ? I.lnb_hi : I.mt_hi;
+    if (!tab || n != m->n_nodes || lo != m->lo || hi != m->hi || (!bias && !I.mt_on))
+        return fail(GM_ESTATE, "no table of this instance with the map's node layout");
+    s = set_device(c);
+    if (s != GM_OK) return s;
+    RemapArgs R;
+    R.zrec = I.zrec.p;
+    R.nz = I.nz;
+    R.n_nodes = n;
+    R.map = ImpMap{m->kind, m->a, m->b, m->alpha, m->shift};
+    R.table = tab;
+    const long long cnt = (long long)I.nz * n;
+    remap_table_kernel<<<(unsigned)std::min<long long>((cnt + 255) / 256, 65536), 256, 0, c->stream>>>(R);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (!bias) I.made = false;
+    return GM_OK;
 }
 
 gm_status gm_mlp_fill_table(gm_ctx *c, int instance, const gm_importance_map *m, int output, const float *mu,

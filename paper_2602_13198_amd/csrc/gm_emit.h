@@ -22,6 +22,9 @@ struct PrepArgs {
     int metric;                  // 0 flat Cartesian; else (ln r, x2, phi) grids: Kerr, flat spherical
     double a_spin, h_slope, r_h;
     int *max_i1;                 // largest first-axis index of a zone holding plasma (-1: none)
+    // electrons: 0 thermal; 1 power law, A = pl_aj n_e B, nu alpha = pl_aa n_e X^{-(p+2)/2}
+    int dist;
+    double pl_aj, pl_aa;
 };
 
 __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
@@ -61,14 +64,17 @@ __global__ __launch_bounds__(256) void zone_prep_kernel(PrepArgs P)
         sqrt_g = kerr_sqrt_neg_g(P.a_spin, P.h_slope, xc1, xc2);
         inside = exp(xc1) < P.r_h;
     }
-    double A = emis_coef(ne, th, B);
-    double nuc = nu_crit(th, B);
+    // power law: nu_c = 3 e B / (2 pi m c), and the absorption coefficient
+    // A_a in the slot of 1/Theta (no Kirchhoff law for it)
+    const bool pl = P.dist == 1;
+    double A = pl ? ((ne > 0.0 && B > 0.0) ? P.pl_aj * ne * B : 0.0) : emis_coef(ne, th, B);
+    double nuc = pl ? 3.0 * kE * B / (2.0 * kPi * kMe * kC) : nu_crit(th, B);
     r[Z_A] = A;
     r[Z_NUC] = nuc;
     r[Z_TH] = th;
     r[Z_NE] = ne;
     r[Z_LNTH] = th > 0.0 ? log(th) : 0.0;
-    r[Z_INVTH] = th > 0.0 ? 1.0 / th : 0.0;
+    r[Z_INVTH] = pl ? P.pl_aa * ne : (th > 0.0 ? 1.0 / th : 0.0);
     r[Z_INVNUC] = nuc > 0.0 ? 1.0 / nuc : 0.0;
     P.vol[z] = sqrt_g * P.dx[0] * P.dx[1] * P.dx[2] * P.L3;
     P.emits[z] = (A > 0.0 && !inside) ? 1 : 0;
@@ -142,6 +148,7 @@ struct EmitArgs {
     const double *nu_nodes;      // [nw] node frequencies
     int nz, nw;
     GCheb G;
+    Elec el;
     double *partial;             // [n_blocks][nw]
     int n_blocks;
     double *w_node, *ln_w;       // [nw]
@@ -158,9 +165,9 @@ struct EmitArgs {
     double mt_lo, mt_hi, lnnu_min;
 };
 
-GM_D double zone_J(const double *zr, double nu, const GCheb &G)
+GM_D double zone_J(const double *zr, double nu, const GCheb &G, const Elec &El)
 {
-    return 4.0 * kPi * zr[Z_A] * G_of_Xc(G, nu / zr[Z_NUC]);
+    return 4.0 * kPi * zr[Z_A] * shape_G(El, G, nu / zr[Z_NUC]);
 }
 
 __global__ __launch_bounds__(256) void phi_partial_kernel(EmitArgs E)
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(256) void phi_partial_kernel(EmitArgs E)
     const double *zr = E.zrec + (size_t)(on ? z : 0) * Z_STRIDE;
     double v = on ? E.vol[z] : 0.0;
     for (int k = 0; k < E.nw; ++k) {
-        double val = on ? v * zone_J(zr, E.nu_nodes[k], E.G) : 0.0;
+        double val = on ? v * zone_J(zr, E.nu_nodes[k], E.G, E.el) : 0.0;
         for (int off = 32; off >= 1; off >>= 1) val += __shfl_down(val, off);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = val;
         __syncthreads();
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(256) void count_kernel(EmitArgs E)
             if (E.mtab)
                 wk_ *= exp(-zone_table(E.mtab, E.mt_n, E.mt_lo, E.mt_hi, z,
                                        E.lnnu_min + E.span * k / (E.nw - 1)));
-            double F = zone_J(zr, E.nu_nodes[k], E.G) / wk_;
+            double F = zone_J(zr, E.nu_nodes[k], E.G, E.el) / wk_;
             double wk = (k == 0 || k == E.nw - 1) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
             s += wk * F;
             fm = fmax(fm, F);
@@ -392,6 +399,59 @@ __global__ __launch_bounds__(256) void sigma_hot_build_kernel(ShBuildArgs S)
         __syncthreads();
     }
     if (threadIdx.x == 0) S.table[node] = log(rn[0] / rd[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Hot cross section of power-law electrons, gamma^-p on [g1, g2] (the
+// Scattering section's average with the power law in place of the thermal
+// distribution), one block per eps node of the thermal table: outer in
+// ln gamma by composite 16-point Gauss-Legendre (64 panels), weight
+// gamma^{1-p}; inner in u = ln(1 - beta mu) as for the thermal table;
+// normalisation by the same outer rule.  Entries are ln(sigma / sigma_T).
+// ---------------------------------------------------------------------------
+struct PlBuildArgs {
+    const double *gl_x, *gl_w;
+    double *table;
+    double le0, de;
+    double p, lg1, lg2;
+};
+
+__global__ __launch_bounds__(256) void sigma_pl_build_kernel(PlBuildArgs S)
+{
+    __shared__ double rn[256], rd[256];
+    const int ie = blockIdx.x;
+    const double eps = exp(S.le0 + S.de * ie);
+    const int NP_OUT = 64, NP_IN = 8, NG = 16;
+    const double h = (S.lg2 - S.lg1) / NP_OUT;
+    double num = 0.0, den = 0.0;
+    for (int q = threadIdx.x; q < NP_OUT * NG; q += blockDim.x) {
+        int pan = q / NG, gi = q % NG;
+        double u = S.lg1 + h * (pan + 0.5 + 0.5 * S.gl_x[gi]);
+        double wv = 0.5 * h * S.gl_w[gi];
+        double gam = exp(u);
+        double wt = exp((1.0 - S.p) * u);
+        double beta = sqrt((gam - 1.0) * (gam + 1.0)) / gam;
+        double ulo = log1p(-beta), uhi = log1p(beta);
+        double hin = (uhi - ulo) / NP_IN;
+        double inner = 0.0;
+        for (int pi = 0; pi < NP_IN; ++pi)
+            for (int gj = 0; gj < NG; ++gj) {
+                double v = ulo + hin * (pi + 0.5 + 0.5 * S.gl_x[gj]);
+                double ev = exp(v);
+                inner += 0.5 * hin * S.gl_w[gj] * ev * ev * sigma_kn(gam * eps * ev);
+            }
+        inner /= (2.0 * beta);
+        num += wv * wt * inner;
+        den += wv * wt;
+    }
+    rn[threadIdx.x] = num;
+    rd[threadIdx.x] = den;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) { rn[threadIdx.x] += rn[threadIdx.x + s]; rd[threadIdx.x] += rd[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S.table[ie] = log(rn[0] / rd[0]);
 }
 
 __global__ void eval_G_kernel(GCheb G, const double *x, double *y, int n)

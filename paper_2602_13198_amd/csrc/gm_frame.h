@@ -189,7 +189,27 @@ struct ScatterCount { uint32_t e_trials, ang_trials; };
 
 GM_D double exp_variate(Rng &r, uint32_t k0, uint32_t k1) { return -log(1.0 - rng_uniform(r, k0, k1)); }
 
-GM_D void scatter_in_frame(Rng &r, uint32_t k0, uint32_t k1, double theta, double eps,
+// Power-law electrons: gamma by inverting the distribution function of the
+// power law, gamma = [g1^{1-p} - u (g1^{1-p} - g2^{1-p})]^{1/(1-p)}; mu and
+// the Klein-Nishina acceptance as for the thermal electrons.  Draws: gamma,
+// mu, the acceptance.
+GM_D void electron_power_law(Rng &r, uint32_t k0, uint32_t k1, const Elec &E, double eps, double &gam,
+                             double &beta, double &mu, ScatterCount &cnt)
+{
+    for (int64_t it = 0;; ++it) {
+        gam = exp(E.inv1mp * log(E.ga - rng_uniform(r, k0, k1) * (E.ga - E.gb)));
+        beta = sqrt((gam - 1.0) * (gam + 1.0)) / gam;
+        double c = 1.0 + 0.5 * beta - 2.0 * rng_uniform(r, k0, k1);
+        mu = -2.0 * c / (1.0 + sqrt(1.0 + 2.0 * beta * c));
+        double ee = gam * eps * (1.0 - beta * mu);
+        if (rng_uniform(r, k0, k1) < sigma_kn(ee) || it >= kMaxTrials) {
+            cnt.e_trials += (uint32_t)(it + 1);
+            return;
+        }
+    }
+}
+
+GM_D void scatter_in_frame(Rng &r, uint32_t k0, uint32_t k1, const Elec &El, double theta, double eps,
                            double kout[4], ScatterCount &cnt)
 {
     const double sq2 = 1.4142135623730951, spi = 1.7724538509055159;
@@ -199,7 +219,8 @@ GM_D void scatter_in_frame(Rng &r, uint32_t k0, uint32_t k1, double theta, doubl
     double w4 = 2.0 * theta * theta * theta;
     double wsum = w1 + w2 + w3 + w4;
     double gam, beta, mu;
-    for (int64_t it = 0;; ++it) {
+    if (El.kind != 0) electron_power_law(r, k0, k1, El, eps, gam, beta, mu, cnt);
+    else for (int64_t it = 0;; ++it) {
         double x;
         for (;;) {
             double uc = rng_uniform(r, k0, k1) * wsum;

@@ -197,4 +197,23 @@ __global__ __launch_bounds__(256) void cells_fill_kernel(CellArgs C)
     }
 }
 
+// In-place mapping of a table's values, taken as ln I: t <- map(t) for every
+// (zone, node) of a zone with plasma (the others keep their neutral value).
+struct RemapArgs {
+    const double *zrec;
+    int nz, n_nodes;
+    ImpMap map;
+    double *table;
+};
+
+__global__ __launch_bounds__(256) void remap_table_kernel(RemapArgs R)
+{
+    const long long n = (long long)R.nz * R.n_nodes;
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(r / R.n_nodes);
+        if (R.zrec[(size_t)z * Z_STRIDE + Z_NE] > 0.0) R.table[r] = imp_value(R.map, R.table[r]);
+    }
+}
+
 }  // namespace gm

@@ -121,6 +121,54 @@ GM_HD double sigma_hot(const ShTable &S, double ln_theta, double eps)
 }
 
 // ---------------------------------------------------------------------------
+// Electrons of a plasma.  Thermal: the emissivity above, Kirchhoff
+// absorption and the thermal hot cross section.  Power law (the paper's
+// Conclusions name non-thermal distributions as future work): isotropic
+// n(gamma) = n_e C gamma^-p on [g1, g2], C = (p - 1)/(g1^{1-p} - g2^{1-p}),
+// with the asymptotic synchrotron forms of a power law, written in the
+// variable X = nu / (nu_c s) of the thermal form with nu_c = 3 e B /
+// (2 pi m c) and s the sine of the angle to the field:
+//   j = A s X^{-(p-1)/2},  A = sqrt3 e^3 n_e C B Gamma((3p+19)/12) Gamma((3p-1)/12) / (4 pi m c^2 (p+1)),
+//   nu alpha = A_a X^{-(p+2)/2},  A_a = sqrt3 e^2 n_e C Gamma((3p+2)/12) Gamma((3p+22)/12) / (12 m c),
+// the second from the absorption integral of a smooth distribution,
+// alpha = (p+2)/(8 pi m nu^2) int n(gamma)/gamma P(nu, gamma) dgamma, with
+// the single-electron spectrum's moments; the angle integral of j is
+// 4 pi A X_c^{-(p-1)/2} (sqrt(pi)/2) Gamma((p+5)/4)/Gamma((p+7)/4).
+// ---------------------------------------------------------------------------
+struct Elec {
+    int kind;                  // 0 thermal, 1 power law
+    double p;
+    double ga, gb, inv1mp;     // g1^{1-p}, g2^{1-p}, 1/(1-p): the inverse distribution function
+    double eg, ea;             // exponents -(p-1)/2 (emission), -(p+2)/2 (absorption)
+    double ang;                // angular factor of the emission's angle integral
+    const double *sig;         // [kShNE] ln(sigma/sigma_T) on the thermal table's eps nodes
+    double le0, inv_de;
+};
+
+// emission shape g(X) and its angle integral G(X_c) of the electrons
+GM_HD double shape_g(const Elec &E, double X)
+{
+    if (E.kind == 0) return g_shape(X);
+    return (X > 0.0 && X < 1.7e308) ? exp(E.eg * log(X)) : 0.0;
+}
+
+GM_HD double shape_G(const Elec &E, const GCheb &G, double Xc)
+{
+    if (E.kind == 0) return G_of_Xc(G, Xc);
+    return (Xc > 0.0 && Xc < 1.7e308) ? exp(E.eg * log(Xc)) * E.ang : 0.0;
+}
+
+// hot cross section of the power law: linear in ln eps between the nodes,
+// clamped at the ends
+GM_HD double sigma_pl(const Elec &E, double eps)
+{
+    double b = fmin(fmax((log(eps) - E.le0) * E.inv_de, 0.0), (double)(kShNE - 1));
+    int j = min((int)b, kShNE - 2);
+    double f = b - j;
+    return exp((1.0 - f) * E.sig[j] + f * E.sig[j + 1]);
+}
+
+// ---------------------------------------------------------------------------
 // K2(x) = int_0^inf exp(-x cosh t) cosh(2t) dt by the trapezoid rule in t,
 // which converges geometrically for this analytic integrand (error of
 // order exp(-pi^2/h)); exp(-x) is factored out.

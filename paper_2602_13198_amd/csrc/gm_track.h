@@ -110,6 +110,7 @@ struct TArgs {
     // Kerr (modified Kerr-Schild): spin, polar slope, horizon, capture and
     // record radii, corrector, reciprocal step scales (dx1, dx2, min(dx3, pi dx2))
     double a_spin, mass, h_slope, r_h, r_capture, r_record;   // mass 1 (Kerr) or 0 (flat spherical)
+    Elec el;                       // electrons (the same in every instance of a shared launch)
     double i1_plasma_max;          // no zone with a larger first-axis index holds plasma
     double verlet_tol;
     int verlet_max_it;
@@ -426,7 +427,7 @@ GM_D double step_bias(const Args &A, double w, double bf)
 // products with the metric at the point; FLAT zones carry their unit u and
 // field direction already.
 template <bool FLAT, class Args, class G>
-GM_D Coef coefficients_at64(const Args &A, int z, const G &gm, const double *k, int n_sc)
+GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
@@ -458,15 +459,22 @@ GM_D Coef coefficients_at64(const Args &A, int z, const G &gm, const double *k, 
         if (s2 > 0.0) {
             double rs = rsqrt(s2);                      // 1 / sin(theta)
             double s = s2 * rs;
-            double j = Az * s * g_shape(nuf * zr[Z_INVNUC] * rs);
-            if (j > 0.0) {
-                // nu alpha = j (e^{h nu / kT} - 1) c^2 / (2 h nu^2), Kirchhoff
-                double inv_nu = inv_ef * (kH / kMeC2);
-                c.nua = j * expm1_kirchhoff(ef * zr[Z_INVTH]) * (kC * kC / (2.0 * kH)) * inv_nu * inv_nu;
+            const double X = nuf * zr[Z_INVNUC] * rs;
+            if (el.kind != 0) {
+                // power law: nu alpha = A_a X^{-(p+2)/2}, A_a in the 1/Theta slot
+                c.nua = zr[Z_INVTH] * exp(el.ea * log(X));
+            } else {
+                double j = Az * s * g_shape(X);
+                if (j > 0.0) {
+                    // nu alpha = j (e^{h nu / kT} - 1) c^2 / (2 h nu^2), Kirchhoff
+                    double inv_nu = inv_ef * (kH / kMeC2);
+                    c.nua = j * expm1_kirchhoff(ef * zr[Z_INVTH]) * (kC * kC / (2.0 * kH)) * inv_nu * inv_nu;
+                }
             }
         }
     }
-    if (A.scattering) c.nus = nuf * ne * kSigT * sigma_hot(A.sh, zr[Z_LNTH], ef);
+    if (A.scattering)
+        c.nus = nuf * ne * kSigT * (el.kind != 0 ? sigma_pl(el, ef) : sigma_hot(A.sh, zr[Z_LNTH], ef));
     c.b = bias_at(A, z, zr[Z_TH], ne, n_sc, ef);
     return c;
 }
@@ -474,8 +482,9 @@ GM_D Coef coefficients_at64(const Args &A, int z, const G &gm, const double *k, 
 // The same in the FP32 form: frame products in double, then emissivity,
 // absorption and the hot cross section as FP32 logarithms and one exp each.
 template <bool FLAT, class Args, class G>
-GM_D Coef coefficients_at32(const Args &A, int z, const G &gm, const double *k, int n_sc)
+GM_D Coef coefficients_at32(const Args &A, const Elec &el, int z, const G &gm, const double *k, int n_sc)
 {
+    (void)el;                      // thermal electrons only (power laws run in FP64)
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
     const float *zf = A.zrec32 + (size_t)z * F_STRIDE;
@@ -508,19 +517,19 @@ GM_D Coef coefficients_at32(const Args &A, int z, const G &gm, const double *k, 
 }
 
 template <bool FLAT, bool F32 = false, class Args, class G>
-GM_D Coef coefficients_at(const Args &A, int z, const G &gm, const double *k, int n_sc)
+GM_D Coef coefficients_at(const Args &A, const Elec &el, int z, const G &gm, const double *k, int n_sc)
 {
-    if constexpr (F32) return coefficients_at32<FLAT>(A, z, gm, k, n_sc);
-    else return coefficients_at64<FLAT>(A, z, gm, k, n_sc);
+    if constexpr (F32) return coefficients_at32<FLAT>(A, el, z, gm, k, n_sc);
+    else return coefficients_at64<FLAT>(A, el, z, gm, k, n_sc);
 }
 
 // Flat spacetime (Cartesian Minkowski metric).
 template <class M, bool F32 = false, class Args>
-GM_D Coef coefficients(const Args &A, int z, const double *x, const double *k, int n_sc)
+GM_D Coef coefficients(const Args &A, const Elec &el, int z, const double *x, const double *k, int n_sc)
 {
     static_assert(!M::kCurved, "the flat form");
     (void)x;
-    return coefficients_at<true, F32>(A, z, GFlat{}, k, n_sc);
+    return coefficients_at<true, F32>(A, el, z, GFlat{}, k, n_sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -568,12 +577,12 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
             double f = a - i;
             lnw = (1.0 - f) * A.ln_w[i] + f * A.ln_w[i + 1];
             if (A.mtab) lnw -= zone_table(A.mtab, A.mt_n, A.mt_lo, A.mt_hi, (int)z, lnnu);
-            double F = 4.0 * kPi * Az * G_of_Xc(A.G, nu / nuc) / exp(lnw);
+            double F = 4.0 * kPi * Az * shape_G(A.el, A.G, nu / nuc) / exp(lnw);
             ++trials;
             over += (F > fm) ? 1u : 0u;
             if (u2 < F / fm || it >= kMaxTrials) break;
         }
-        double jmax = Az * g_shape(nu / nuc);
+        double jmax = Az * shape_g(A.el, nu / nuc);
         double cth;
         uint32_t dtr = 0;
         for (int64_t it = 0;; ++it) {
@@ -584,7 +593,7 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
             double j = 0.0;
             if (s2 > 0.0) {
                 double s = sqrt(s2);
-                j = Az * s * g_shape(nu / (nuc * s));
+                j = Az * s * shape_g(A.el, nu / (nuc * s));
             }
             if (u4 < j / jmax || it >= kMaxTrials) break;
         }
@@ -611,7 +620,7 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
         // flat: opacities at the birth point now; Kerr: the tracker's first
         // evaluation of a loaded photon computes them with the acceleration
         Coef c{0.0, 0.0, 1.0, true};
-        if constexpr (!M::kCurved) c = coefficients<M, F32>(A, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
+        if constexpr (!M::kCurved) c = coefficients<M, F32>(A, A.el, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
         // write generation-0 queue entry q
         const PhotonQ &Q = L.dst;
         Q.inst[q] = ii;
@@ -842,7 +851,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_flat(TArgs L)
                 c1 = Coef{ph.cnua, ph.cnus, ph.cb, ph.cvac};
             } else {
                 double xv[4] = {0.0, xn[0], xn[1], xn[2]};
-                c1 = coefficients<Minkowski, F32>(A, zn, xv, ph.k, ph.n_sc);
+                c1 = coefficients<Minkowski, F32>(A, L.el, zn, xv, ph.k, ph.n_sc);   // one distribution per launch
                 ph.cz = zn;
                 ph.cnua = c1.nua; ph.cnus = c1.nus; ph.cb = c1.b; ph.cvac = c1.vacuum;
                 ph.ncoef += 1;
@@ -1061,7 +1070,7 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_flat(TArgs L)
             double eps = scatter_tetrad(g, u, bh, has_b, ks, e);
             double kf[4];
             ScatterCount cnt{0, 0};
-            scatter_in_frame(r, A.key0, A.key1, zr[Z_TH], eps, kf, cnt);
+            scatter_in_frame(r, A.key0, A.key1, A.el, zr[Z_TH], eps, kf, cnt);
 #pragma unroll
             for (int m = 0; m < 4; ++m) kc[m] = kf[0] * e[0][m] + kf[1] * e[1][m] + kf[2] * e[2][m] + kf[3] * e[3][m];
             lds_inc(&B.stats[S_E_TRIALS], cnt.e_trials);
@@ -1078,7 +1087,7 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_flat(TArgs L)
         lds_inc(&B.stats[S_CHILDREN], 1);
         lds_inc(&B.stats[S_GEN0 + min(n_sc, 15)], 1);
         double x1 = -log(1.0 - rng_uniform(r, A.key0, A.key1));
-        Coef c = coefficients<Minkowski, F32>(A, zone_cart(A, x[1], x[2], x[3]), x, kc, n_sc);
+        Coef c = coefficients<Minkowski, F32>(A, A.el, zone_cart(A, x[1], x[2], x[3]), x, kc, n_sc);
         const PhotonQ &O = BATCHED ? L.out : Q;
         if (BATCHED) {
 #pragma unroll

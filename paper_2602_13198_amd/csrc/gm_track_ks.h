@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
             // lookup and no record load (most steps on the way out)
             const bool beyond = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
             const int zn = beyond ? -1 : zone_ks(A, P[0], P[1], P[2]);
-            Coef c1 = coefficients_at<false, F32>(A, zn, GKerr{K}, kn, ph.n_sc);
+            Coef c1 = coefficients_at<false, F32>(A, A.el, zn, GKerr{K}, kn, ph.n_sc);
             ph.ncoef += 1;
             if (mode != MODE_STEP) {
                 // restart at the scattering point, or first evaluation of a
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(256, 2) void scatter_kernel_ks(TArgs L)
             }
             double kf[4];
             ScatterCount cnt{0, 0};
-            scatter_in_frame(r, A.key0, A.key1, zr[Z_TH], eps, kf, cnt);
+            scatter_in_frame(r, A.key0, A.key1, A.el, zr[Z_TH], eps, kf, cnt);
 #pragma unroll
             for (int m = 0; m < 4; ++m) kc[m] = kf[0] * e[0][m] + kf[1] * e[1][m] + kf[2] * e[2][m] + kf[3] * e[3][m];
             lds_inc(&B.stats[S_E_TRIALS], cnt.e_trials);

@@ -58,7 +58,7 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
            "gm_queue_stats", "gm_set_emission_table", "gm_set_score_weights", "gm_set_tally_mode",
            "gm_mlp_set_loss", "gm_unload_zones", "gm_mlp_grad_noalloc", "gm_mlp_fill_table",
-           "gm_cells_accumulate", "gm_cells_fill_table", "gm_expected_roots", "gm_read_table",
+           "gm_cells_accumulate", "gm_cells_fill_table", "gm_remap_table", "gm_expected_roots", "gm_read_table",
            "gm_set_graph"]
 
 
@@ -68,9 +68,20 @@ class GmGrid(C.Structure):
                 ("L_unit_cm", C.c_double), ("r_record", C.c_double)]
 
 
+class GmElectrons(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double), ("gamma_min", C.c_double), ("gamma_max", C.c_double)]
+
+
+def electrons_struct(el) -> GmElectrons:
+    """gm_electrons of a workload's electrons (None: thermal)."""
+    if not el:
+        return GmElectrons(0, 0.0, 0.0, 0.0)
+    return GmElectrons(int(el["kind"]), float(el["p"]), float(el["gamma_min"]), float(el["gamma_max"]))
+
+
 class GmZones(C.Structure):
     _fields_ = [("on_device", C.c_int), ("n_e", C.c_void_p), ("theta_e", C.c_void_p),
-                ("B", C.c_void_p), ("ucon", C.c_void_p), ("bcon", C.c_void_p)]
+                ("B", C.c_void_p), ("ucon", C.c_void_p), ("bcon", C.c_void_p), ("electrons", GmElectrons)]
 
 
 class GmEmitParams(C.Structure):
@@ -142,6 +153,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_mlp_fill_table": (i, [vp, i, C.POINTER(GmImportanceMap), i, vp, vp]),
         "gm_cells_accumulate": (i, [vp, i, C.POINTER(GmImportanceMap), C.POINTER(C.c_int), dp]),
         "gm_cells_fill_table": (i, [vp, i, C.POINTER(GmImportanceMap), C.c_double]),
+        "gm_remap_table": (i, [vp, i, C.POINTER(GmImportanceMap)]),
         "gm_expected_roots": (i, [vp, i, C.POINTER(GmEmitParams), dp]),
         "gm_read_table": (i, [vp, i, i, dp, C.c_int64, C.POINTER(C.c_int)]),
         "gm_set_graph": (i, [vp, i, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
@@ -245,19 +257,19 @@ class Context:
     def load_zones(self, wl, instance: int = 0):
         arrs = [np.ascontiguousarray(a, dtype=np.float64)
                 for a in (wl.n_e, wl.theta_e, wl.B, wl.ucon, wl.bcon)]
-        Z = GmZones(0, *[a.ctypes.data for a in arrs])
+        Z = GmZones(0, *[a.ctypes.data for a in arrs], electrons_struct(getattr(wl, "electrons", None)))
         G = grid_struct(wl.grid)
         _check(load_library().gm_load_zones(self._h, int(instance), C.byref(G), C.byref(Z)))
         self.shapes[instance] = int(np.prod(wl.grid["n"]))
 
-    def load_zones_device(self, grid: dict, n_e, theta_e, B, ucon, bcon, instance: int = 0):
+    def load_zones_device(self, grid: dict, n_e, theta_e, B, ucon, bcon, instance: int = 0, electrons=None):
         """gm_load_zones with the zone arrays in device memory (copied to
         float64 cuda tensors first when given as host arrays)."""
         dev = "cuda:%d" % self.device
         ts = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(dev) if not torch.is_tensor(a)
               else a.to(device=dev, dtype=torch.float64).contiguous()
               for a in (n_e, theta_e, B, ucon, bcon)]
-        Z = GmZones(1, *[t.data_ptr() for t in ts])
+        Z = GmZones(1, *[t.data_ptr() for t in ts], electrons_struct(electrons))
         G = grid_struct(grid)
         _check(load_library().gm_load_zones(self._h, int(instance), C.byref(G), C.byref(Z)))
         self.shapes[instance] = int(np.prod(grid["n"]))
@@ -481,6 +493,10 @@ class Context:
         buf = np.zeros(nz * nn.value)
         _check(load_library().gm_read_table(self._h, int(instance), int(table), _dp(buf), buf.size, None))
         return buf.reshape(nz, nn.value)
+
+    def remap_table(self, instance, imap):
+        """The instance's table (imap.table) mapped in place, values taken as ln I."""
+        _check(load_library().gm_remap_table(self._h, int(instance), C.byref(imap)))
 
     def cells_fill_table(self, instance, imap, prior=20.0):
         _check(load_library().gm_cells_fill_table(self._h, int(instance), C.byref(imap), float(prior)))

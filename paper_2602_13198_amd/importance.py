@@ -75,8 +75,23 @@ def zone_geometry(wl):
     return (i1, i2, i3), rad, cth
 
 
+_FEATURES = {}
+
+
 def zone_features(wl):
-    """[nz][5]: ln Theta_e, ln n_e, ln(B + 1e-10), radius feature, cos theta."""
+    """[nz][5]: ln Theta_e, ln n_e, ln(B + 1e-10), radius feature, cos theta
+    (kept for the workload object once computed)."""
+    key = id(wl)
+    hit = _FEATURES.get(key)
+    if hit is not None and hit[0] is wl:
+        return hit[1]
+    f = _zone_features(wl)
+    _FEATURES.clear()
+    _FEATURES[key] = (wl, f)
+    return f
+
+
+def _zone_features(wl):
     _, rad, cth = zone_geometry(wl)
     tiny = 1e-300
     return np.stack([np.log(np.maximum(wl.theta_e, 1e-3)), np.log(np.maximum(wl.n_e, tiny)),
@@ -269,15 +284,16 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
         b_I = math.log(m_em_mean)                            # ln S = y + ln(mean t)
         fill = lambda m: ctx.mlp_fill_table(inst, m, 1, net.mu, net.sd)   # noqa: E731
     if use_emission:
-        # the plain roots' mean of S: expected roots of the table ln S over the plain ones
+        # the table ln S once, then mapped in place: the plain roots' mean of
+        # S is the expected roots of the table ln S over the plain ones
         m_em.b = b_I
         fill(m_em)
         i_bar = ctx.expected_roots(emit_round, inst) / nb0
-        m_em.kind, m_em.alpha, m_em.b = GM.IMP_MIXTURE, alpha, b_I - math.log(max(i_bar, 1e-300))
-        fill(m_em)
+        m_em.kind, m_em.alpha, m_em.a, m_em.b = GM.IMP_MIXTURE, alpha, 1.0, -math.log(max(i_bar, 1e-300))
+        ctx.remap_table(inst, m_em)
         nb1 = ctx.expected_roots(emit_round, inst)
-        m_em.shift = math.log(nb0 / max(nb1, 1e-300))
-        fill(m_em)
+        m_em.kind, m_em.a, m_em.b, m_em.shift = GM.IMP_LINEAR, 1.0, 0.0, math.log(nb0 / max(nb1, 1e-300))
+        ctx.remap_table(inst, m_em)
         info["emission_shift"] = m_em.shift
     info["tables_s"] = time.perf_counter() - t0
     return info

@@ -76,8 +76,9 @@ def test_network_table(gm, table):
 
 def test_cell_tables_and_expected_roots(gm):
     """Cell sums and ratios (per unit weight and per photon) against numpy
-    on the same records; the expected roots equal the make's summed
-    expected counts, with and without the emission table."""
+    on the same records, the in-place remap of a table; the expected roots
+    equal the make's summed expected counts, with and without the emission
+    table."""
     wl = _wl()
     c = gm.Context(0)
     c.load_zones(wl)
@@ -128,6 +129,16 @@ def test_cell_tables_and_expected_roots(gm):
         j = zcell * n + k
         r = np.where(N[j] > 0, (S[j] + 5.0 * ratio_n) / (N[j] + 5.0), ratio_n)
         np.testing.assert_allclose(tab[on, k], np.log(r) + 0.7, rtol=0, atol=1e-10)
+    # in place: the mixture of the stored ln I, then a shift; zones without
+    # plasma keep their value
+    before = c.read_table(0, 0)
+    mr = gm.Context.importance_map(gm.TABLE_BIAS, n, lo, hi, gm.IMP_MIXTURE, a=1.0, b=-0.3, alpha=0.4, shift=0.2)
+    c.remap_table(0, mr)
+    after = c.read_table(0, 0)
+    np.testing.assert_allclose(after[on], np.log(0.6 + 0.4 * np.exp(before[on] - 0.3)) + 0.2, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(after[wl.n_e <= 0], before[wl.n_e <= 0])
+    with pytest.raises(gm.GmError, match="error -4"):
+        c.remap_table(0, gm.Context.importance_map(gm.TABLE_BIAS, n + 1, lo, hi))
     # the emission table changes the expected roots by the mapped factor
     me = gm.Context.importance_map(gm.TABLE_EMISSION, n, math.log(1e8), math.log(1e16), gm.IMP_LINEAR, a=0.0, b=0.5)
     c.cells_accumulate(0, me, blocks)
