@@ -411,6 +411,40 @@ def paper_sphere_form(ctx, inst, steps=2, n_s=1e7):
             "geodesic_steps_per_superphoton": float(tot[2]) / max(n, 1)}
 
 
+def power_law_form(ctx, inst, steps=3, n_s=1e6):
+    """Compton scattering off power-law electrons: the flat sphere (32^3
+    Cartesian zones, R = 1e14 cm, B = 1 G) filled with an isotropic power
+    law of index 3 on [10, 1e3], tau_T = 0.05 with b = 1/tau_T, four
+    generations, emission 1e9-1e12 Hz, FP64."""
+    import torch
+    from paper_2602_13198_amd import workloads as W
+    wl = W.power_law_sphere(n_target=n_s, seed=0, tau_T=0.05, gamma_max=1e3, nu_min=1e9, nu_max=1e12)
+    wl.emit["instance"] = inst
+    ctx.load_zones(wl, inst)
+    ctx.set_instance_bias(inst, wl.track)
+
+    def step(seed):
+        ctx.make_superphotons(dict(wl.emit, seed=seed), instance=inst)
+        st = ctx.track_scatter(wl.track)
+        ctx.read_spectrum(inst, reset=True)
+        return st
+    step(9600)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = None
+    for s in range(steps):
+        st = step(9601 + s)
+        tot = st if tot is None else tot + st
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.unload(inst)
+    n = int(tot[0] + tot[1])
+    return {"workload": "power-law electrons (p=3 on gamma 10..1e3) in the 32^3 flat sphere, R=1e14 cm, B=1 G, "
+                        "tau_T=0.05, b=20, 4 generations, N_s=%g, FP64" % n_s,
+            "value": n / dt, "unit": "superphotons/s", "ms_per_step": dt / steps * 1e3,
+            "children_per_root": float(tot[1]) / max(float(tot[0]), 1.0)}
+
+
 def survey_form(ctx, steps=2, n_inst=64, log=lambda m: None):
     """The batched survey: 64 tori (spins -0.5 .. 0.9375, R_high 1 .. 160,
     M_unit log-uniform over two decades, N_s log-uniform on [1e5, 1e7])
@@ -658,6 +692,8 @@ def main():
         log("flat sphere: %.4g superphotons/s" % out["forms"]["flat_scattering_sphere"]["value"])
         out["forms"]["paper_thin_sphere"] = paper_sphere_form(ctx, 4)
         log("paper thin sphere: %.4g superphotons/s" % out["forms"]["paper_thin_sphere"]["value"])
+        out["forms"]["power_law_sphere"] = power_law_form(ctx, 5)
+        log("power-law sphere: %.4g superphotons/s" % out["forms"]["power_law_sphere"]["value"])
         ctx.unload(0)
         out["forms"]["survey"] = survey_form(ctx, n_inst=args.survey_inst, log=log)
         log("survey: %.4g superphotons/s" % out["forms"]["survey"]["value"])

@@ -770,6 +770,7 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
         A.inv_dx[j] = 1.0 / I.grid.dx[j];
         A.xe[j] = I.grid.x_start[j] + I.grid.n[j] * I.grid.dx[j];
     }
+    A.inv_n3 = 1.0 / I.grid.n[2];
     A.C = kH * I.grid.L_unit_cm / kMeC2;
     A.inst = ii;
     A.key0 = (uint32_t)I.ep.seed;

@@ -68,7 +68,7 @@ enum { Z_U0 = 0, Z_B0 = 4, Z_A = 8, Z_NUC = 9, Z_TH = 10, Z_NE = 11, Z_LNTH = 12
 template <class G>
 GM_D bool fluid_frame_vec(bool zone_has_b, const G &gm, double u[4], double bh[4])
 {
-    const double iun = 1.0 / sqrt(-gm.dot(u, u));
+    const double iun = rsqrt(-gm.dot(u, u));
 #pragma unroll
     for (int m = 0; m < 4; ++m) u[m] *= iun;
     double bu = gm.dot(bh, u);

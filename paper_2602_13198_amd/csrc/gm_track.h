@@ -66,6 +66,7 @@ struct TArgs {
     const float *zrec32;           // FP32 records (precision form)
     int n[3];
     double xs[3], dx[3], inv_dx[3], xe[3];
+    double inv_n3;                 // 1 / n[2]
     double C;                      // h ell / (m_e c^2): converts d(lambda) to cm s
     int inst;
     uint32_t key0, key1;
@@ -385,8 +386,12 @@ GM_D int zone_ks(const TArgs &A, double x1, double x2, double x3)
     double f2 = floor((x2 - A.xs[1]) * A.inv_dx[1]);
     f2 = fmin(fmax(f2, 0.0), (double)(A.n[1] - 1));
     double f3 = floor((x3 - A.xs[2]) * A.inv_dx[2]);
-    double n3 = (double)A.n[2];
-    f3 -= n3 * floor(f3 / n3);
+    // f3 mod n3 for the integer-valued f3: the quotient from a multiply by
+    // 1/n3 is off by at most one, which the two corrections undo
+    const double n3 = (double)A.n[2];
+    f3 -= n3 * floor(f3 * A.inv_n3);
+    f3 = (f3 >= n3) ? f3 - n3 : f3;
+    f3 = (f3 < 0.0) ? f3 + n3 : f3;
     return ((int)f1 * A.n[1] + (int)f2) * A.n[2] + (int)f3;
 }
 
