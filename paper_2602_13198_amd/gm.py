@@ -316,6 +316,17 @@ class Context:
                                                1, _dp(led), int(reset)))
         return out, led
 
+    def reset_spectrum(self, instance: int = 0):
+        """Clear an instance's tally and ledger; an instance never tracked
+        has none, and nothing is done."""
+        if not hasattr(self, "n_theta"):
+            return
+        try:
+            self.read_spectrum(instance, reset=True)
+        except GmError as exc:
+            if "error -4" not in str(exc):
+                raise
+
     # -- inspection ---------------------------------------------------------
     def read_emission(self, instance: int = 0):
         nz = self.shapes[instance]

@@ -117,7 +117,7 @@ def pilot(ctx, wl, inst, rounds, seed0, n_s, root_stride=4, track=None):
     reads them if it needs them on the host)."""
     track = dict(track or wl.track)
     emit = dict(wl.emit, n_target=float(n_s))
-    ctx.read_spectrum(inst, reset=True)
+    ctx.reset_spectrum(inst)
     ctx.make_superphotons(dict(emit, seed=seed0), instance=inst)
     ctx.track_scatter(track)
     sp, _ = ctx.read_spectrum(inst, reset=True)
@@ -210,6 +210,24 @@ class Network:
 # ---------------------------------------------------------------------------
 # tables (built on the device by the library)
 # ---------------------------------------------------------------------------
+def heldout_deviance(net, ctx, X, T, C, hold):
+    """Poisson deviance e^y - t y per output on the held-out rows, of the
+    network and of the best constant predictor (ln of the training rows'
+    mean target): [(network, constant), ...]."""
+    y = net.predict(ctx, X[hold])
+    out = []
+    for o in range(T.shape[1]):
+        w = C[hold, o] > 0
+        tr = (~hold) & (C[:, o] > 0)
+        if not w.any() or not tr.any():
+            out.append((math.inf, math.inf))
+            continue
+        t, yy = T[hold, o][w], y[w, o]
+        c = math.log(max(T[tr, o].mean(), 1e-300))
+        out.append((float(np.mean(np.exp(yy) - t * yy)), float(np.mean(math.exp(c) - t * c))))
+    return out
+
+
 def emission_band(ev, nodes, pad=0.5):
     """ln nu range of the emission records (the band the plain roots are
     born in), padded by `pad` node spacings on each side."""
@@ -239,7 +257,10 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
     ln S_em over those of the plain method), so that the plain roots' mean
     of the density ratio is 1 and every region keeps at least 1 - alpha of
     its plain roots; a last shift, fixed by the expected roots, absorbs
-    what the interpolation between nodes leaves."""
+    what the interpolation between nodes leaves.  The network trains on
+    nine rows in ten; an output whose Poisson deviance on the held-out
+    rows is not below that of the constant mean builds no table (the form
+    falls back to the plain bias, resp. emission; info["fallback"])."""
     info, t0 = {}, time.perf_counter()
     e = wl.emit
     emit_round = dict(e, n_target=float(n_s))
@@ -273,10 +294,23 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
         T[len(sc):, 1], Cw[len(sc):, 1] = t_em / m_em_mean, 1.0
         net = Network(seed=net_seed)
         t1 = time.perf_counter()
-        hist = net.fit(ctx, X, T, Cw, steps=train_steps)
+        # every tenth row held out: a table is built only from an output that
+        # predicts those rows better than the constant mean does
+        hold = (np.arange(len(X)) % 10) == 0
+        Ct = Cw.copy()
+        Ct[hold] = 0.0
+        hist = net.fit(ctx, X, T, Ct, steps=train_steps)
         info["train_s"] = time.perf_counter() - t1
         info["loss_first_last"] = [hist[0][1], hist[-1][1]]
         info["records"] = [int(len(sc)), int(len(em))]
+        dev = heldout_deviance(net, ctx, X, T, Cw, hold)
+        info["heldout_deviance"] = dev
+        if use_bias and not dev[0][0] < dev[0][1]:
+            use_bias = False
+            info["fallback"] = info.get("fallback", []) + ["bias"]
+        if use_emission and not dev[1][0] < dev[1][1]:
+            use_emission = False
+            info["fallback"] = info.get("fallback", []) + ["emission"]
         if use_bias:
             # ln I = y + ln(mean t); c_b = records / summed score
             m_bias.b = math.log(m_sc) + math.log(len(sc) / max(sc["score"].sum(), 1e-300))
@@ -295,6 +329,7 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
         m_em.kind, m_em.a, m_em.b, m_em.shift = GM.IMP_LINEAR, 1.0, 0.0, math.log(nb0 / max(nb1, 1e-300))
         ctx.remap_table(inst, m_em)
         info["emission_shift"] = m_em.shift
+    info["bias_table"], info["emission_table"] = bool(use_bias), bool(use_emission)
     info["tables_s"] = time.perf_counter() - t0
     return info
 
@@ -358,7 +393,7 @@ def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rou
                 ctx.set_event_log(0)
                 torch.cuda.synchronize()
                 t_prep = time.perf_counter() - ta
-                over = dict(bias_mode=GM.BIAS_WINDOW, bias_max=b_max) if use_bias else None
+                over = dict(bias_mode=GM.BIAS_WINDOW, bias_max=b_max) if info["bias_table"] else None
                 r = CV.time_to_error(ctx, wl, inst, L_ref, mask, 400000 + 1000 * k, n_round, max_rounds=512,
                                      track_overrides=over)
             except GM.GmError as exc:          # reported, not hidden: the form has no time then
