@@ -25,6 +25,13 @@ constexpr int kShNE = 256;
 constexpr double kShThMin = 1e-2, kShThMax = 1e3;
 constexpr double kShEMin = 1e-12, kShEMax = 1e6;
 
+// Holds a loaded value in a register at this point of the program.  Loads
+// whose results are all settled together are issued as one batch and waited
+// for once; otherwise the compiler may sink some of them past a branch or
+// reuse their registers, paying the memory latency once per round.
+GM_D void settle(double v) { asm volatile("" :: "v"(v)); }
+GM_D void settle(float v) { asm volatile("" :: "v"(v)); }
+
 // Rejection loops stop after this many trials.
 constexpr int64_t kMaxTrials = 100000;
 // Margin on the per-zone frequency rejection bound (curvature of ln J

@@ -45,16 +45,29 @@ struct KMetric {
     double d1[7], d2[7];                                  // d/dx1, d/dx2 of g00 g01 g03 g11 g13 g22 g33
 };
 
+// sin(pi x) and cos(pi x): on the device the library's sincospi, whose
+// reduction of a multiple of pi is exact and short (the tracker evaluates
+// two per point); the host's check of the zones uses sin and cos.
+GM_HD void sincos_pi(double x, double *s, double *c)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    sincospi(x, s, c);
+#else
+    *s = ::sin(kPi * x);
+    *c = ::cos(kPi * x);
+#endif
+}
+
 template <bool DERIV>
 GM_HD void kerr_metric(double a, double M, double hs, double x1, double x2, KMetric &K)
 {
     double r = exp(x1);
+    // theta = pi (x2 + (1-h)/(2 pi) sin(2 pi x2)): both sines from sincospi
     double st, ct;
-    sincos(2.0 * kPi * x2, &st, &ct);
-    double th = kPi * x2 + 0.5 * (1.0 - hs) * st;
+    sincos_pi(2.0 * x2, &st, &ct);
     double dth = kPi * (1.0 + (1.0 - hs) * ct);
     double s, c;
-    sincos(th, &s, &c);
+    sincos_pi(x2 + (0.5 / kPi) * (1.0 - hs) * st, &s, &c);
     K.r = r;
     if (!DERIV) {
         double s2 = s * s, S = r * r + a * a * c * c, z = 2.0 * M * r / S;

@@ -107,18 +107,29 @@ struct ShTable {
     double lt0, inv_dt, le0, inv_de;
 };
 
-GM_HD double sigma_hot(const ShTable &S, double ln_theta, double eps)
+// In two halves, so that a caller can request the four table entries early
+// and interpolate once other work has covered their latency.
+struct ShFetch {
+    double t00, t01, t10, t11, fa, fb;
+};
+
+GM_HD ShFetch sigma_hot_fetch(const ShTable &S, double ln_theta, double ln_eps)
 {
     double a = (ln_theta - S.lt0) * S.inv_dt;
-    double b = (log(eps) - S.le0) * S.inv_de;
+    double b = (ln_eps - S.le0) * S.inv_de;
     a = fmin(fmax(a, 0.0), (double)(kShNT - 1));
     b = fmin(fmax(b, 0.0), (double)(kShNE - 1));
     int i = min((int)a, kShNT - 2), j = min((int)b, kShNE - 2);
-    double fa = a - i, fb = b - j;
     const double *r0 = S.t + i * kShNE + j, *r1 = r0 + kShNE;
-    double v = (1.0 - fa) * ((1.0 - fb) * r0[0] + fb * r0[1]) + fa * ((1.0 - fb) * r1[0] + fb * r1[1]);
+    return ShFetch{r0[0], r0[1], r1[0], r1[1], a - i, b - j};
+}
+
+GM_HD double sigma_hot_finish(const ShFetch &f)
+{
+    double v = (1.0 - f.fa) * ((1.0 - f.fb) * f.t00 + f.fb * f.t01) + f.fa * ((1.0 - f.fb) * f.t10 + f.fb * f.t11);
     return exp(v);
 }
+
 
 // ---------------------------------------------------------------------------
 // Electrons of a plasma.  Thermal: the emissivity above, Kirchhoff

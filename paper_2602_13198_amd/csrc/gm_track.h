@@ -447,6 +447,8 @@ GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, c
             zr[2 * m] = v.x;
             zr[2 * m + 1] = v.y;
         }
+#pragma unroll
+        for (int m = 0; m < Z_STRIDE; ++m) settle(zr[m]);
     }
     double ne = zr[Z_NE];
     if (!(ne > 0.0)) return c;
@@ -454,6 +456,11 @@ GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, c
     double u[4], bh[4];
     bool has_b = FLAT ? fluid_frame_flat(zr, u, bh) : fluid_frame_m(zr, gm, u, bh);
     double ef = -gm.dot(k, u);
+    // the thermal hot cross section's table entries are requested before the
+    // absorption is computed, which then covers their latency
+    const bool sh_thermal = A.scattering && el.kind == 0;
+    ShFetch shf{};
+    if (sh_thermal) shf = sigma_hot_fetch(A.sh, zr[Z_LNTH], log(ef));
     double inv_ef = 1.0 / ef;
     double nuf = ef * (kMeC2 / kH);
     double Az = zr[Z_A];
@@ -478,8 +485,12 @@ GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, c
             }
         }
     }
-    if (A.scattering)
-        c.nus = nuf * ne * kSigT * (el.kind != 0 ? sigma_pl(el, ef) : sigma_hot(A.sh, zr[Z_LNTH], ef));
+    if (sh_thermal) {
+        settle(shf.t00); settle(shf.t01); settle(shf.t10); settle(shf.t11);
+        c.nus = nuf * ne * kSigT * sigma_hot_finish(shf);
+    } else if (A.scattering) {
+        c.nus = nuf * ne * kSigT * sigma_pl(el, ef);
+    }
     c.b = bias_at(A, z, zr[Z_TH], ne, n_sc, ef);
     return c;
 }
@@ -492,7 +503,18 @@ GM_D Coef coefficients_at32(const Args &A, const Elec &el, int z, const G &gm, c
     (void)el;                      // thermal electrons only (power laws run in FP64)
     Coef c{0.0, 0.0, 1.0, true};
     if (z < 0) return c;
-    const float *zf = A.zrec32 + (size_t)z * F_STRIDE;
+    // the 64-byte record in one round of 16-byte loads, as in FP64
+    float zf[F_STRIDE];
+    {
+        const float4 *src = reinterpret_cast<const float4 *>(A.zrec32 + (size_t)z * F_STRIDE);
+#pragma unroll
+        for (int m = 0; m < F_STRIDE / 4; ++m) {
+            float4 v = src[m];
+            zf[4 * m] = v.x; zf[4 * m + 1] = v.y; zf[4 * m + 2] = v.z; zf[4 * m + 3] = v.w;
+        }
+#pragma unroll
+        for (int m = 0; m < F_STRIDE; ++m) settle(zf[m]);
+    }
     float nef = zf[F_NE];
     if (!(nef > 0.0f)) return c;
     c.vacuum = false;

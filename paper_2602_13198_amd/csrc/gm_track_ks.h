@@ -223,6 +223,19 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 #pragma unroll
                 for (int m = 0; m < 3; ++m) P[m] = ph.x[m];
             }
+            // touch the zone record of the point now (the record is one cache
+            // line), so that the line arrives while the metric and the
+            // corrector are computed; the pole reflection below can move the
+            // point to a neighbouring zone, whose record then comes later
+            double ne_touch = 0.0;
+            {
+                const bool far_out = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
+                const int zt = far_out ? -1 : zone_ks(A, P[0], P[1], P[2]);
+                if (zt >= 0) {
+                    if constexpr (F32) ne_touch = (double)A.zrec32[(size_t)zt * F_STRIDE + F_NE];
+                    else ne_touch = A.zrec[(size_t)zt * Z_STRIDE + Z_NE];
+                }
+            }
             KMetric K;
             kerr_metric<true>(A.a_spin, A.mass, A.h_slope, P[0], P[1], K);
             if (mode != MODE_LOAD) {
@@ -290,6 +303,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
             // lookup and no record load (most steps on the way out)
             const bool beyond = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
             const int zn = beyond ? -1 : zone_ks(A, P[0], P[1], P[2]);
+            settle(ne_touch);
             Coef c1 = coefficients_at<false, F32>(A, A.el, zn, GKerr{K}, kn, ph.n_sc);
             ph.ncoef += 1;
             if (mode != MODE_STEP) {
