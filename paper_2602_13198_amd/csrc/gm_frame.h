@@ -82,6 +82,27 @@ GM_D bool fluid_frame_vec(bool zone_has_b, const G &gm, double u[4], double bh[4
     return has_b;
 }
 
+// The two frame products the opacities need, without forming the unit
+// vectors: with u_n = u / sqrt(-u.u) and b' = b + (b.u_n) u_n (b projected
+// normal to u_n), eps = -k.u_n and kb = k.b' / |b'|, where
+// |b'|^2 = b.b + (b.u_n)^2 and k.b' = k.b - (b.u_n) eps.  kb is 0 and the
+// result false when the zone has no field or b' vanishes here.
+template <class G, class T>
+GM_D bool frame_products(bool zone_has_b, const G &gm, const T *uz, const T *bz, const double *k,
+                         double &eps, double &kb)
+{
+    double u[4], b[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { u[m] = (double)uz[m]; b[m] = (double)bz[m]; }
+    const double iun = rsqrt(-gm.dot(u, u));
+    eps = -gm.dot(k, u) * iun;
+    const double bu = gm.dot(b, u) * iun;
+    const double n2 = gm.dot(b, b) + bu * bu;
+    const bool has_b = zone_has_b && n2 > 0.0;
+    kb = has_b ? (gm.dot(k, b) - bu * eps) * rsqrt(n2) : 0.0;
+    return has_b;
+}
+
 // Same from a packed FP64 zone record.
 template <class G>
 GM_D bool fluid_frame_m(const double *zr, const G &gm, double u[4], double bh[4])

@@ -31,11 +31,6 @@ GM_HD D3 operator-(D3 x, D3 y) { return {x.v - y.v, x.d1 - y.d1, x.d2 - y.d2}; }
 GM_HD D3 operator*(D3 x, D3 y) { return {x.v * y.v, x.d1 * y.v + x.v * y.d1, x.d2 * y.v + x.v * y.d2}; }
 GM_HD D3 operator*(double s, D3 x) { return {s * x.v, s * x.d1, s * x.d2}; }
 GM_HD D3 operator+(double s, D3 x) { return {s + x.v, x.d1, x.d2}; }
-GM_HD D3 operator/(D3 x, D3 y)
-{
-    double iy = 1.0 / y.v, q = x.v * iy;
-    return {q, (x.d1 - q * y.d1) * iy, (x.d2 - q * y.d2) * iy};
-}
 
 // The seven metric components (and optionally their derivatives) at a point.
 struct KMetric {
@@ -92,7 +87,14 @@ GM_HD void kerr_metric(double a, double M, double hs, double x1, double x2, KMet
     D3 Sn{s, 0.0, c * dth}, Cs{c, 0.0, -s * dth};
     D3 S2 = Sn * Sn, C2 = Cs * Cs;
     D3 S = R * R + (a * a) * C2;
-    D3 Z = (2.0 * M * R) / S;
+    // one reciprocal, of Sigma r^2 dth^2, serves 1/Sigma and the inverse
+    // metric's quotients below
+    const double q = 1.0 / (S.v * r * r * dth * dth);
+    const double iS = q * (r * r * dth * dth);
+    D3 Z;
+    Z.v = 2.0 * M * r * iS;
+    Z.d1 = (2.0 * M * R.d1 - Z.v * S.d1) * iS;
+    Z.d2 = (-Z.v * S.d2) * iS;
     D3 one{1.0, 0.0, 0.0};
     D3 Zp = 1.0 + Z;
     D3 g[7];
@@ -106,11 +108,10 @@ GM_HD void kerr_metric(double a, double M, double hs, double x1, double x2, KMet
     K.g00 = g[0].v; K.g01 = g[1].v; K.g03 = g[2].v; K.g11 = g[3].v; K.g13 = g[4].v; K.g22 = g[5].v; K.g33 = g[6].v;
 #pragma unroll
     for (int i = 0; i < 7; ++i) { K.d1[i] = g[i].d1; K.d2[i] = g[i].d2; }
-    // inverse: one reciprocal of Sigma r^2 dth^2 serves four quotients; the
-    // sin^2 quotient keeps its own division (infinite on the axis, as before)
+    // inverse: the reciprocal q serves four quotients; the sin^2 quotient
+    // keeps its own division (infinite on the axis, as before)
     double D = r * r - 2.0 * M * r + a * a;
     double Sv = S.v, z = Z.v;
-    const double q = 1.0 / (Sv * r * r * dth * dth);
     const double iSr2 = q * (dth * dth);                   // 1 / (Sigma r^2)
     K.u00 = -(1.0 + z);
     K.u01 = z * (iSr2 * Sv * r);                           // z / r

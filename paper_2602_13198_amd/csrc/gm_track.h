@@ -453,9 +453,16 @@ GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, c
     double ne = zr[Z_NE];
     if (!(ne > 0.0)) return c;
     c.vacuum = false;
-    double u[4], bh[4];
-    bool has_b = FLAT ? fluid_frame_flat(zr, u, bh) : fluid_frame_m(zr, gm, u, bh);
-    double ef = -gm.dot(k, u);
+    double ef, kb;                 // -k.u and k.(field direction) at the point
+    bool has_b;
+    if constexpr (FLAT) {
+        double u[4], bh[4];
+        has_b = fluid_frame_flat(zr, u, bh);
+        ef = -gm.dot(k, u);
+        kb = gm.dot(k, bh);
+    } else {
+        has_b = frame_products(zr[Z_HASB] != 0.0, gm, zr + Z_U0, zr + Z_B0, k, ef, kb);
+    }
     // the thermal hot cross section's table entries are requested before the
     // absorption is computed, which then covers their latency
     const bool sh_thermal = A.scattering && el.kind == 0;
@@ -465,7 +472,7 @@ GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, c
     double nuf = ef * (kMeC2 / kH);
     double Az = zr[Z_A];
     if (has_b && Az > 0.0) {
-        double cth = gm.dot(k, bh) * inv_ef;
+        double cth = kb * inv_ef;
         cth = fmin(fmax(cth, -1.0), 1.0);
         double s2 = 1.0 - cth * cth;
         if (s2 > 0.0) {
@@ -518,16 +525,21 @@ GM_D Coef coefficients_at32(const Args &A, const Elec &el, int z, const G &gm, c
     float nef = zf[F_NE];
     if (!(nef > 0.0f)) return c;
     c.vacuum = false;
-    double u[4], bh[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) { u[m] = (double)zf[F_U0 + m]; bh[m] = (double)zf[F_B0 + m]; }
+    double ef, kb;                 // -k.u and k.(field direction) at the point
     bool has_b = zf[F_HASB] != 0.0f;
-    if (!FLAT) has_b = fluid_frame_vec(has_b, gm, u, bh);
-    double ef = -gm.dot(k, u);
+    if constexpr (FLAT) {
+        double u[4], bh[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) { u[m] = (double)zf[F_U0 + m]; bh[m] = (double)zf[F_B0 + m]; }
+        ef = -gm.dot(k, u);
+        kb = gm.dot(k, bh);
+    } else {
+        has_b = frame_products(has_b, gm, zf + F_U0, zf + F_B0, k, ef, kb);
+    }
     float lnnu = __logf((float)(ef * (kMeC2 / kH)));
     float lnA = zf[F_LNA];
     if (has_b && lnA > -1e30f) {
-        double cth = fmin(fmax(gm.dot(k, bh) / ef, -1.0), 1.0);
+        double cth = fmin(fmax(kb / ef, -1.0), 1.0);
         float s2 = (float)(1.0 - cth * cth);
         if (s2 > 0.0f) {
             float lns = 0.5f * __logf(s2);

@@ -255,7 +255,8 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                         den += fabs(kn[m]);
                         kp[m] = kn[m];
                     }
-                    if (num / (den + 1e-300) < A.verlet_tol || it >= A.verlet_max_it) break;
+                    // relative change num / den below the tolerance (den > 0)
+                    if (num < A.verlet_tol * (den + 1e-300) || it >= A.verlet_max_it) break;
                 }
                 ph.vit += (uint32_t)it;
                 // the scattering point restarts with the acceleration of the
