@@ -88,9 +88,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def track_variant(waves: int, batch: int, kerr: bool = True) -> str:
-    """Name of the compiled FP64 tracker a tuning selects."""
-    return "track_kernel_%s<%d, false, %s>" % ("ks" if kerr else "flat", waves, "true" if batch > 1 else "false")
+def track_variant(waves: int, batch: int, kerr: bool = True, const_bias: bool = True) -> str:
+    """Name of the compiled FP64 tracker a tuning selects (the Kerr tracker
+    has a form for launches whose instances all have the constant bias)."""
+    b = "true" if batch > 1 else "false"
+    if kerr:
+        return "track_kernel_ks<%d, false, %s, %s>" % (waves, b, "true" if const_bias else "false")
+    return "track_kernel_flat<%d, false, %s>" % (waves, b)
 
 
 # the variant the committed profiles cover: the Kerr tracker at 2 waves/SIMD,

@@ -853,15 +853,28 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     const bool f32 = tp->precision == GM_PRECISION_F32_EMISSIVITY;
     using KernelFn = void (*)(TArgs);
 #define GM_TRACK_VARIANTS(K, F, B) {K<2, F, B>, K<3, F, B>, K<4, F, B>}
-    static const KernelFn track_fns[2][2][2][3] = {
-        {{GM_TRACK_VARIANTS(track_kernel_flat, false, false), GM_TRACK_VARIANTS(track_kernel_flat, false, true)},
-         {GM_TRACK_VARIANTS(track_kernel_flat, true, false), GM_TRACK_VARIANTS(track_kernel_flat, true, true)}},
-        {{GM_TRACK_VARIANTS(track_kernel_ks, false, false), GM_TRACK_VARIANTS(track_kernel_ks, false, true)},
-         {GM_TRACK_VARIANTS(track_kernel_ks, true, false), GM_TRACK_VARIANTS(track_kernel_ks, true, true)}}};
+#define GM_TRACK_VARIANTS_KS(F, B, CB) {track_kernel_ks<2, F, B, CB>, track_kernel_ks<3, F, B, CB>, track_kernel_ks<4, F, B, CB>}
+    // [kerr][constant bias][f32][batched][waves - 2]; the flat tracker has no
+    // constant-bias form
+    static const KernelFn track_fns[2][2][2][2][3] = {
+        {{{GM_TRACK_VARIANTS(track_kernel_flat, false, false), GM_TRACK_VARIANTS(track_kernel_flat, false, true)},
+          {GM_TRACK_VARIANTS(track_kernel_flat, true, false), GM_TRACK_VARIANTS(track_kernel_flat, true, true)}},
+         {{GM_TRACK_VARIANTS(track_kernel_flat, false, false), GM_TRACK_VARIANTS(track_kernel_flat, false, true)},
+          {GM_TRACK_VARIANTS(track_kernel_flat, true, false), GM_TRACK_VARIANTS(track_kernel_flat, true, true)}}},
+        {{{GM_TRACK_VARIANTS_KS(false, false, false), GM_TRACK_VARIANTS_KS(false, true, false)},
+          {GM_TRACK_VARIANTS_KS(true, false, false), GM_TRACK_VARIANTS_KS(true, true, false)}},
+         {{GM_TRACK_VARIANTS_KS(false, false, true), GM_TRACK_VARIANTS_KS(false, true, true)},
+          {GM_TRACK_VARIANTS_KS(true, false, true), GM_TRACK_VARIANTS_KS(true, true, true)}}}};
 #undef GM_TRACK_VARIANTS
+#undef GM_TRACK_VARIANTS_KS
+    bool const_bias = true;
+    for (int k = 0; k < n_inst; ++k) {
+        const Instance &I = c->inst[ids[k]];
+        const_bias = const_bias && (I.bias_mode >= 0 ? I.bias_mode : tp->bias_mode) == GM_BIAS_CONST;
+    }
     // one instance: the arguments travel as kernel arguments; several: per
     // instance from device memory, one instance per pass of a wave
-    const KernelFn track_fn = track_fns[kerr][f32][n_inst > 1][c->track_waves - 2];
+    const KernelFn track_fn = track_fns[kerr][const_bias][f32][n_inst > 1][c->track_waves - 2];
     const KernelFn birth_fn = kerr ? (KernelFn)birth_kernel<KerrMKS, false>
                                    : f32 ? (KernelFn)birth_kernel<Minkowski, true> : (KernelFn)birth_kernel<Minkowski, false>;
     const bool batched = n_inst > 1;

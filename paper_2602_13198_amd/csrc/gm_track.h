@@ -401,10 +401,13 @@ GM_D int zone_ks(const TArgs &A, double x1, double x2, double x3)
 // [1, bias_max].  In the weight-window mode (4) the table gives an
 // importance factor, returned unclamped: the bias of a step is the
 // photon's weight times it (step_bias).  Any b >= 1 keeps the estimator
-// unbiased: the child carries w/b, the parent keeps w(1 - 1/b).
-template <class Args>
+// unbiased: the child carries w/b, the parent keeps w(1 - 1/b).  CB: the
+// caller knows at compile time that the bias is the constant one (mode 0),
+// which spares the tracker the registers of the other modes.
+template <bool CB = false, class Args>
 GM_D double bias_at(const Args &A, int z, double theta, double ne, int n_sc, double eps)
 {
+    if constexpr (CB) return fmin(fmax(A.bias_value, 1.0), A.bias_max);
     double b;
     if (A.bias_mode == 0) b = A.bias_value;
     else if (A.bias_mode == 1) b = A.bias_value * theta * theta;
@@ -419,10 +422,10 @@ GM_D double bias_at(const Args &A, int z, double theta, double ne, int n_sc, dou
 // Bias of a step from the value carried by the photon or evaluated at the
 // step's end: the value itself, or in the weight-window mode the weight at
 // the step's start times the importance factor, clamped to [1, bias_max].
-template <class Args>
+template <bool CB = false, class Args>
 GM_D double step_bias(const Args &A, double w, double bf)
 {
-    if (A.bias_mode != 4) return bf;
+    if (CB || A.bias_mode != 4) return bf;
     return fmin(fmax(w * bf, 1.0), A.bias_max);
 }
 
@@ -431,7 +434,7 @@ GM_D double step_bias(const Args &A, double w, double bf)
 // alpha_sc = n_e sigma_h; and the bias at that point.  gm gives inner
 // products with the metric at the point; FLAT zones carry their unit u and
 // field direction already.
-template <bool FLAT, class Args, class G>
+template <bool FLAT, bool CB = false, class Args, class G>
 GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, const double *k, int n_sc)
 {
     Coef c{0.0, 0.0, 1.0, true};
@@ -498,13 +501,13 @@ GM_D Coef coefficients_at64(const Args &A, const Elec &el, int z, const G &gm, c
     } else if (A.scattering) {
         c.nus = nuf * ne * kSigT * sigma_pl(el, ef);
     }
-    c.b = bias_at(A, z, zr[Z_TH], ne, n_sc, ef);
+    c.b = bias_at<CB>(A, z, zr[Z_TH], ne, n_sc, ef);
     return c;
 }
 
 // The same in the FP32 form: frame products in double, then emissivity,
 // absorption and the hot cross section as FP32 logarithms and one exp each.
-template <bool FLAT, class Args, class G>
+template <bool FLAT, bool CB = false, class Args, class G>
 GM_D Coef coefficients_at32(const Args &A, const Elec &el, int z, const G &gm, const double *k, int n_sc)
 {
     (void)el;                      // thermal electrons only (power laws run in FP64)
@@ -551,15 +554,15 @@ GM_D Coef coefficients_at32(const Args &A, const Elec &el, int z, const G &gm, c
     }
     if (A.scattering)
         c.nus = (double)__expf(lnnu + zf[F_LNNESIG] + ln_sigma_hot32(A.sh32, zf[F_LNTH], __logf((float)ef)));
-    c.b = bias_at(A, z, (double)zf[F_TH], (double)nef, n_sc, ef);
+    c.b = bias_at<CB>(A, z, (double)zf[F_TH], (double)nef, n_sc, ef);
     return c;
 }
 
-template <bool FLAT, bool F32 = false, class Args, class G>
+template <bool FLAT, bool F32 = false, bool CB = false, class Args, class G>
 GM_D Coef coefficients_at(const Args &A, const Elec &el, int z, const G &gm, const double *k, int n_sc)
 {
-    if constexpr (F32) return coefficients_at32<FLAT>(A, el, z, gm, k, n_sc);
-    else return coefficients_at64<FLAT>(A, el, z, gm, k, n_sc);
+    if constexpr (F32) return coefficients_at32<FLAT, CB>(A, el, z, gm, k, n_sc);
+    else return coefficients_at64<FLAT, CB>(A, el, z, gm, k, n_sc);
 }
 
 // Flat spacetime (Cartesian Minkowski metric).

@@ -148,8 +148,9 @@ GM_D int plasma_zone(const TArgs &A, int z)
 // Kerr tracker (geodesic section: velocity Verlet with an iterated
 // corrector; Absorption and Scattering sections).  Scheduling as in the
 // flat tracker: lanes idle until enough of the wave is idle, then claim
-// queue entries together and run the finished photons' bookkeeping.
-template <int WAVES, bool F32, bool BATCHED>
+// queue entries together and run the finished photons' bookkeeping.  CB:
+// every instance of the launch has the constant bias.
+template <int WAVES, bool F32, bool BATCHED, bool CB>
 __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 {
     extern __shared__ double lds[];
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
             const bool beyond = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
             const int zn = beyond ? -1 : zone_ks(A, P[0], P[1], P[2]);
             settle(ne_touch);
-            Coef c1 = coefficients_at<false, F32>(A, A.el, zn, GKerr{K}, kn, ph.n_sc);
+            Coef c1 = coefficients_at<false, F32, CB>(A, A.el, zn, GKerr{K}, kn, ph.n_sc);
             ph.ncoef += 1;
             if (mode != MODE_STEP) {
                 // restart at the scattering point, or first evaluation of a
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                 double tau_a = 0.5 * (ph.nua + c1.nua) * A.C * dl;
                 double tau_s = A.scattering ? 0.5 * (ph.nus + c1.nus) * A.C * dl : 0.0;
                 const double bf = c1.vacuum ? ph.b : c1.b;
-                const double b = step_bias(A, ph.w, bf);
+                const double b = step_bias<CB>(A, ph.w, bf);
                 const double e_old = ph.e;
                 if (A.scattering && ph.n_sc < A.n_sc_max && b * tau_s > ph.x1) {
                     // ---- scattering inside the step, at the fraction f: absorb

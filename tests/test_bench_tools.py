@@ -64,7 +64,8 @@ def test_issued_fp64_convention(tmp_path, monkeypatch):
 
 
 def test_variant_names_match_the_compiled_kernels():
-    assert bench.track_variant(2, 1) == "track_kernel_ks<2, false, false>"
+    assert bench.track_variant(2, 1) == "track_kernel_ks<2, false, false, true>"
+    assert bench.track_variant(2, 4, const_bias=False) == "track_kernel_ks<2, false, true, false>"
     assert bench.track_variant(3, 64, kerr=False) == "track_kernel_flat<3, false, true>"
 
 
