@@ -451,6 +451,14 @@ typedef struct {
 gm_status gm_set_event_log(gm_ctx *ctx, void *device_buffer, uint64_t capacity, uint64_t root_stride);
 gm_status gm_event_count(gm_ctx *ctx, uint64_t *n);
 
+/* Least and greatest fluid-frame energy eps (m_e c^2) of the event log's
+ * emission records (generation 0, positive weight), found on the device:
+ * the band the plain roots were born in, over which the importance forms
+ * lay the emission proposal's nodes (the proposal density of the Sampling
+ * procedure section, made adaptive).  GM_ESTATE without an event log or
+ * without such a record.  Synchronises. */
+gm_status gm_event_band(gm_ctx *ctx, double *eps_min, double *eps_max);
+
 /* Tables of an instance built on the device from importance estimates.  A
  * map says which table (bias: nodes in ln eps of the incoming fluid-frame
  * photon energy; emission: nodes in ln nu, Hz, of the emitted photon), its

@@ -189,6 +189,7 @@ struct gm_ctx {
     float *scratch = nullptr;                   // this device's copy of the scratch array
     // cell sums of the event records (adaptive form) and their layout
     DevBuf<double> cell_acc;
+    DevBuf<unsigned long long> band_mm;
     gm_importance_map cell_map{};
     int cell_blocks[3] = {0, 0, 0}, cell_nc[3] = {0, 0, 0};
     int cell_inst = -1;
@@ -366,6 +367,7 @@ gm_status gm_destroy(gm_ctx *c)
     c->inst_args.release(); c->root_off.release(); c->inst_ctr.release();
     c->bak_d.release(); c->bak_u.release(); c->call_bak_d.release(); c->call_bak_u.release();
     c->cell_acc.release();
+    c->band_mm.release();
     c->mlp_p.release(); c->mlp_m.release(); c->mlp_v.release(); c->mlp_g.release();
     c->mlp_gpart.release(); c->mlp_pb.release(); c->evlog_n.release();
     c->gcheb.release(); c->sh_table.release(); c->sh_table32.release(); c->gl_x.release(); c->gl_w.release();
@@ -1432,6 +1434,31 @@ gm_status gm_event_count(gm_ctx *c, uint64_t *n)
     HIPCHK(hipMemcpyAsync(&v, c->evlog_n.p, sizeof(v), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     *n = v;
+    return GM_OK;
+}
+
+gm_status gm_event_band(gm_ctx *c, double *eps_min, double *eps_max)
+{
+    if (!c || !eps_min || !eps_max) return fail(GM_EINVAL, "NULL argument");
+    if (!c->evlog) return fail(GM_ESTATE, "no event log set");
+    gm_status s = set_device(c);
+    if (s != GM_OK) return s;
+    if (c->band_mm.ensure(2) != hipSuccess) return fail(GM_ENOMEM, "band");
+    unsigned long long n_ev = 0, mm[2] = {~0ull, 0ull};
+    HIPCHK(hipMemcpyAsync(c->band_mm.p, mm, sizeof(mm), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(&n_ev, c->evlog_n.p, sizeof(n_ev), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    n_ev = std::min(n_ev, c->evlog_cap);
+    if (n_ev > 0) {
+        const unsigned nb = (unsigned)std::min<unsigned long long>((n_ev + 255) / 256, 2048);
+        event_band_kernel<<<nb, 256, 0, c->stream>>>(c->evlog, n_ev, c->band_mm.p);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(mm, c->band_mm.p, sizeof(mm), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (mm[0] > mm[1]) return fail(GM_ESTATE, "no emission records in the event log");
+    std::memcpy(eps_min, &mm[0], sizeof(double));
+    std::memcpy(eps_max, &mm[1], sizeof(double));
     return GM_OK;
 }
 

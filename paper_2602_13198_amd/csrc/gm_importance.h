@@ -162,6 +162,34 @@ GM_D int node_of(const CellArgs &C, double v)
     return (int)fmin(fmax(rint(p), 0.0), (double)(C.n_nodes - 1));
 }
 
+// Least and greatest eps of the event log's emission records (generation
+// 0, positive weight): the bit patterns of positive doubles order like
+// their values, so each wave reduces them as integers and its first lane
+// merges them with one atomic min and one atomic max.
+__global__ __launch_bounds__(256) void event_band_kernel(const EventRec *ev, unsigned long long n,
+                                                         unsigned long long *mm)
+{
+    unsigned long long lo = ~0ull, hi = 0ull;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        const EventRec &r = ev[i];
+        if (r.gen == 0 && r.w > 0.0 && r.eps > 0.0 && r.eps <= 1.7976931348623157e308) {
+            const unsigned long long u = (unsigned long long)__double_as_longlong(r.eps);
+            lo = min(lo, u);
+            hi = max(hi, u);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, (unsigned long long)__shfl_xor(lo, o));
+        hi = max(hi, (unsigned long long)__shfl_xor(hi, o));
+    }
+    if (lane_id() == 0) {
+        atomicMin(&mm[0], lo);
+        atomicMax(&mm[1], hi);
+    }
+}
+
 __global__ __launch_bounds__(256) void cells_accumulate_kernel(CellArgs C)
 {
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < C.n_ev;

@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
         Q.nua[q] = c.nua; Q.nus[q] = c.nus; Q.b[q] = c.b;
         Q.s0[q] = rng.s0; Q.s1[q] = rng.s1; Q.s2[q] = rng.s2; Q.blk[q] = rng.block;
         Q.n_sc[q] = 0;
-        Q.ev[q] = (A.evlog && p % A.root_stride == 0)
+        Q.ev[q] = (A.evlog && A.root_stride != 0 && p % A.root_stride == 0)
                       ? log_event(A, rng, nullptr, (int)z, 0, eps, w, x + 1, kNoEvent) : kNoEvent;
         lds_add(&B.ledger[L_W_EMIT], w);
         lds_add(&B.ledger[L_E_EMIT], w * e_inf(g, k) * kMeC2);

@@ -54,7 +54,7 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G", "gm_set_timing",
            "gm_read_timing", "gm_set_tuning", "gm_mlp_set_params", "gm_mlp_get_params",
            "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_set_bias_table",
-           "gm_set_event_log", "gm_event_count", "gm_set_batch",
+           "gm_set_event_log", "gm_event_count", "gm_event_band", "gm_set_batch",
            "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
            "gm_queue_stats", "gm_set_emission_table", "gm_set_score_weights", "gm_set_tally_mode",
            "gm_mlp_set_loss", "gm_unload_zones", "gm_mlp_grad_noalloc", "gm_mlp_fill_table",
@@ -144,6 +144,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_mlp_train_step": (i, [vp, vp, vp, vp, C.c_int64, C.c_float, vp]),
         "gm_set_bias_table": (i, [vp, i, dp, i, C.c_double, C.c_double]),
         "gm_set_event_log": (i, [vp, vp, u64, u64]),
+        "gm_event_band": (i, [vp, dp, dp]),
         "gm_set_emission_table": (i, [vp, i, dp, i, C.c_double, C.c_double]),
         "gm_set_score_weights": (i, [vp, i, dp, i]),
         "gm_set_tally_mode": (i, [vp, i]),
@@ -390,8 +391,14 @@ class Context:
         _check(load_library().gm_event_count(self._h, C.byref(n)))
         cap = self._evlog.numel() // EVENT_BYTES
         m = min(int(n.value), cap)
-        raw = self._evlog[: m * EVENT_BYTES].cpu().numpy()
-        return raw.view(EVENT_DTYPE).copy()
+        raw = self._evlog[: m * EVENT_BYTES].cpu().numpy()       # a fresh host copy
+        return raw.view(EVENT_DTYPE)
+
+    def event_band(self):
+        """(eps_min, eps_max) of the event log's emission records, m_e c^2."""
+        lo, hi = C.c_double(0.0), C.c_double(0.0)
+        _check(load_library().gm_event_band(self._h, C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
 
     # ---- learned form: the network ----
     def mlp_set_params(self, params):

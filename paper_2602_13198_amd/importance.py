@@ -79,8 +79,9 @@ _FEATURES = {}
 
 
 def zone_features(wl):
-    """[nz][5]: ln Theta_e, ln n_e, ln(B + 1e-10), radius feature, cos theta
-    (kept for the workload object once computed)."""
+    """[nz][8]: ln Theta_e, ln n_e, ln(B + 1e-10), 0 (the photon energy's
+    slot), radius feature, cos theta, 0, 0 -- the zone's part of a feature
+    row (kept for the workload object once computed)."""
     key = id(wl)
     hit = _FEATURES.get(key)
     if hit is not None and hit[0] is wl:
@@ -94,14 +95,18 @@ def zone_features(wl):
 def _zone_features(wl):
     _, rad, cth = zone_geometry(wl)
     tiny = 1e-300
-    return np.stack([np.log(np.maximum(wl.theta_e, 1e-3)), np.log(np.maximum(wl.n_e, tiny)),
-                     np.log(wl.B + 1e-10), rad, cth], axis=1)
+    zf = np.zeros((len(rad), 8))
+    zf[:, 0] = np.log(np.maximum(wl.theta_e, 1e-3))
+    zf[:, 1] = np.log(np.maximum(wl.n_e, tiny))
+    zf[:, 2] = np.log(wl.B + 1e-10)
+    zf[:, 4], zf[:, 5] = rad, cth
+    return zf
 
 
 def rows(zf, zone, ln_e):
-    """Feature rows [n][8] (6 used) for zones and log photon energies."""
-    X = np.zeros((len(zone), 8))
-    X[:, [0, 1, 2, 4, 5]] = zf[zone]
+    """Feature rows [n][8] (6 used) for zones and log photon energies: one
+    gather of the zones' rows, then the energy slot."""
+    X = zf[zone]
     X[:, 3] = ln_e
     return X
 
@@ -135,12 +140,18 @@ def pilot(ctx, wl, inst, rounds, seed0, n_s, root_stride=4, track=None):
     return sw
 
 
-def split_records(ev, root_stride):
-    """(scatter records, emission records) with positive weight; emission
-    records stand for root_stride roots each."""
-    ok = (ev["w"] > 0) & np.isfinite(ev["w"]) & np.isfinite(ev["score"])
-    ev = ev[ok]
-    return ev[ev["gen"] > 0], ev[ev["gen"] == 0]
+def event_columns(ev):
+    """The event log's fields the tables use, as contiguous columns."""
+    return {k: np.ascontiguousarray(ev[k]) for k in ("zone", "gen", "eps", "w", "score")}
+
+
+def split_records(ev):
+    """(scatter records, emission records) with positive weight, as column
+    dicts (zone, eps, w, score); an emission record stands for the pilot's
+    root stride of roots."""
+    gen, w, score = ev["gen"], ev["w"], ev["score"]
+    ok = (w > 0) & np.isfinite(w) & np.isfinite(score)
+    return tuple({k: ev[k][m] for k in ("zone", "eps", "w", "score")} for m in (ok & (gen > 0), ok & (gen == 0)))
 
 
 # ---------------------------------------------------------------------------
@@ -163,16 +174,20 @@ class Network:
         return np.concatenate(parts).astype(np.float32)
 
     def standardise(self, X):
-        Z = np.zeros_like(X, dtype=np.float32)
-        Z[:, :6] = (X[:, :6] - self.mu) / self.sd
+        Z = np.zeros((len(X), 8), dtype=np.float32)
+        Z[:, :6] = (X[:, :6] - self.mu) * (1.0 / self.sd)
         return Z
 
     def fit(self, ctx, X, T, C, steps=800, batch=16384, lr=2e-3):
         """X rows, T [n][2] targets (>= 0, normalised to mean 1 per output),
         C [n][2] weights (0 where a row does not train an output)."""
         import torch
-        self.mu = X[:, :6].mean(0)
-        self.sd = X[:, :6].std(0) + 1e-6
+        # feature means and standard deviations from the first two moments
+        n6 = max(len(X), 1)
+        m1 = X.sum(0)[:6] / n6
+        m2 = np.einsum("ij,ij->j", X, X)[:6] / n6
+        self.mu = m1
+        self.sd = np.sqrt(np.maximum(m2 - m1 * m1, 0.0)) + 1e-6
         Z = self.standardise(X)
         n = len(Z)
         ctx.mlp_set_params(self.initial_params(self.seed))
@@ -186,10 +201,16 @@ class Network:
         gen = torch.Generator(device="cuda")
         gen.manual_seed(self.seed)
         hist = []
+        # batches are consecutive slices of the rows in a fresh random order
+        # per pass over them (one gather per pass, not per step)
+        per_pass = max(n // b, 1)
         for s in range(steps):
             if n > batch:
-                idx = torch.randint(0, n, (batch,), device="cuda", generator=gen)
-                xb, tb, cb = Xd[idx].contiguous(), Td[idx].contiguous(), Cd[idx].contiguous()
+                k = s % per_pass
+                if k == 0:
+                    perm = torch.randperm(n, device="cuda", generator=gen)
+                    Xp, Tp, Cp = Xd[perm], Td[perm], Cd[perm]
+                xb, tb, cb = Xp[k * b:(k + 1) * b], Tp[k * b:(k + 1) * b], Cp[k * b:(k + 1) * b]
             else:
                 xb, tb, cb = Xd, Td, Cd
             want = (s % 100 == 0) or s == steps - 1
@@ -230,16 +251,21 @@ def heldout_deviance(net, ctx, X, T, C, hold):
 
 def emission_band(ev, nodes, pad=0.5):
     """ln nu range of the emission records (the band the plain roots are
-    born in), padded by `pad` node spacings on each side."""
-    em = ev[(ev["gen"] == 0) & (ev["w"] > 0)]
-    ln_nu = np.log(em["eps"] * MEC2_OVER_H)
-    lo, hi = float(ln_nu.min()), float(ln_nu.max())
+    born in), padded by `pad` node spacings on each side; ev is the records
+    (host columns) or the (eps_min, eps_max) pair the library finds on the
+    device."""
+    if isinstance(ev, tuple):
+        lo, hi = (math.log(e * MEC2_OVER_H) for e in ev)
+    else:
+        m = (ev["gen"] == 0) & (ev["w"] > 0)
+        ln_nu = np.log(ev["eps"][m] * MEC2_OVER_H)
+        lo, hi = float(ln_nu.min()), float(ln_nu.max())
     d = (hi - lo) / max(nodes - 1, 1)
     return lo - pad * d, hi + pad * d
 
 
 def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=True, use_emission=True,
-                 alpha=0.5, nodes=16, em_nodes=32, root_stride=4, train_steps=300):
+                 alpha=0.5, nodes=16, em_nodes=32, train_steps=150, train_batch=32768):
     """Tables of the adaptive ("cells") or learned ("network") form from the
     records in the context's event log, built on the device; sets the
     instance's weight-window bias table and defensive emission table.
@@ -265,9 +291,11 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
     e = wl.emit
     emit_round = dict(e, n_target=float(n_s))
     nb0 = ctx.expected_roots(emit_round, inst)
-    ev = ctx.read_event_log()
+    # the cells need the records on the device only; the network trains on
+    # host rows
+    ev = event_columns(ctx.read_event_log()) if mode != "cells" else None
     info["read_s"] = time.perf_counter() - t0
-    lo_nu, hi_nu = emission_band(ev, em_nodes)
+    lo_nu, hi_nu = emission_band(ctx.event_band(), em_nodes)
     info["emission_band_hz"] = [math.exp(lo_nu), math.exp(hi_nu)]
     m_bias = GM.Context.importance_map(GM.TABLE_BIAS, nodes, LN_EPS[0], LN_EPS[1], GM.IMP_LINEAR)
     m_em = GM.Context.importance_map(GM.TABLE_EMISSION, em_nodes, lo_nu, hi_nu, GM.IMP_LINEAR, per_photon=1)
@@ -282,7 +310,8 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
         fill = lambda m: ctx.cells_fill_table(inst, m)       # noqa: E731
         info["records"] = [int(tot_sc[2]), int(tot_em[2])]
     else:
-        sc, em = split_records(ev, root_stride)
+        sc, em = split_records(ev)
+        n_sc, n_em = len(sc["zone"]), len(em["zone"])
         del ev
         zf = zone_features(wl)
         X = np.concatenate([rows(zf, sc["zone"], np.log(sc["eps"])), rows(zf, em["zone"], np.log(em["eps"]))])
@@ -290,21 +319,24 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
         m_sc, m_em_mean = max(t_sc.mean(), 1e-300), max(t_em.mean(), 1e-300)
         T = np.zeros((len(X), 2))
         Cw = np.zeros((len(X), 2))
-        T[:len(sc), 0], Cw[:len(sc), 0] = t_sc / m_sc, 1.0
-        T[len(sc):, 1], Cw[len(sc):, 1] = t_em / m_em_mean, 1.0
+        T[:n_sc, 0], Cw[:n_sc, 0] = t_sc / m_sc, 1.0
+        T[n_sc:, 1], Cw[n_sc:, 1] = t_em / m_em_mean, 1.0
         net = Network(seed=net_seed)
         t1 = time.perf_counter()
+        info["features_s"] = t1 - t0 - info["read_s"]
         # every tenth row held out: a table is built only from an output that
         # predicts those rows better than the constant mean does
         hold = (np.arange(len(X)) % 10) == 0
         Ct = Cw.copy()
         Ct[hold] = 0.0
-        hist = net.fit(ctx, X, T, Ct, steps=train_steps)
+        hist = net.fit(ctx, X, T, Ct, steps=train_steps, batch=train_batch)
         info["train_s"] = time.perf_counter() - t1
         info["loss_first_last"] = [hist[0][1], hist[-1][1]]
-        info["records"] = [int(len(sc)), int(len(em))]
+        info["records"] = [n_sc, n_em]
+        t2 = time.perf_counter()
         dev = heldout_deviance(net, ctx, X, T, Cw, hold)
         info["heldout_deviance"] = dev
+        info["heldout_s"] = time.perf_counter() - t2
         if use_bias and not dev[0][0] < dev[0][1]:
             use_bias = False
             info["fallback"] = info.get("fallback", []) + ["bias"]
@@ -313,10 +345,11 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
             info["fallback"] = info.get("fallback", []) + ["emission"]
         if use_bias:
             # ln I = y + ln(mean t); c_b = records / summed score
-            m_bias.b = math.log(m_sc) + math.log(len(sc) / max(sc["score"].sum(), 1e-300))
+            m_bias.b = math.log(m_sc) + math.log(n_sc / max(sc["score"].sum(), 1e-300))
             ctx.mlp_fill_table(inst, m_bias, 0, net.mu, net.sd)
         b_I = math.log(m_em_mean)                            # ln S = y + ln(mean t)
         fill = lambda m: ctx.mlp_fill_table(inst, m, 1, net.mu, net.sd)   # noqa: E731
+    t3 = time.perf_counter()
     if use_emission:
         # the table ln S once, then mapped in place: the plain roots' mean of
         # S is the expected roots of the table ln S over the plain ones
@@ -331,6 +364,7 @@ def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=
         info["emission_shift"] = m_em.shift
     info["bias_table"], info["emission_table"] = bool(use_bias), bool(use_emission)
     info["tables_s"] = time.perf_counter() - t0
+    info["emission_table_s"] = info["tables_s"] - (t3 - t0)
     return info
 
 
@@ -389,7 +423,7 @@ def compare_forms(ctx, wl, inst, seeds=3, ref_rounds=24, round_div=32, pilot_rou
             try:
                 pilot(ctx, wl, inst, pilot_rounds, 300000 + 1000 * k, n_round, root_stride)
                 info = build_tables(ctx, wl, inst, b_plain, b_max, n_round, form, net_seed=1 + k,
-                                    use_bias=use_bias, use_emission=use_em, alpha=alpha, root_stride=root_stride)
+                                    use_bias=use_bias, use_emission=use_em, alpha=alpha)
                 ctx.set_event_log(0)
                 torch.cuda.synchronize()
                 t_prep = time.perf_counter() - ta

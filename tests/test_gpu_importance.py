@@ -74,6 +74,32 @@ def test_network_table(gm, table):
     assert np.all(tab[wl.n_e <= 0] == 0.0)
 
 
+def test_event_band_equals_the_records(gm):
+    """The device's least and greatest eps of the emission records equal
+    numpy's over the same records read back (exact: a min and a max), also
+    after a second round appends records; without a log, or without an
+    emission record, the call fails with GM_ESTATE."""
+    wl = _wl()
+    c = gm.Context(0)
+    c.load_zones(wl)
+    with pytest.raises(gm.GmError, match="error -4"):
+        c.event_band()
+    c.set_event_log(2_000_000, 0)                     # scattering records only
+    c.make_superphotons(wl.emit)
+    c.track_scatter(wl.track)
+    with pytest.raises(gm.GmError, match="error -4"):
+        c.event_band()
+    c.set_event_log(2_000_000, 3)
+    for seed in (5, 6):
+        c.make_superphotons(dict(wl.emit, seed=seed))
+        c.track_scatter(wl.track)
+        ev = c.read_event_log()
+        em = ev[(ev["gen"] == 0) & (ev["w"] > 0)]
+        assert len(em) > 100 and (ev["gen"] > 0).any()
+        assert c.event_band() == (em["eps"].min(), em["eps"].max())
+    c.close()
+
+
 def test_cell_tables_and_expected_roots(gm):
     """Cell sums and ratios (per unit weight and per photon) against numpy
     on the same records, the in-place remap of a table; the expected roots
