@@ -889,6 +889,11 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, track_fn, 256, lds_track));
     occ = std::max(occ, 1);
     const int grid = c->n_cu * occ;
+    // the rejection trials: one resident wave set, each lane running through
+    // its share of the chunk's roots
+    int occ_s = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_s, birth_sample_kernel, 256, lds_small));
+    const unsigned long long grid_s_max = (unsigned long long)c->n_cu * std::max(occ_s, 1);
 
     std::vector<TArgs> args(n_inst);
     std::vector<unsigned long long> off(n_inst + 1, 0);
@@ -972,6 +977,9 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
         L.root_count = cnt;
         L.dst = queue(c, 0);
         L.src_count = c->ctr.p;                       // generation-0 count
+        birth_sample_kernel<<<(unsigned)std::min<unsigned long long>((cnt + 255) / 256, grid_s_max), 256, lds_small,
+                              c->stream>>>(L);
+        HIPCHK(hipGetLastError());
         birth_fn<<<(unsigned)((cnt + 255) / 256), 256, lds_small, c->stream>>>(L);
         HIPCHK(hipGetLastError());
         for (int g = 0; g < ngen; ++g) {

@@ -579,6 +579,99 @@ GM_D Coef coefficients(const Args &A, const Elec &el, int z, const double *x, co
 // the zone, frequency by rejection against the zone's bound on dN/d ln nu,
 // direction by rejection against j(pi/2), fluid-frame tetrad, weight w(nu),
 // remaining optical depth, opacities at the birth point.
+//
+// In two kernels.  birth_sample_kernel runs the two rejection loops with
+// each lane taking its own roots' trials one after another (lane i of a
+// grid of T lanes takes roots i, i + T, i + 2T, ... of the chunk), so a
+// wave waits for its slowest lane's total over many roots, not for the
+// slowest lane at every root (the trials per root have a long geometric
+// tail).  It leaves nu, ln w, cos theta and the stream's block counter
+// after the last trial in the root's generation-0 queue slots (x1, w, k^0,
+// blk), which birth_kernel reads and then overwrites.  The position's three
+// draws, the stream's first three blocks, are made by birth_kernel, so
+// every root draws exactly the numbers of a single pass.
+__global__ __launch_bounds__(256) void birth_sample_kernel(TArgs L)
+{
+    extern __shared__ double lds[];
+    const int stride = L_N + S_N;
+    lds_zero(lds, L.n_inst, stride);
+    const PhotonQ &Q = L.dst;
+    const unsigned long long T = (unsigned long long)gridDim.x * blockDim.x;
+    unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // the lane's current root: phase 0 set-up, 1 frequency trials, 2 direction trials
+    int phase = 0, ii = 0;
+    const TArgs *Ap = L.insts;
+    uint32_t z = 0, trials = 0, over = 0, dtr = 0;
+    int64_t it = 0;
+    Rng rng{0u, 0u, 0u, 0u};
+    double Az = 0.0, nuc = 0.0, fm = 0.0, nu = 0.0, lnw = 0.0, jmax = 0.0;
+    while (q < L.root_count) {
+        if (phase == 0) {
+            const unsigned long long gq = L.root_begin + q;
+            ii = inst_of_root(L, gq);
+            Ap = L.insts + ii;
+            const unsigned long long p = gq - L.root_off[ii];
+            z = Ap->zone_of_root[p];
+            const double *zr = Ap->zrec + (size_t)z * Z_STRIDE;
+            Az = zr[Z_A];
+            nuc = zr[Z_NUC];
+            fm = Ap->fmax[z];
+            rng = Rng{(uint32_t)p, (uint32_t)(p >> 32), ((uint32_t)Ap->inst << 8) | 1u, 3u};
+            trials = over = dtr = 0;
+            it = 0;
+            phase = 1;
+        }
+        const TArgs &A = *Ap;
+        if (phase == 1) {
+            const double lnnu = A.lnnu_min + rng_uniform(rng, A.key0, A.key1) * A.lnnu_span;
+            nu = exp(lnnu);
+            const double u2 = rng_uniform(rng, A.key0, A.key1);
+            const double dlnw = A.lnnu_span / (A.n_wnodes - 1);
+            const double a = (lnnu - A.lnnu_min) / dlnw;
+            int i = (int)floor(a);
+            i = max(0, min(i, A.n_wnodes - 2));
+            const double f = a - i;
+            lnw = (1.0 - f) * A.ln_w[i] + f * A.ln_w[i + 1];
+            if (A.mtab) lnw -= zone_table(A.mtab, A.mt_n, A.mt_lo, A.mt_hi, (int)z, lnnu);
+            const double F = 4.0 * kPi * Az * shape_G(A.el, A.G, nu / nuc) / exp(lnw);
+            ++trials;
+            over += (F > fm) ? 1u : 0u;
+            if (u2 < F / fm || it >= kMaxTrials) {
+                jmax = Az * shape_g(A.el, nu / nuc);
+                it = 0;
+                phase = 2;
+            } else {
+                ++it;
+            }
+        } else {
+            const double cth = 2.0 * rng_uniform(rng, A.key0, A.key1) - 1.0;
+            const double u4 = rng_uniform(rng, A.key0, A.key1);
+            ++dtr;
+            const double s2 = 1.0 - cth * cth;
+            double j = 0.0;
+            if (s2 > 0.0) {
+                const double s = sqrt(s2);
+                j = Az * s * shape_g(A.el, nu / (nuc * s));
+            }
+            if (u4 < j / jmax || it >= kMaxTrials) {
+                Q.x1[q] = nu;
+                Q.w[q] = lnw;
+                Q.k[0][q] = cth;
+                Q.blk[q] = rng.block;
+                BlockAcc B = lds_acc(lds, stride, ii);
+                lds_inc(&B.stats[S_NU_TRIALS], trials);
+                if (over) lds_inc(&B.stats[S_OVERSHOOT], over);
+                lds_inc(&B.stats[S_DIR_TRIALS], dtr);
+                q += T;
+                phase = 0;
+            } else {
+                ++it;
+            }
+        }
+    }
+    lds_flush_all(L, lds, stride);
+}
+
 // ---------------------------------------------------------------------------
 template <class M, bool F32>
 __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
@@ -604,41 +697,11 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
         x[1] = A.xs[0] + (i1 + rng_uniform(rng, A.key0, A.key1)) * A.dx[0];
         x[2] = A.xs[1] + (i2 + rng_uniform(rng, A.key0, A.key1)) * A.dx[1];
         x[3] = A.xs[2] + (i3 + rng_uniform(rng, A.key0, A.key1)) * A.dx[2];
-        const double Az = zr[Z_A], nuc = zr[Z_NUC];
-        const double fm = A.fmax[z];
-        const double dlnw = A.lnnu_span / (A.n_wnodes - 1);
-        double lnnu, nu, lnw;
-        uint32_t trials = 0, over = 0;
-        for (int64_t it = 0;; ++it) {
-            lnnu = A.lnnu_min + rng_uniform(rng, A.key0, A.key1) * A.lnnu_span;
-            nu = exp(lnnu);
-            double u2 = rng_uniform(rng, A.key0, A.key1);
-            double a = (lnnu - A.lnnu_min) / dlnw;
-            int i = (int)floor(a);
-            i = max(0, min(i, A.n_wnodes - 2));
-            double f = a - i;
-            lnw = (1.0 - f) * A.ln_w[i] + f * A.ln_w[i + 1];
-            if (A.mtab) lnw -= zone_table(A.mtab, A.mt_n, A.mt_lo, A.mt_hi, (int)z, lnnu);
-            double F = 4.0 * kPi * Az * shape_G(A.el, A.G, nu / nuc) / exp(lnw);
-            ++trials;
-            over += (F > fm) ? 1u : 0u;
-            if (u2 < F / fm || it >= kMaxTrials) break;
-        }
-        double jmax = Az * shape_g(A.el, nu / nuc);
-        double cth;
-        uint32_t dtr = 0;
-        for (int64_t it = 0;; ++it) {
-            cth = 2.0 * rng_uniform(rng, A.key0, A.key1) - 1.0;
-            double u4 = rng_uniform(rng, A.key0, A.key1);
-            ++dtr;
-            double s2 = 1.0 - cth * cth;
-            double j = 0.0;
-            if (s2 > 0.0) {
-                double s = sqrt(s2);
-                j = Az * s * shape_g(A.el, nu / (nuc * s));
-            }
-            if (u4 < j / jmax || it >= kMaxTrials) break;
-        }
+        // frequency, its weight and the direction from birth_sample_kernel;
+        // the stream continues after its last trial
+        const PhotonQ &Q = L.dst;
+        const double nu = Q.x1[q], lnw = Q.w[q], cth = Q.k[0][q];
+        rng.block = Q.blk[q];
         double phi = 2.0 * kPi * rng_uniform(rng, A.key0, A.key1);
         double g[4][4], u[4], bh[4], e[4][4];
         if constexpr (M::kCurved) {
@@ -664,7 +727,6 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
         Coef c{0.0, 0.0, 1.0, true};
         if constexpr (!M::kCurved) c = coefficients<M, F32>(A, A.el, zone_cart(A, x[1], x[2], x[3]), x, k, 0);
         // write generation-0 queue entry q
-        const PhotonQ &Q = L.dst;
         Q.inst[q] = ii;
 #pragma unroll
         for (int m = 0; m < 3; ++m) Q.x[m][q] = x[m + 1];
@@ -679,9 +741,6 @@ __global__ __launch_bounds__(256) void birth_kernel(TArgs L)
         lds_add(&B.ledger[L_W_EMIT], w);
         lds_add(&B.ledger[L_E_EMIT], w * e_inf(g, k) * kMeC2);
         lds_inc(&B.stats[S_ROOTS], 1);
-        lds_inc(&B.stats[S_NU_TRIALS], trials);
-        if (over) lds_inc(&B.stats[S_OVERSHOOT], over);
-        lds_inc(&B.stats[S_DIR_TRIALS], dtr);
         lds_inc(&B.stats[S_GEN0], 1);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *L.src_count = L.root_count;
