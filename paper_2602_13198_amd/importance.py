@@ -141,8 +141,13 @@ def pilot(ctx, wl, inst, rounds, seed0, n_s, root_stride=4, track=None):
 
 
 def event_columns(ev):
-    """The event log's fields the tables use, as contiguous columns."""
-    return {k: np.ascontiguousarray(ev[k]) for k in ("zone", "gen", "eps", "w", "score")}
+    """The event log's fields the tables use, as contiguous columns, in the
+    order of the created photons' streams: the log's own order follows the
+    device's scheduling, and the network's batches and held-out rows are
+    taken by position, so sorting makes its training repeatable."""
+    key = (ev["s0"].astype(np.uint64) | (ev["s1"].astype(np.uint64) << np.uint64(32)))
+    order = np.argsort(key)          # 64 bits of a distinct stream per record
+    return {k: np.ascontiguousarray(ev[k][order]) for k in ("zone", "gen", "eps", "w", "score")}
 
 
 def split_records(ev):
@@ -265,7 +270,7 @@ def emission_band(ev, nodes, pad=0.5):
 
 
 def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=True, use_emission=True,
-                 alpha=0.5, nodes=16, em_nodes=32, train_steps=150, train_batch=32768):
+                 alpha=0.5, nodes=16, em_nodes=32, train_steps=600, train_batch=16384):
     """Tables of the adaptive ("cells") or learned ("network") form from the
     records in the context's event log, built on the device; sets the
     instance's weight-window bias table and defensive emission table.

@@ -174,17 +174,20 @@ def test_cell_tables_and_expected_roots(gm):
 
 
 def _masked_rse(c, wl, emit, rounds, seed0, track=None):
-    """Summed spectrum of `rounds` rounds: relative standard errors per bin
-    and the superphotons spent."""
+    """Spectrum summed over `rounds` rounds: relative standard errors per
+    bin, the superphotons spent and the rounds' luminosities [rounds][...]."""
     c.reset_spectrum(0)
     n = 0
+    per = []
     for r in range(rounds):
         c.make_superphotons(dict(emit, seed=seed0 + r))
         st = c.track_scatter(track or wl.track)
         n += int(st[0] + st[1])
-    sp, _ = c.read_spectrum(0, reset=True)
+        per.append(c.read_spectrum(0, reset=True)[0])
+    per = np.array(per)
+    S1, S2 = per[..., 0].sum(0), per[..., 1].sum(0)
     with np.errstate(divide="ignore", invalid="ignore"):
-        return np.sqrt(sp[..., 1]) / sp[..., 0], n
+        return np.sqrt(S2) / S1, n, per[..., 0]
 
 
 @pytest.mark.parametrize("form", ["cells", "network"])
@@ -205,13 +208,18 @@ def test_emission_proposal_lowers_resolved_bin_variance(gm, form):
     info = IM.build_tables(c, wl, 0, 10.0, 100.0, n_round, form, use_bias=False, use_emission=True)
     c.set_event_log(0)
     assert info["emission_table"], info
-    rse_q, n_q = _masked_rse(c, wl, emit, 6, 700)
+    rse_q, n_q, L_q = _masked_rse(c, wl, emit, 6, 700)
     c.set_emission_table(0, None)
-    rse_p, n_p = _masked_rse(c, wl, emit, 6, 800)
+    rse_p, n_p, L_p = _masked_rse(c, wl, emit, 6, 800)
     c.close()
     m = (sw > 0) & np.isfinite(rse_p) & np.isfinite(rse_q)
     ratio = (rse_p[m] ** 2).sum() / (rse_q[m] ** 2).sum()
-    print("%s: %d resolved bins, summed relative variance plain / proposal %.2f, superphotons %.3g / %.3g"
-          % (form, m.sum(), ratio, n_p, n_q))
+    # the proposal moves effort only: both estimate the same spectrum (the
+    # spread of the independent rounds gives each mean's variance)
+    Lq, Lp = L_q[:, m], L_p[:, m]
+    z = np.abs(Lq.mean(0) - Lp.mean(0)) / np.sqrt((Lq.var(0, ddof=1) + Lp.var(0, ddof=1)) / len(Lq))
+    print("%s: %d resolved bins, summed relative variance plain / proposal %.2f, superphotons %.3g / %.3g, "
+          "max |z| %.2f, mean z^2 %.2f" % (form, m.sum(), ratio, n_p, n_q, z.max(), np.mean(z ** 2)))
     assert m.sum() >= 20
     assert ratio >= 1.5 and n_q <= 1.3 * n_p
+    assert z.max() < 5.5 and np.mean(z ** 2) < 1.6
