@@ -400,6 +400,17 @@ gm_status gm_mlp_grad_noalloc(gm_ctx *ctx, const float *X, const float *T, const
 gm_status gm_mlp_train_step(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
                             float lr, float *loss);
 
+/* `steps` Adam steps of gm_mlp_train_step queued in one call, step s on the
+ * rows [k b, (k + 1) b) with k = s mod floor(n / b) (consecutive batches of
+ * the rows as given: shuffle them first), learning rate
+ * lr0 * decay^(s / steps); loss_first_last (host, may be NULL) receives the
+ * loss before the first and before the last step.  The same kernels in the
+ * same order as the single steps, so the parameters equal those of the
+ * equivalent sequence of gm_mlp_train_step calls bit for bit.  GM_EINVAL
+ * for b < 1, b > n or steps < 1.  Synchronises only for loss_first_last. */
+gm_status gm_mlp_train_steps(gm_ctx *ctx, const float *X, const float *T, const float *C, int64_t n,
+                             int64_t b, int steps, float lr0, float decay, float *loss_first_last);
+
 /* ---- tables and records of the learned and adaptive forms -------------
  * Not passages of the paper, which names tuning the bias "on the fly" as
  * future work (Conclusions); they only change where superphotons are

@@ -1834,7 +1834,7 @@ static gm_status mlp_gradient(gm_ctx *c, const float *X, const float *T, const f
     M.gpart = c->mlp_gpart.p; M.loss_scale = 1.0f; M.loss_kind = c->mlp_loss;
     mlp_grad_kernel<<<(unsigned)nb, 64 * kMlpGradWaves, 0, c->stream>>>(M);
     HIPCHK(hipGetLastError());
-    mlp_reduce_kernel<<<(kMlpParams + 1 + 255) / 256, 256, 0, c->stream>>>(c->mlp_gpart.p, (int)nb, c->mlp_g.p);
+    mlp_reduce_kernel<<<kMlpReduceBlocks, 256, 0, c->stream>>>(c->mlp_gpart.p, (int)nb, c->mlp_g.p);
     HIPCHK(hipGetLastError());
     return GM_OK;
 }
@@ -1870,7 +1870,7 @@ gm_status gm_mlp_grad_noalloc(gm_ctx *c, const float *X, const float *T, const f
     // every block writes all of its partial (no clearing needed)
     mlp_grad_kernel<<<(unsigned)nb, 64 * kMlpGradWaves, 0, c->stream>>>(M);
     HIPCHK(hipGetLastError());
-    mlp_reduce_kernel<<<(kMlpParams + 1 + 255) / 256, 256, 0, c->stream>>>(c->scratch, (int)nb, grad_loss);
+    mlp_reduce_kernel<<<kMlpReduceBlocks, 256, 0, c->stream>>>(c->scratch, (int)nb, grad_loss);
     HIPCHK(hipGetLastError());
     return GM_OK;
 }
@@ -1894,6 +1894,26 @@ gm_status gm_mlp_train_step(gm_ctx *c, const float *X, const float *T, const flo
     if (loss) {
         HIPCHK(hipMemcpyAsync(loss, c->mlp_g.p + kMlpParams, sizeof(float), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return GM_OK;
+}
+
+gm_status gm_mlp_train_steps(gm_ctx *c, const float *X, const float *T, const float *C, int64_t n, int64_t b,
+                             int steps, float lr0, float decay, float *loss_first_last)
+{
+    if (!c || !X || !T || !C || n <= 0 || n > (1LL << 31) || b < 1 || b > n || steps < 1 || !(lr0 > 0.0f) ||
+        !(decay > 0.0f))
+        return fail(GM_EINVAL, "bad argument");
+    const int64_t per_pass = n / b;
+    for (int st = 0; st < steps; ++st) {
+        const int64_t k = st % per_pass;
+        // the learning rate of step st, as the single steps' caller forms it
+        const float lr = (float)((double)lr0 * std::pow((double)decay, (double)st / (double)steps));
+        float *loss = nullptr;
+        if (loss_first_last && (st == 0 || st == steps - 1)) loss = loss_first_last + (st == 0 ? 0 : 1);
+        gm_status s = gm_mlp_train_step(c, X + k * b * kMlpXStride, T + k * b * kMlpOut, C + k * b * kMlpOut, b, lr,
+                                        loss);
+        if (s != GM_OK) return s;
     }
     return GM_OK;
 }

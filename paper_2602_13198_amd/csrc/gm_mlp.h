@@ -10,7 +10,7 @@
 // receives exactly one addition per wave (two waves) onto zero, and IEEE
 // addition is commutative, so the block's partial does not depend on the
 // order of the waves' LDS atomics; blocks write their partials, which a
-// second kernel sums in block order, so the gradient is deterministic.  An
+// second kernel sums in a fixed order, so the gradient is deterministic.  An
 // Adam kernel updates the FP32 weights and refreshes their BF16 copies.
 //
 // Operand layouts of the 16x16x16 BF16 MFMA (lane l, element j = 0..3):
@@ -341,14 +341,28 @@ __global__ __launch_bounds__(64 * kMlpGradWaves) void mlp_grad_kernel(MlpArgs M)
     for (int i = threadIdx.x; i < kMlpParams + 1; i += blockDim.x) out[i] = gacc[i];
 }
 
-// Sum the blocks' partial gradients in block order.
+// Sum the blocks' partial gradients.  A block takes 64 consecutive entries
+// (lane = entry); its wave w sums the partials of blocks w, w + 4, w + 8, ...
+// in that order, eight loads in flight, and the four waves' sums are added
+// in wave order -- a fixed association, so the gradient does not depend on
+// scheduling, and 4 x 75 waves share the partials' reads instead of one
+// thread per entry walking all of them.
+constexpr int kMlpReduceEntries = 64;
+constexpr int kMlpReduceBlocks = (kMlpParams + 1 + kMlpReduceEntries - 1) / kMlpReduceEntries;
+
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *gpart, int n_blocks, float *g)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > kMlpParams) return;
+    __shared__ float part[4][kMlpReduceEntries];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = blockIdx.x * kMlpReduceEntries + l;
     float s = 0.0f;
-    for (int b = 0; b < n_blocks; ++b) s += gpart[(size_t)b * (kMlpParams + 1) + i];
-    g[i] = s;
+    if (i <= kMlpParams) {
+#pragma unroll 8
+        for (int b = w; b < n_blocks; b += 4) s += gpart[(size_t)b * (kMlpParams + 1) + i];
+    }
+    part[w][l] = s;
+    __syncthreads();
+    if (w == 0 && i <= kMlpParams) g[i] = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
 }
 
 struct AdamArgs {

@@ -53,7 +53,7 @@ EXPORTS = ["gm_create", "gm_destroy", "gm_last_error", "gm_load_zones", "gm_make
            "gm_track_scatter", "gm_read_spectrum", "gm_read_emission", "gm_set_trace",
            "gm_trace_count", "gm_sigma_hot_table", "gm_eval_G", "gm_set_timing",
            "gm_read_timing", "gm_set_tuning", "gm_mlp_set_params", "gm_mlp_get_params",
-           "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_set_bias_table",
+           "gm_mlp_forward", "gm_mlp_grad", "gm_mlp_train_step", "gm_mlp_train_steps", "gm_set_bias_table",
            "gm_set_event_log", "gm_event_count", "gm_event_band", "gm_set_batch",
            "gm_set_instance_bias", "gm_fma_chain_bound", "gm_set_queue_capacity",
            "gm_queue_stats", "gm_set_emission_table", "gm_set_score_weights", "gm_set_tally_mode",
@@ -142,6 +142,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gm_mlp_forward": (i, [vp, vp, C.c_int64, vp]),
         "gm_mlp_grad": (i, [vp, vp, vp, vp, C.c_int64, vp, vp]),
         "gm_mlp_train_step": (i, [vp, vp, vp, vp, C.c_int64, C.c_float, vp]),
+        "gm_mlp_train_steps": (i, [vp, vp, vp, vp, C.c_int64, C.c_int64, i, C.c_float, C.c_float, vp]),
         "gm_set_bias_table": (i, [vp, i, dp, i, C.c_double, C.c_double]),
         "gm_set_event_log": (i, [vp, vp, u64, u64]),
         "gm_event_band": (i, [vp, dp, dp]),
@@ -457,6 +458,18 @@ class Context:
                                                 C.c_void_p(Cd.data_ptr()), int(Xd.shape[0]), float(lr),
                                                 C.c_void_p(L.ctypes.data) if want_loss else None))
         return float(L[0]) if want_loss else None
+
+    def mlp_train_steps(self, Xd, Td, Cd, batch: int, steps: int, lr0: float, decay: float,
+                        want_loss: bool = False):
+        """`steps` Adam steps in one library call over consecutive batches of
+        the rows as given; returns (loss before the first, before the last
+        step) when asked (synchronises then)."""
+        L = np.zeros(2, np.float32)
+        _check(load_library().gm_mlp_train_steps(self._h, C.c_void_p(Xd.data_ptr()), C.c_void_p(Td.data_ptr()),
+                                                 C.c_void_p(Cd.data_ptr()), int(Xd.shape[0]), int(batch),
+                                                 int(steps), float(lr0), float(decay),
+                                                 C.c_void_p(L.ctypes.data) if want_loss else None))
+        return (float(L[0]), float(L[1])) if want_loss else None
 
     def set_bias_table(self, instance: int, ln_b, ln_eps_lo: float, ln_eps_hi: float):
         t = np.ascontiguousarray(ln_b, dtype=np.float64)

@@ -207,22 +207,24 @@ class Network:
         gen.manual_seed(self.seed)
         hist = []
         # batches are consecutive slices of the rows in a fresh random order
-        # per pass over them (one gather per pass, not per step)
+        # per pass over them; each pass's steps run in one library call, the
+        # learning rate falling as lr 0.1^(s / steps) over the whole fit
         per_pass = max(n // b, 1)
-        for s in range(steps):
+        s = 0
+        while s < steps:
+            k = min(per_pass, steps - s)
             if n > batch:
-                k = s % per_pass
-                if k == 0:
-                    perm = torch.randperm(n, device="cuda", generator=gen)
-                    Xp, Tp, Cp = Xd[perm], Td[perm], Cd[perm]
-                xb, tb, cb = Xp[k * b:(k + 1) * b], Tp[k * b:(k + 1) * b], Cp[k * b:(k + 1) * b]
+                perm = torch.randperm(n, device="cuda", generator=gen)
+                Xp, Tp, Cp = Xd[perm], Td[perm], Cd[perm]
             else:
-                xb, tb, cb = Xd, Td, Cd
-            want = (s % 100 == 0) or s == steps - 1
-            lr_s = lr * (0.1 ** (s / steps))
-            L = ctx.mlp_train_step(xb, tb, cb, lr_s, want_loss=want)
-            if want:
-                hist.append((s, L))
+                Xp, Tp, Cp = Xd, Td, Cd
+            want = s == 0 or s + k == steps
+            L = ctx.mlp_train_steps(Xp, Tp, Cp, b, k, lr * 0.1 ** (s / steps), 0.1 ** (k / steps), want_loss=want)
+            if s == 0:
+                hist.append((0, L[0]))
+            if s + k == steps:
+                hist.append((steps - 1, L[1]))
+            s += k
         ctx.mlp_set_loss(GM.MLP_SQUARED)
         return hist
 
@@ -270,7 +272,7 @@ def emission_band(ev, nodes, pad=0.5):
 
 
 def build_tables(ctx, wl, inst, b_plain, b_max, n_s, mode, net_seed=1, use_bias=True, use_emission=True,
-                 alpha=0.5, nodes=16, em_nodes=32, train_steps=600, train_batch=16384):
+                 alpha=0.5, nodes=16, em_nodes=32, train_steps=1000, train_batch=16384):
     """Tables of the adaptive ("cells") or learned ("network") form from the
     records in the context's event log, built on the device; sets the
     instance's weight-window bias table and defensive emission table.

@@ -121,6 +121,40 @@ def test_training_reduces_loss(ctx):
     assert L1 < 3 * Lo + 1e-3
 
 
+def test_train_steps_equal_single_steps(gm, ctx):
+    """gm_mlp_train_steps: k Adam steps in one call (batches wrapping round
+    the rows) leave the parameters bit for bit where the k single steps over
+    the same batches with the same learning rates leave them, and report the
+    same first and last losses; bad batch sizes or step counts give
+    GM_EINVAL."""
+    import torch
+    n, b, k = 5000, 1024, 7                           # four batches a pass: the steps wrap
+    p0, X, T, C = _case(11, n)
+    T = np.abs(T)                                     # Poisson targets
+    Xd, Td, Cd = (torch.as_tensor(a.astype(np.float32), device="cuda") for a in (X, T, C))
+    ctx.mlp_set_loss(gm.MLP_POISSON)
+    ctx.mlp_set_params(p0.astype(np.float32))
+    L = ctx.mlp_train_steps(Xd, Td, Cd, b, k, 2e-3, 0.1, want_loss=True)
+    pa = ctx.mlp_get_params()
+    ctx.mlp_set_params(p0.astype(np.float32))         # also resets the Adam state
+    lr0, dec = float(np.float32(2e-3)), float(np.float32(0.1))
+    losses = []
+    for s in range(k):
+        j = s % (n // b)
+        lr = float(np.float32(lr0 * dec ** (s / k)))
+        ls = ctx.mlp_train_step(Xd[j * b:(j + 1) * b], Td[j * b:(j + 1) * b], Cd[j * b:(j + 1) * b], lr,
+                                want_loss=s in (0, k - 1))
+        if s in (0, k - 1):
+            losses.append(ls)
+    pb = ctx.mlp_get_params()
+    ctx.mlp_set_loss(gm.MLP_SQUARED)
+    assert np.array_equal(pa, pb) and not np.array_equal(pa, p0.astype(np.float32))
+    assert L == tuple(losses)
+    for bad in (dict(batch=0, steps=3), dict(batch=n + 1, steps=3), dict(batch=b, steps=0)):
+        with pytest.raises(gm.GmError, match="error -1"):
+            ctx.mlp_train_steps(Xd, Td, Cd, bad["batch"], bad["steps"], 2e-3, 0.1)
+
+
 def test_learned_form_keeps_the_spectrum(gm, ctx):
     """Scattering sphere tau_T = 0.1: the learned form -- the network trained
     with the Poisson deviance on one pilot round's records, then the
