@@ -57,3 +57,31 @@ def test_emission_band_covers_the_records():
     d = (math.log(2e10) - math.log(1e9)) / 10
     assert math.isclose(lo, math.log(1e9) - 0.5 * d, rel_tol=1e-12)
     assert math.isclose(hi, math.log(2e10) + 0.5 * d, rel_tol=1e-12)
+
+
+def test_event_columns_do_not_depend_on_the_log_order():
+    """The device writes the event log in scheduling order; the columns the
+    network trains on come out the same for any order of the same records
+    (sorted by the created photons' streams), and the split keeps every
+    record with a positive finite weight and score, scatterings apart from
+    emissions."""
+    from paper_2602_13198_amd import gm as GM
+    rng = np.random.default_rng(4)
+    n = 5000
+    ev = np.zeros(n, GM.EVENT_DTYPE)
+    ev["s0"] = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    ev["s1"] = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    ev["zone"] = rng.integers(0, 1000, n)
+    ev["gen"] = rng.integers(0, 3, n)
+    ev["eps"] = rng.uniform(1e-9, 1e-3, n)
+    ev["w"] = np.where(rng.random(n) < 0.05, 0.0, rng.random(n))
+    ev["score"] = rng.random(n)
+    a = IM.event_columns(ev)
+    b = IM.event_columns(ev[rng.permutation(n)])
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+    sc, em = IM.split_records(a)
+    ok = ev["w"] > 0
+    assert len(sc["zone"]) == (ok & (ev["gen"] > 0)).sum()
+    assert len(em["zone"]) == (ok & (ev["gen"] == 0)).sum()
+    assert np.all(sc["w"] > 0) and np.all(em["w"] > 0)
