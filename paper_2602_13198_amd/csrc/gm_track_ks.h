@@ -224,18 +224,18 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 #pragma unroll
                 for (int m = 0; m < 3; ++m) P[m] = ph.x[m];
             }
-            // touch the zone record of the point now (the record is one cache
-            // line), so that the line arrives while the metric and the
-            // corrector are computed; the pole reflection below can move the
-            // point to a neighbouring zone, whose record then comes later
+            // the zone of the point (-1 beyond the outermost plasma zone: no
+            // zone lookup and no record load, most steps on the way out), and
+            // a touch of its record now (the record is one cache line), so
+            // that the line arrives while the metric and the corrector are
+            // computed; the pole reflection below moves the point to another
+            // zone, whose record then comes later
+            const bool beyond = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
+            int zn = beyond ? -1 : zone_ks(A, P[0], P[1], P[2]);
             double ne_touch = 0.0;
-            {
-                const bool far_out = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
-                const int zt = far_out ? -1 : zone_ks(A, P[0], P[1], P[2]);
-                if (zt >= 0) {
-                    if constexpr (F32) ne_touch = (double)A.zrec32[(size_t)zt * F_STRIDE + F_NE];
-                    else ne_touch = A.zrec[(size_t)zt * Z_STRIDE + Z_NE];
-                }
+            if (zn >= 0) {
+                if constexpr (F32) ne_touch = (double)A.zrec32[(size_t)zn * F_STRIDE + F_NE];
+                else ne_touch = A.zrec[(size_t)zn * Z_STRIDE + Z_NE];
             }
             KMetric K;
             kerr_metric<true>(A.a_spin, A.mass, A.h_slope, P[0], P[1], K);
@@ -272,6 +272,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                     kn[2] = -kn[2];
                     an[2] = -an[2];
                     a_fresh[2] = -a_fresh[2];
+                    if (!beyond) zn = zone_ks(A, P[0], P[1], P[2]);
                 }
             } else {
 #pragma unroll
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
                 const double b_sc = ph.nus;
                 ph.acc_edrift += ph.w * (e_here - ph.e);
                 wchild = ph.w / b_sc;
-                zs = plasma_zone(A, zone_ks(A, P[0], P[1], P[2]));
+                zs = plasma_zone(A, zn);      // beyond: no plasma either way
                 if (zs < 0) zs = plasma_zone(A, zone_ks(A, ph.x[0], ph.x[1], ph.x[2]));
                 if (zs < 0) zs = plasma_zone(A, ph.zone_end);
                 ev_rng = ph.rng;              // the parent's stream at the event
@@ -301,10 +302,6 @@ __global__ __launch_bounds__(256, WAVES) void track_kernel_ks(TArgs L)
 #pragma unroll
                 for (int m = 0; m < 4; ++m) ph.k[m] = kn[m];
             }
-            // beyond the outermost plasma zone the point is vacuum: no zone
-            // lookup and no record load (most steps on the way out)
-            const bool beyond = floor((P[0] - A.xs[0]) * A.inv_dx[0]) > A.i1_plasma_max;
-            const int zn = beyond ? -1 : zone_ks(A, P[0], P[1], P[2]);
             settle(ne_touch);
             Coef c1 = coefficients_at<false, F32, CB>(A, A.el, zn, GKerr{K}, kn, ph.n_sc);
             ph.ncoef += 1;
