@@ -110,6 +110,28 @@ WORKLOAD_TEXT = ("Kerr torus under a scattering corona: a=0.9375, 192x96x96 modi
                  "constant bias b=10, 4 generations; N_s=1e8; 200x6 bins; FP64")
 
 
+FLAT_WORKLOAD_TEXT = ("flat scattering synchrotron sphere: R=1e14 cm, 32^3 Cartesian zones, Theta_e=4, "
+                      "B=1 G, tau_T in {1e-3,1e-2,1e-1} (b=1/tau_T), N_s=1e6 each, 128x6 bins, "
+                      "three instances in shared launches, FP64")
+
+# kernels whose profiler summaries are kept: the headline's tracker, and the
+# flat tracker of the secondary flat sphere field (form: its bench field)
+SUMMARY_TARGETS = {
+    "corona_torus": dict(kernel=TRACK_KERNEL, prefix=PROFILE, workload=WORKLOAD_TEXT, form=None),
+    "scattering_sphere": dict(kernel=track_variant(2, 64, kerr=False),
+                              prefix=os.path.join(ROOT, "profiles", "track_kernel_flat_scattering_sphere"),
+                              workload=FLAT_WORKLOAD_TEXT, form="flat_scattering_sphere"),
+}
+
+
+def _target_file(target, suffix):
+    """Summary file of a target: the headline's module-level names, else
+    the target's prefix with the suffix."""
+    if target["form"] is None:
+        return {"_traffic.json": TRAFFIC_JSON, "_fp64_issue.json": ISSUE_JSON, "_kernel_trace.txt": TRACE_TXT}[suffix]
+    return target["prefix"] + suffix
+
+
 def _summary(path):
     try:
         d = json.load(open(path))
@@ -194,16 +216,17 @@ def _trace_rows(d):
     return stats, launches
 
 
-def summarize_traffic(fetch_dir, write_dir, commands, copy_mib):
-    """Writes the HBM traffic summary of the tracking kernel from two
+def summarize_traffic(fetch_dir, write_dir, commands, copy_mib, target=SUMMARY_TARGETS["corona_torus"]):
+    """Writes the HBM traffic summary of a tracking kernel from two
     rocprofv3 --pmc runs of `bench.py --copy-mib N` (FETCH_SIZE, then
     WRITE_SIZE): KiB per launch, each scaled by what the same counter reads
     for the plain device copy of known size in the same run."""
-    out = {"kernel": TRACK_KERNEL, "workload": WORKLOAD_TEXT, "kernel_source_hash": kernel_source_hash()}
+    kernel = target["kernel"]
+    out = {"kernel": kernel, "workload": target["workload"], "kernel_source_hash": kernel_source_hash()}
     factors = {}
     for key, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _counter_rows(d)
-        mine = [float(r["Counter_Value"]) for r in rows if TRACK_KERNEL in r["Kernel_Name"]]
+        mine = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
         copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
         copy_bytes = copy_mib * 2**20
         # the copy reads and writes copy_bytes once each
@@ -216,13 +239,13 @@ def summarize_traffic(fetch_dir, write_dir, commands, copy_mib):
     out["bytes_per_launch"] = 1024.0 * (out["fetch_kib_per_launch_raw"] * factors["fetch"]
                                         + out["write_kib_per_launch_raw"] * factors["write"])
     out["commands"] = commands
-    with open(TRAFFIC_JSON, "w") as fh:
+    with open(_target_file(target, "_traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out, indent=1))
 
 
-def summarize_issue(pmc_dir, commands):
+def summarize_issue(pmc_dir, commands, target=SUMMARY_TARGETS["corona_torus"]):
     """Writes the issued FP64 operations of the tracking kernel from one
     rocprofv3 --pmc run of the FP64 VALU instruction counters: per wave
     instruction 64 lanes for ADD, MUL and transcendental, 128 for FMA (masked
@@ -230,7 +253,7 @@ def summarize_issue(pmc_dir, commands):
     rows = _counter_rows(pmc_dir)
     acc, n = {}, {}
     for r in rows:
-        if TRACK_KERNEL not in r["Kernel_Name"]:
+        if target["kernel"] not in r["Kernel_Name"]:
             continue
         k = r["Counter_Name"]
         acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
@@ -238,31 +261,37 @@ def summarize_issue(pmc_dir, commands):
     per = {k: acc[k] / n[k] for k in acc}
     issued = 64.0 * (per["SQ_INSTS_VALU_ADD_F64"] + per["SQ_INSTS_VALU_MUL_F64"]
                      + per["SQ_INSTS_VALU_TRANS_F64"]) + 128.0 * per["SQ_INSTS_VALU_FMA_F64"]
-    out = {"kernel": TRACK_KERNEL, "workload": WORKLOAD_TEXT, "kernel_source_hash": kernel_source_hash(),
+    out = {"kernel": target["kernel"], "workload": target["workload"], "kernel_source_hash": kernel_source_hash(),
            "launches": max(n.values()), "per_launch": per, "issued_fp64_flop_per_launch": issued,
            "convention": "64 x (ADD_F64 + MUL_F64 + TRANS_F64) + 128 x FMA_F64 per wave instruction",
            "commands": commands}
-    with open(ISSUE_JSON, "w") as fh:
+    with open(_target_file(target, "_fp64_issue.json"), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out, indent=1))
 
 
-def summarize_trace(trace_dir, bench_log, command):
+def summarize_trace(trace_dir, bench_log, command, target=SUMMARY_TARGETS["corona_torus"]):
     """Writes the kernel-trace summary: rocprofv3 --stats table, the last
     launches, and the tracker's average launch time as bench.py measured it
     with HIP events in the same run."""
     rows, tr = _trace_rows(trace_dir)
     line = [l for l in open(bench_log) if l.startswith("{")][-1]
     b = json.loads(line)
-    mine = [r for r in rows if TRACK_KERNEL in r["Name"]]
-    lines = ["# rocprofv3 kernel trace: " + WORKLOAD_TEXT,
+    kernel = target["kernel"]
+    mine = [r for r in rows if kernel in r["Name"]]
+    if target["form"] is None:
+        value, avg, nl = b["value"], b["roofline"]["avg_launch_ms"], b["roofline"]["launches"]
+    else:
+        f = b["forms"][target["form"]]
+        value, avg, nl = f["value"], f["tracker_avg_launch_ms"], f["tracker_launches"]
+    lines = ["# rocprofv3 kernel trace: " + target["workload"],
              "# command: " + command,
              "# bench.py in the same run: %s superphotons/s under the profiler; avg %s launch "
              "%.3f ms over %d timed launches (HIP events); rocprofv3 average over all %s launches: %.3f ms"
-             % ("%.4g" % b["value"], TRACK_KERNEL, b["roofline"]["avg_launch_ms"], b["roofline"]["launches"],
+             % ("%.4g" % value, kernel, avg, nl,
                 mine[0]["Calls"] if mine else "0", float(mine[0]["AverageNs"]) * 1e-6 if mine else float("nan")),
-             "# HBM traffic of the same kernel: %s" % os.path.basename(TRAFFIC_JSON), "",
+             "# HBM traffic of the same kernel: %s" % os.path.basename(_target_file(target, "_traffic.json")), "",
              "## kernel_stats.csv (top 16)"]
     lines.append(",".join(rows[0].keys()))
     for r in rows[:16]:
@@ -273,7 +302,7 @@ def summarize_trace(trace_dir, bench_log, command):
         lines.append("%s | %.3f ms | grid %s" % (
             r["Kernel_Name"][:60], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6,
             r.get("Grid_Size_X", r.get("Grid_Size", "?"))))
-    with open(TRACE_TXT, "w") as fh:
+    with open(_target_file(target, "_kernel_trace.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines[:8]))
 
@@ -371,9 +400,7 @@ def flat_sphere_form(ctx, base_inst, steps=5):
         ctx.unload(base_inst + i)
     n = int(tot[0] + tot[1])
     fl = flat_flops(tot)
-    return {"workload": "flat scattering synchrotron sphere: R=1e14 cm, 32^3 Cartesian zones, Theta_e=4, "
-                        "B=1 G, tau_T in {1e-3,1e-2,1e-1} (b=1/tau_T), N_s=1e6 each, 128x6 bins, "
-                        "three instances in shared launches, FP64",
+    return {"workload": FLAT_WORKLOAD_TEXT, "tracker_launches": launches,
             "value": n / dt, "unit": "superphotons/s", "ms_per_step": dt / steps * 1e3,
             "tracker": track_variant(2, 64, kerr=False),
             "tracker_avg_launch_ms": ms / launches if launches else None,
@@ -552,15 +579,18 @@ def main():
     ap.add_argument("--summarize-issue", metavar="PMC_DIR",
                     help="write the tracker's issued FP64 operations from a rocprofv3 --pmc run and exit")
     ap.add_argument("--commands", nargs="*", default=[], help="the profiler command lines, recorded in the summaries")
+    ap.add_argument("--summary-target", default="corona_torus", choices=sorted(SUMMARY_TARGETS),
+                    help="the kernel a --summarize-* call writes the summary of")
     args = ap.parse_args()
+    target = SUMMARY_TARGETS[args.summary_target]
     if args.summarize_traffic:
-        summarize_traffic(*args.summarize_traffic, args.commands, args.copy_mib or 1024)
+        summarize_traffic(*args.summarize_traffic, args.commands, args.copy_mib or 1024, target)
         return
     if args.summarize_issue:
-        summarize_issue(args.summarize_issue, args.commands)
+        summarize_issue(args.summarize_issue, args.commands, target)
         return
     if args.summarize_trace:
-        summarize_trace(*args.summarize_trace, " && ".join(args.commands))
+        summarize_trace(*args.summarize_trace, " && ".join(args.commands), target)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus %d requested): sharding over several "

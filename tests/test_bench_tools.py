@@ -77,3 +77,20 @@ def test_kerr_flop_count_from_counters():
     st[bench.S["ROOTS"]], st[bench.S["CHILDREN"]] = 7, 3
     P = bench.KS_FLOPS_PER
     assert bench.ks_flops(st) == P["point"] * 1010 + P["corrector"] * 2500 + P["split"] * 10 + P["load"] * 10
+
+
+def test_flat_target_summary(tmp_path):
+    """A summary of the flat tracker's counters takes that kernel's rows
+    only and goes to the flat target's own file."""
+    t = dict(bench.SUMMARY_TARGETS["scattering_sphere"], prefix=str(tmp_path / "flat"))
+    kf = "void gm::%s(gm::TArgs)" % t["kernel"]
+    d = str(tmp_path / "pmc")
+    rows = []
+    for k, v in ((kf, 1.0), (kf, 3.0), (KNAME, 100.0)):
+        rows += [(k, "SQ_INSTS_VALU_ADD_F64", v), (k, "SQ_INSTS_VALU_MUL_F64", v),
+                 (k, "SQ_INSTS_VALU_TRANS_F64", v), (k, "SQ_INSTS_VALU_FMA_F64", v), (k, "SQ_INSTS_VALU", v)]
+    write_counters(d, rows)
+    bench.summarize_issue(d, ["cmd"], t)
+    out = json.load(open(str(tmp_path / "flat_fp64_issue.json")))
+    assert out["kernel"] == t["kernel"] and out["launches"] == 2
+    assert out["issued_fp64_flop_per_launch"] == pytest.approx(64 * 3 * 2.0 + 128 * 2.0)
