@@ -26,6 +26,17 @@ def write_counters(d, rows):
 KNAME = "void gm::%s(gm::TArgs)" % bench.TRACK_KERNEL
 
 
+@pytest.fixture(autouse=True)
+def _summaries_to_tmp(tmp_path, monkeypatch):
+    """No test here writes a committed profile summary: every summary path
+    points into the test's own directory."""
+    monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "k_traffic.json"))
+    monkeypatch.setattr(bench, "ISSUE_JSON", str(tmp_path / "k_fp64_issue.json"))
+    monkeypatch.setattr(bench, "TRACE_TXT", str(tmp_path / "k_kernel_trace.txt"))
+    monkeypatch.setattr(bench, "SUMMARY_TARGETS", {k: dict(v, prefix=str(tmp_path / k))
+                                                   for k, v in bench.SUMMARY_TARGETS.items()})
+
+
 def test_traffic_is_scaled_by_the_copy(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "traffic.json"))
     f, w = str(tmp_path / "f"), str(tmp_path / "w")
