@@ -1825,7 +1825,11 @@ gm_status gm_mlp_forward(gm_ctx *c, const float *X, int64_t n, float *Y)
 }
 
 // Gradient (and loss) of the weighted squared loss over n rows into mlp_g.
-static gm_status mlp_gradient(gm_ctx *c, const float *X, const float *T, const float *C, int64_t n)
+// The gradient of the loss over n rows into c->mlp_g (loss in its last
+// entry); with adam, the same launches end in that Adam step of the FP32
+// master and the BF16 copy.
+static gm_status mlp_gradient(gm_ctx *c, const float *X, const float *T, const float *C, int64_t n,
+                              const AdamArgs *adam = nullptr)
 {
     const long long nb = (n + kMlpGradRows - 1) / kMlpGradRows;
     if (c->mlp_gpart.ensure((size_t)nb * (kMlpParams + 1)) != hipSuccess) return fail(GM_ENOMEM, "gradient partials");
@@ -1834,7 +1838,10 @@ static gm_status mlp_gradient(gm_ctx *c, const float *X, const float *T, const f
     M.gpart = c->mlp_gpart.p; M.loss_scale = 1.0f; M.loss_kind = c->mlp_loss;
     mlp_grad_kernel<<<(unsigned)nb, 64 * kMlpGradWaves, 0, c->stream>>>(M);
     HIPCHK(hipGetLastError());
-    mlp_reduce_kernel<<<kMlpReduceBlocks, 256, 0, c->stream>>>(c->mlp_gpart.p, (int)nb, c->mlp_g.p);
+    if (adam)
+        mlp_reduce_adam_kernel<<<kMlpReduceBlocks, 256, 0, c->stream>>>(c->mlp_gpart.p, (int)nb, c->mlp_g.p, *adam);
+    else
+        mlp_reduce_kernel<<<kMlpReduceBlocks, 256, 0, c->stream>>>(c->mlp_gpart.p, (int)nb, c->mlp_g.p);
     HIPCHK(hipGetLastError());
     return GM_OK;
 }
@@ -1881,16 +1888,15 @@ gm_status gm_mlp_train_step(gm_ctx *c, const float *X, const float *T, const flo
     if (!c || !X || !T || !C || n <= 0 || n > (1LL << 31) || !(lr > 0.0f)) return fail(GM_EINVAL, "bad argument");
     if (!c->mlp_ready) return fail(GM_ESTATE, "network parameters not set");
     gm_status s = set_device(c);
-    if (s == GM_OK) s = mlp_gradient(c, X, T, C, n);
     if (s != GM_OK) return s;
-    c->mlp_t += 1;
     AdamArgs A{};
     A.P = c->mlp_p.p; A.m = c->mlp_m.p; A.v = c->mlp_v.p; A.g = c->mlp_g.p; A.Pb = c->mlp_pb.p;
     A.lr = lr; A.beta1 = 0.9f; A.beta2 = 0.999f; A.eps = 1e-8f;
-    A.bc1 = (float)(1.0 - std::pow(0.9, (double)c->mlp_t));
-    A.bc2 = (float)(1.0 - std::pow(0.999, (double)c->mlp_t));
-    mlp_adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, c->stream>>>(A);
-    HIPCHK(hipGetLastError());
+    A.bc1 = (float)(1.0 - std::pow(0.9, (double)(c->mlp_t + 1)));
+    A.bc2 = (float)(1.0 - std::pow(0.999, (double)(c->mlp_t + 1)));
+    s = mlp_gradient(c, X, T, C, n, &A);
+    if (s != GM_OK) return s;
+    c->mlp_t += 1;
     if (loss) {
         HIPCHK(hipMemcpyAsync(loss, c->mlp_g.p + kMlpParams, sizeof(float), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

@@ -10,8 +10,9 @@
 // receives exactly one addition per wave (two waves) onto zero, and IEEE
 // addition is commutative, so the block's partial does not depend on the
 // order of the waves' LDS atomics; blocks write their partials, which a
-// second kernel sums in a fixed order, so the gradient is deterministic.  An
-// Adam kernel updates the FP32 weights and refreshes their BF16 copies.
+// second kernel sums in a fixed order, so the gradient is deterministic; in
+// a training step that kernel then applies the Adam step to the FP32 weights
+// and refreshes their BF16 copies.
 //
 // Operand layouts of the 16x16x16 BF16 MFMA (lane l, element j = 0..3):
 //   A (16 x K16):  row l % 16, k = 4 (l / 16) + j
@@ -341,6 +342,39 @@ __global__ __launch_bounds__(64 * kMlpGradWaves) void mlp_grad_kernel(MlpArgs M)
     for (int i = threadIdx.x; i < kMlpParams + 1; i += blockDim.x) out[i] = gacc[i];
 }
 
+// Refresh the BF16 padded copies of the weights from the FP32 master.
+GM_D void write_bf16_param(short *Pb, int i, float v)
+{
+    if (i >= kW1 && i < kB1) {
+        int k = (i - kW1) / kMlpH, n = (i - kW1) % kMlpH;
+        Pb[kW1b + k * kMlpH + n] = f2bf(v);
+    } else if (i >= kW2 && i < kB2) {
+        Pb[kW2b + (i - kW2)] = f2bf(v);
+    } else if (i >= kW3 && i < kB3) {
+        int k = (i - kW3) / kMlpOut, n = (i - kW3) % kMlpOut;
+        Pb[kW3b + k * 16 + n] = f2bf(v);
+    }
+}
+
+struct AdamArgs {
+    float *P, *m, *v;
+    const float *g;
+    short *Pb;
+    float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
+};
+
+// One parameter's Adam step with gradient g (FP32 master, moments, BF16 copy).
+GM_D void adam_update(const AdamArgs &A, int i, float g)
+{
+    float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
+    float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
+    A.m[i] = m;
+    A.v[i] = v;
+    float p = A.P[i] - A.lr * (m / A.bc1) / (sqrtf(v / A.bc2) + A.eps);
+    A.P[i] = p;
+    write_bf16_param(A.Pb, i, p);
+}
+
 // Sum the blocks' partial gradients.  A block takes 64 consecutive entries
 // (lane = entry); its wave w sums the partials of blocks w, w + 4, w + 8, ...
 // in that order, eight loads in flight, and the four waves' sums are added
@@ -365,40 +399,29 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *gpart, int
     if (w == 0 && i <= kMlpParams) g[i] = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
 }
 
-struct AdamArgs {
-    float *P, *m, *v;
-    const float *g;
-    short *Pb;
-    float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
-};
-
-// Refresh the BF16 padded copies of the weights from the FP32 master.
-GM_D void write_bf16_param(short *Pb, int i, float v)
+// The same sum followed, for the block's entries, by their Adam step: the
+// arithmetic of mlp_reduce_kernel and mlp_adam_kernel in the same order,
+// one launch fewer per training step.
+__global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(const float *gpart, int n_blocks, float *g, AdamArgs A)
 {
-    if (i >= kW1 && i < kB1) {
-        int k = (i - kW1) / kMlpH, n = (i - kW1) % kMlpH;
-        Pb[kW1b + k * kMlpH + n] = f2bf(v);
-    } else if (i >= kW2 && i < kB2) {
-        Pb[kW2b + (i - kW2)] = f2bf(v);
-    } else if (i >= kW3 && i < kB3) {
-        int k = (i - kW3) / kMlpOut, n = (i - kW3) % kMlpOut;
-        Pb[kW3b + k * 16 + n] = f2bf(v);
+    __shared__ float part[4][kMlpReduceEntries];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = blockIdx.x * kMlpReduceEntries + l;
+    float s = 0.0f;
+    if (i <= kMlpParams) {
+#pragma unroll 8
+        for (int b = w; b < n_blocks; b += 4) s += gpart[(size_t)b * (kMlpParams + 1) + i];
+    }
+    part[w][l] = s;
+    __syncthreads();
+    if (w == 0 && i <= kMlpParams) {
+        const float gi = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
+        g[i] = gi;
+        if (i < kMlpParams) adam_update(A, i, gi);
     }
 }
 
-__global__ __launch_bounds__(256) void mlp_adam_kernel(AdamArgs A)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kMlpParams) return;
-    float g = A.g[i];
-    float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
-    float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
-    A.m[i] = m;
-    A.v[i] = v;
-    float p = A.P[i] - A.lr * (m / A.bc1) / (sqrtf(v / A.bc2) + A.eps);
-    A.P[i] = p;
-    write_bf16_param(A.Pb, i, p);
-}
+
 
 // Write every BF16 entry (padding as zero) from the FP32 master: one thread
 // per BF16 entry, so no two threads write the same place.
