@@ -85,22 +85,27 @@ def test_emission_counts(oracle_lib):
 
 def test_thin_sphere_matches_analytic_spectrum(oracle_lib):
     """Optically thin sphere (eq:Lnu_analytic_thin_test): every (theta, nu)
-    bin agrees with the analytic expectation within its Monte Carlo error."""
-    wl = W.strictly_thin_sphere(n_target=30000, seed=1)
-    tr = dict(wl.track, n_nu=48, nu_lo=1e8, nu_hi=1e14)
-    res, _ = oracle_lib.run(wl.with_track(**tr))
-    E = thin_expectation(wl, tr)
-    S1, S2, N = res.spectrum[..., 0], res.spectrum[..., 1], res.spectrum[..., 2]
-    use = N >= 30
-    chi2 = ((S1[use] - E[use]) ** 2 / S2[use]).sum()
-    dof = use.sum()
-    assert dof >= 120
-    assert chi2 / dof < 1.3
-    assert S1.sum() == pytest.approx(E.sum(), rel=5 * math.sqrt(S2.sum()) / S1.sum())
+    bin agrees with the analytic expectation within its Monte Carlo error.
+    Four seeds pooled, ~600 bins: chi^2/dof has a spread of sqrt(2/600) =
+    0.06 about 1, so the bound 1.2 is ~3.5 of those."""
+    chi2, dof = 0.0, 0
+    for seed in (1, 2, 3, 4):
+        wl = W.strictly_thin_sphere(n_target=30000, seed=seed)
+        tr = dict(wl.track, n_nu=48, nu_lo=1e8, nu_hi=1e14)
+        res, _ = oracle_lib.run(wl.with_track(**tr))
+        E = thin_expectation(wl, tr)
+        S1, S2, N = res.spectrum[..., 0], res.spectrum[..., 1], res.spectrum[..., 2]
+        use = N >= 30
+        chi2 += ((S1[use] - E[use]) ** 2 / S2[use]).sum()
+        dof += use.sum()
+        assert S1.sum() == pytest.approx(E.sum(), rel=5 * math.sqrt(S2.sum()) / S1.sum())
+    assert dof >= 480
+    assert chi2 / dof < 1.2
 
 
 def test_convergence_rate(oracle_lib):
-    """eq:conv_parameter falls as N_s^-1/2 (thin sphere, theta-summed)."""
+    """eq:conv_parameter falls as N_s^-1/2 (thin sphere, theta-summed),
+    within 0.05 of that slope."""
     # band kept below ~2e13 Hz, above which the weight floor leaves bins
     # with almost no superphotons at any of these N
     tr = dict(W.default_track(), n_nu=20, nu_lo=1e8, nu_hi=1e13, n_theta=1)
@@ -109,7 +114,7 @@ def test_convergence_rate(oracle_lib):
     logs, errs = [], []
     for N in (1000, 4000, 16000, 64000):
         e = []
-        for seed in range(3):
+        for seed in range(6):
             wl = W.strictly_thin_sphere(n_target=N, seed=100 + seed).with_track(**tr)
             res, _ = oracle_lib.run(wl)
             L = res.spectrum[0, :, 0]
@@ -118,7 +123,10 @@ def test_convergence_rate(oracle_lib):
         logs.append(math.log(N))
         errs.append(math.log(np.mean(e)))
     slope = np.polyfit(logs, errs, 1)[0]
-    assert -0.62 < slope < -0.38
+    # six seeds per N: the slope scatters by ~0.015 between seed sets; the
+    # emission's stratified counts per zone (floor or floor + 1) make it a
+    # little steeper than -1/2 at these N (-0.52 over twelve seeds)
+    assert -0.55 < slope < -0.45
 
 
 def test_any_tau_sphere(oracle_lib):
