@@ -399,9 +399,8 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *gpart, int
     if (w == 0 && i <= kMlpParams) g[i] = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
 }
 
-// The same sum followed, for the block's entries, by their Adam step: the
-// arithmetic of mlp_reduce_kernel and mlp_adam_kernel in the same order,
-// one launch fewer per training step.
+// The same sum followed, for the block's entries, by their Adam step
+// (adam_update): one launch per training step for both.
 __global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(const float *gpart, int n_blocks, float *g, AdamArgs A)
 {
     __shared__ float part[4][kMlpReduceEntries];
