@@ -653,6 +653,9 @@ def main():
 
     # the FP32 precision form, same workload and tuning
     el32, tot32, ms32, l32 = timed_steps(ctx, wl, 0, args.steps, 100, precision=1)
+    # the far-field step rule (off in the headline), same workload and seeds
+    wlf = wl.with_far_steps(4.0)
+    elf, totf, msf, lf = timed_steps(ctx, wlf, 0, args.steps, 100)
 
     out = {
         "metric": "superphotons/s",
@@ -708,6 +711,16 @@ def main():
                 "ms_per_step": el32 / args.steps * 1e3,
                 "avg_track_launch_ms": ms32 / l32 if l32 else None,
                 "speedup_vs_f64": (int(tot32[0] + tot32[1]) / el32) / value,
+            },
+            "far_steps": {
+                "what": "outgoing photons beyond the plasma (r > %.1f r_g) step 4x further; FP64, same workload "
+                        "and tuning; the histories' draws, kinds and weights are those of the default rule"
+                        % wlf.track["r_far"],
+                "value": int(totf[0] + totf[1]) / elf, "unit": "superphotons/s",
+                "ms_per_step": elf / args.steps * 1e3,
+                "avg_track_launch_ms": msf / lf if lf else None,
+                "geodesic_steps_per_superphoton": float(totf[S["STEPS"]]) / float(totf[0] + totf[1]),
+                "speedup_vs_default": (int(totf[0] + totf[1]) / elf) / value,
             },
         },
     }

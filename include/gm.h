@@ -154,6 +154,15 @@ typedef struct {
     double  nu_lo, nu_hi;   /* Hz                                                 */
     int     n_theta;        /* tally inclination bins, uniform on [0, pi]         */
     int     precision;      /* GM_PRECISION_*                                     */
+    /* Far-field steps (spherical grids; the paper leaves the step rule open):
+     * an outgoing photon (k^1 > 0) at r > r_far takes its zone-crossing
+     * quotient with step_h * step_far.  0 (or 1): off.  Otherwise step_far
+     * must be >= 1, and r_far at least the outer radius of the outermost
+     * zone holding plasma and 4 M (outside the photon orbits, where an
+     * outgoing photon never turns back), else GM_EINVAL; ignored on the
+     * Cartesian grid. */
+    double  step_far;
+    double  r_far;
 } gm_track_params;
 
 /* Ledger slots read by gm_read_spectrum (photons/s and erg/s at infinity). */

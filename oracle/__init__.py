@@ -89,7 +89,8 @@ class TrackParams(C.Structure):
                 ("verlet_tol", C.c_double), ("verlet_max_it", C.c_int),
                 ("roulette_frac", C.c_double), ("roulette_p", C.c_double),
                 ("horizon_eps", C.c_double), ("max_steps", C.c_int64), ("n_nu", C.c_int),
-                ("nu_lo", C.c_double), ("nu_hi", C.c_double), ("n_theta", C.c_int)]
+                ("nu_lo", C.c_double), ("nu_hi", C.c_double), ("n_theta", C.c_int),
+                ("step_far", C.c_double), ("r_far", C.c_double)]
 
 
 TRACE_DTYPE = np.dtype([("s0", "<u4"), ("s1", "<u4"), ("s2", "<u4"), ("n_sc", "<i4"),
@@ -457,6 +458,8 @@ def track_params(track: dict) -> TrackParams:
     T.bias_max = float(track.get("bias_max", 1e6))
     T.n_sc_max = int(track.get("n_sc_max", 4))
     T.step_h = float(track.get("step_h", 0.25))
+    T.step_far = float(track.get("step_far", 0.0))
+    T.r_far = float(track.get("r_far", 0.0))
     T.verlet_tol = float(track.get("verlet_tol", 1e-3))
     T.verlet_max_it = int(track.get("verlet_max_it", 8))
     T.roulette_frac = float(track.get("roulette_frac", 1e-4))

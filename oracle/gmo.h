@@ -103,6 +103,8 @@ typedef struct {
     int64_t max_steps;
     int    n_nu;  double nu_lo, nu_hi;  /* tally frequency bins, Hz         */
     int    n_theta;                      /* tally inclination bins          */
+    double step_far, r_far; /* outgoing photons beyond r_far: step_h * step_far
+                               (spherical grids; 0 or 1: off)              */
 } gmo_track_params;
 
 /* Termination kinds written into trace records. */

@@ -882,7 +882,13 @@ static void run_photon(const gmo_ctx *c, const gmo_track_params *tp, worker *wk,
             record_end(c, wk, ph, GMO_END_STUCK, -1, -1);
             return;
         }
-        double dl = step_size(G, tp->step_h, ph->x, ph->k);
+        // far-field rule: an outgoing photon beyond r_far (outside the plasma
+        // and the photon orbits, so it never comes back) steps step_far
+        // times further
+        double h = tp->step_h;
+        if (spherical_grid(G) && tp->step_far > 1.0 && ph->k[1] > 0.0 && exp(ph->x[1]) > tp->r_far)
+            h *= tp->step_far;
+        double dl = step_size(G, h, ph->x, ph->k);
         double xn[4], kn[4], an[4];
         wk->stats[GMO_S_VERLET_IT] += verlet(G, tp->verlet_tol, tp->verlet_max_it, ph->x, ph->k, ph->a, dl, xn, kn, an);
         if (ks_metric) pole_reflect(xn, kn, an);
@@ -1090,7 +1096,8 @@ int gmo_track_scatter(gmo_ctx *c, const gmo_track_params *tp, uint64_t root_begi
     if (!c || !c->made) { gmo_set_error("make superphotons first"); return GMO_ESTATE; }
     if (tp->n_nu < 1 || tp->n_theta < 1 || !(tp->nu_hi > tp->nu_lo) || !(tp->nu_lo > 0.0) ||
         !(tp->bias_max >= 1.0) || !(tp->step_h > 0.0) || tp->verlet_max_it < 1 ||
-        tp->n_sc_max < 0 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0)) {
+        tp->n_sc_max < 0 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0) ||
+        !(tp->step_far == 0.0 || tp->step_far >= 1.0)) {
         gmo_set_error("bad track parameters"); return GMO_EINVAL;
     }
     if ((tp->bias_mode == GMO_BIAS_TABLE || tp->bias_mode == GMO_BIAS_WINDOW) && !c->btab) {

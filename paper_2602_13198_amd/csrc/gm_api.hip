@@ -798,6 +798,8 @@ static TArgs fill_args(gm_ctx *c, int ii, const gm_track_params *tp)
     A.bias_value = I.bias_mode >= 0 ? I.bias_value : tp->bias_value;
     A.bias_max = I.bias_mode >= 0 ? I.bias_max : tp->bias_max;
     A.step_h = tp->step_h;
+    A.step_far = tp->step_far > 1.0 ? tp->step_far : 1.0;
+    A.r_far = tp->step_far > 1.0 ? tp->r_far : HUGE_VAL;
     A.roulette_frac = tp->roulette_frac;
     A.roulette_p = tp->roulette_p;
     A.max_steps = tp->max_steps;
@@ -901,6 +903,13 @@ static gm_status track_batch(gm_ctx *c, const std::vector<int> &ids, const gm_tr
         gm_status s = prepare_instance(c, c->inst[ids[k]], tp);
         if (s != GM_OK) return s;
         args[k] = fill_args(c, ids[k], tp);
+        const gm_grid &G = c->inst[ids[k]].grid;
+        if (tp->step_far > 1.0 && G.metric != GM_METRIC_MINKOWSKI_CART) {
+            // outside the plasma and the photon orbits: no turning back
+            const double r_pl = std::exp(G.x_start[0] + (c->inst[ids[k]].max_i1 + 1) * G.dx[0]);
+            if (!(tp->r_far >= r_pl && tp->r_far >= 4.0 * metric_mass(G.metric)))
+                return fail(GM_EINVAL, "r_far %g must be >= the plasma's outer radius %g and 4 M", tp->r_far, r_pl);
+        }
         off[k + 1] = off[k] + c->inst[ids[k]].n_roots;
     }
     if (c->inst_args.ensure(n_inst) != hipSuccess || c->root_off.ensure(n_inst + 1) != hipSuccess ||
@@ -1108,7 +1117,8 @@ gm_status gm_track_scatter(gm_ctx *c, const gm_track_params *tp, int64_t *stats)
     if (tp->n_nu < 1 || tp->n_theta < 1 || !(tp->nu_lo > 0.0) || !(tp->nu_hi > tp->nu_lo) ||
         !(tp->bias_max >= 1.0) || !(tp->step_h > 0.0) || tp->verlet_max_it < 1 || tp->n_sc_max < 0 ||
         tp->n_sc_max > 15 || !(tp->roulette_p > 0.0 && tp->roulette_p <= 1.0) || tp->max_steps < 1 ||
-        tp->bias_mode < 0 || tp->bias_mode > 4 || (tp->bias_mode < 3 && !(tp->bias_value > 0.0)))
+        tp->bias_mode < 0 || tp->bias_mode > 4 || (tp->bias_mode < 3 && !(tp->bias_value > 0.0)) ||
+        !(tp->step_far == 0.0 || (tp->step_far >= 1.0 && std::isfinite(tp->step_far))))
         return fail(GM_EINVAL, "bad track parameters");
     if (tp->precision != GM_PRECISION_F64 && tp->precision != GM_PRECISION_F32_EMISSIVITY)
         return fail(GM_EINVAL, "precision %d", tp->precision);

@@ -103,6 +103,7 @@ struct TArgs {
     // transport parameters
     int scattering, bias_mode, n_sc_max;
     double bias_value, bias_max, step_h, roulette_frac, roulette_p;
+    double step_far, r_far;        // far-field step factor beyond r_far (1, +inf: off)
     long long max_steps;
     double L_unit_cm;
     ShTable sh;

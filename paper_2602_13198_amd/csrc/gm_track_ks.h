@@ -116,7 +116,8 @@ GM_D void finish_ks(const TArgs &A, BlockAcc &B, const PhotonK &ph, int kind)
     write_trace_ks(A, ph, kind, inu, ith);
 }
 
-// Step size: step_h over the largest rate of zone crossing, the azimuth
+// Step size: step_h over the largest rate of zone crossing (times step_far
+// for an outgoing photon beyond r_far), the azimuth
 // scaled like the polar angle at most; moving inward, at most half the
 // coordinate distance to the horizon; at most a tenth of the x2 distance to
 // the nearer pole (k^phi grows like 1/sin^2 theta there, and a longer step
@@ -125,7 +126,7 @@ GM_D double step_ks(const TArgs &A, const PhotonK &ph)
 {
     // the least of the quotients num/den (positive denominators) is chosen by
     // cross-multiplied comparisons, so the step costs one division
-    double num = A.step_h;
+    double num = (ph.k[1] > 0.0 && ph.r > A.r_far) ? A.step_h * A.step_far : A.step_h;
     double den = fmax(fmax(fabs(ph.k[1]) * A.inv_sc[0], fabs(ph.k[2]) * A.inv_sc[1]),
                       fabs(ph.k[3]) * A.inv_sc[2]);
     if (ph.k[1] < 0.0) {

@@ -106,7 +106,7 @@ class GmTrackParams(C.Structure):
                 ("roulette_frac", C.c_double), ("roulette_p", C.c_double),
                 ("horizon_eps", C.c_double), ("max_steps", C.c_int64), ("n_nu", C.c_int),
                 ("nu_lo", C.c_double), ("nu_hi", C.c_double), ("n_theta", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("step_far", C.c_double), ("r_far", C.c_double)]
 
 
 _lib = None
@@ -215,6 +215,8 @@ def track_struct(t: dict) -> GmTrackParams:
     T.bias_max = float(t.get("bias_max", 1e6))
     T.n_sc_max = int(t.get("n_sc_max", 4))
     T.step_h = float(t.get("step_h", 0.25))
+    T.step_far = float(t.get("step_far", 0.0))
+    T.r_far = float(t.get("r_far", 0.0))
     T.verlet_tol = float(t.get("verlet_tol", 1e-3))
     T.verlet_max_it = int(t.get("verlet_max_it", 8))
     T.roulette_frac = float(t.get("roulette_frac", 1e-4))

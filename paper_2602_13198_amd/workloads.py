@@ -67,6 +67,20 @@ class Workload:
     def n_zones(self) -> int:
         return int(np.prod(self.grid["n"]))
 
+    def outer_plasma_radius(self) -> float:
+        """Outer radius of the outermost first-axis zone holding plasma
+        (spherical grids, x1 = ln r); the least r_far the far-field step
+        rule accepts on this grid (with 4 M)."""
+        n1 = self.grid["n"][0]
+        rows = np.flatnonzero(self.n_e.reshape(n1, -1).max(axis=1) > 0.0)
+        i1 = int(rows[-1]) if len(rows) else -1
+        return float(np.exp(self.grid["x_start"][0] + (i1 + 1) * self.grid["dx"][0]))
+
+    def with_far_steps(self, factor: float) -> "Workload":
+        """Outgoing photons beyond the plasma (and 4 M) step `factor` times
+        further."""
+        return self.with_track(step_far=float(factor), r_far=max(self.outer_plasma_radius(), 4.0))
+
     def with_emit(self, **kw) -> "Workload":
         e = dict(self.emit)
         e.update(kw)

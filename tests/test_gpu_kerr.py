@@ -74,7 +74,8 @@ def test_torus_emission_exact(gm, oracle_lib, wl):
     small_torus(n_target=2000, seed=7),
     small_torus(n_target=2000, seed=8, scattering=0),
     small_torus(n_target=600, seed=9, bias_value=3e4, n_sc_max=2),
-], ids=["torus_scat", "torus_noscat", "torus_heavy_bias"])
+    small_torus(n_target=2000, seed=7).with_far_steps(4.0),
+], ids=["torus_scat", "torus_noscat", "torus_heavy_bias", "torus_far_steps"])
 def test_torus_same_seed_histories(gm, oracle_lib, wl):
     g = run_gpu(gm, wl, trace_cap=1_000_000)
     ores, _ = oracle_lib.run(wl, trace_cap=1_000_000)
@@ -167,3 +168,31 @@ def test_heterogeneous_survey_batched_equals_separate(gm):
         assert a[..., 2].sum() > 0
         np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
         np.testing.assert_allclose(la, lb, rtol=1e-12, atol=1e-300)
+
+
+def test_far_steps_keep_the_histories(gm):
+    """Far-field steps on the device: the same photons, generations, end
+    kinds and weights as without them, the frequency bin of >= 99.5 % and
+    the inclination bin of >= 99 % of the escapes, fewer steps; an r_far
+    inside the plasma (or the photon orbits) is refused."""
+    wl = small_torus(n_target=40000, seed=12)
+    a = run_gpu(gm, wl, trace_cap=1_000_000)
+    b = run_gpu(gm, wl.with_far_steps(4.0), trace_cap=1_000_000)
+    ta, tb = (np.sort(r["trace"], order=["s0", "s1", "s2"]) for r in (a, b))
+    assert len(ta) == len(tb) > 10000
+    for f in ("s0", "s1", "s2", "n_sc", "kind"):
+        assert np.array_equal(ta[f], tb[f]), f
+    assert np.array_equal(ta["w_end"], tb["w_end"])
+    esc = ta["kind"] == 1
+    assert np.mean(ta["i_nu"][esc] == tb["i_nu"][esc]) >= 0.995
+    assert np.mean(ta["i_theta"][esc] == tb["i_theta"][esc]) >= 0.99
+    assert b["stats"][2] < 0.6 * a["stats"][2]
+    c = gm.Context(0)
+    c.load_zones(wl)
+    c.make_superphotons(wl.emit)
+    for r_far in (0.5 * wl.outer_plasma_radius(), 3.0):
+        with pytest.raises(gm.GmError, match="error -1"):
+            c.track_scatter(dict(wl.track, step_far=4.0, r_far=r_far))
+    with pytest.raises(gm.GmError, match="error -1"):
+        c.track_scatter(dict(wl.track, step_far=0.5, r_far=1e3))
+    c.close()

@@ -144,3 +144,28 @@ def test_torus_escaping_photons_stay_null(oracle_lib, torus_run):
     assert len(esc) > 50 and (esc["n_sc"] > 0).any()
     worst = max(_null_norm(oracle_lib, wl.grid, r["x"], r["k"])[0] for r in esc)
     assert worst < 1e-2, worst
+
+
+def test_far_steps_change_only_the_flight_out(oracle_lib):
+    """Far-field step rule: an outgoing photon beyond the plasma and the
+    photon orbits meets no more opacity and never turns back, so stepping it
+    four times further leaves every history's draws, generation and end
+    kind as they were, the frequency bin (e_inf = -k_t is conserved along
+    the geodesic) and, but for the integration error at the record radius,
+    the inclination bin; it only removes steps."""
+    wl = W.torus(n1=64, n2=32, step_h=0.125, n_target=3000, seed=4)
+    far = wl.with_far_steps(4.0)
+    assert 4.0 <= far.track["r_far"] < wl.track.get("r_record", 1000.0)
+    a, _ = oracle_lib.run(wl, trace_cap=200000)
+    b, _ = oracle_lib.run(far, trace_cap=200000)
+    ta, tb = (np.sort(r.trace, order=["s0", "s1", "s2"]) for r in (a, b))
+    assert len(ta) == len(tb) > 500
+    for f in ("s0", "s1", "s2", "n_sc", "kind"):
+        assert np.array_equal(ta[f], tb[f]), f
+    assert np.array_equal(ta["w_end"], tb["w_end"])
+    esc = ta["kind"] == 1
+    assert esc.sum() > 100
+    assert np.mean(ta["i_nu"][esc] == tb["i_nu"][esc]) >= 0.995
+    assert np.mean(ta["i_theta"][esc] == tb["i_theta"][esc]) >= 0.99
+    assert tb["n_steps"][esc].sum() < 0.6 * ta["n_steps"][esc].sum()
+    assert np.array_equal(ta["n_steps"][~esc], tb["n_steps"][~esc])
