@@ -102,3 +102,17 @@ def test_survey_instances():
     for a_ in {w.meta["a"] for w in S}:
         v = [w.track["bias_value"] * w.meta["M_unit"] * w.theta_e.max() ** 2 for w in S if w.meta["a"] == a_]
         np.testing.assert_allclose(v, v[0], rtol=1e-9)
+
+
+def test_outer_plasma_radius_bounds_the_plasma():
+    """The far-field rule's least r_far: every zone with plasma lies inside
+    it, and a zone of the next first-axis row outward would not."""
+    wl = W.torus(n1=64, n2=32, step_h=0.125, n_target=1000)
+    r_out = wl.outer_plasma_radius()
+    n1 = wl.grid["n"][0]
+    rows = np.flatnonzero(wl.n_e.reshape(n1, -1).max(axis=1) > 0.0)
+    x0, dx = wl.grid["x_start"][0], wl.grid["dx"][0]
+    assert np.exp(x0 + rows[-1] * dx) < r_out <= np.exp(x0 + (rows[-1] + 1) * dx) * (1 + 1e-12)
+    far = wl.with_far_steps(4.0)
+    assert far.track["step_far"] == 4.0 and far.track["r_far"] == max(r_out, 4.0)
+    assert wl.track.get("step_far", 0.0) == 0.0
