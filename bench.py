@@ -419,27 +419,34 @@ def paper_sphere_form(ctx, inst, steps=2, n_s=1e7):
     ctx.load_zones(wl, inst)
     ctx.set_instance_bias(inst, wl.track)
 
-    def step(seed):
+    def step(seed, track):
         ctx.make_superphotons(dict(wl.emit, seed=seed), instance=inst)
-        st = ctx.track_scatter(wl.track)
+        st = ctx.track_scatter(track)
         ctx.read_spectrum(inst, reset=True)
         return st
-    step(9500)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tot = None
-    for s in range(steps):
-        st = step(9501 + s)
-        tot = st if tot is None else tot + st
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+
+    def timed(track):
+        step(9500, track)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tot = None
+        for s in range(steps):
+            st = step(9501 + s, track)
+            tot = st if tot is None else tot + st
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, tot
+    dt, tot = timed(wl.track)
+    # the far-field step rule (x4 beyond the sphere), same seeds
+    dtf, totf = timed(wl.with_far_steps(4.0).track)
     ctx.unload(inst)
     n = int(tot[0] + tot[1])
     return {"workload": "the paper's optically thin synchrotron sphere on its log-r grid: R=1 cm, Theta_e=100, "
                         "n_e=1e13, B=1 G, 8192x128x1 (t, ln r, theta, phi) zones to 1e4 cm, record at 3000 cm, "
                         "2500 bins of 0.01 in ln nu, N_s=%g, FP64" % n_s,
             "value": n / dt, "unit": "superphotons/s", "ms_per_step": dt / steps * 1e3,
-            "geodesic_steps_per_superphoton": float(tot[2]) / max(n, 1)}
+            "geodesic_steps_per_superphoton": float(tot[2]) / max(n, 1),
+            "far_steps_x4": {"value": int(totf[0] + totf[1]) / dtf, "unit": "superphotons/s",
+                             "geodesic_steps_per_superphoton": float(totf[2]) / max(int(totf[0] + totf[1]), 1)}}
 
 
 def power_law_form(ctx, inst, steps=3, n_s=1e6):
